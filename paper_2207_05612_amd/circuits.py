@@ -1,0 +1,293 @@
+"""Seeded synthetic random-circuit generators.
+
+This module produces *inputs* only: gate matrices, the qubit -> chain-site map
+and the per-layer gate lists.  It holds none of the compression method's
+arithmetic and is shared by the FP64 oracle (``oracle/``) and by the GPU path,
+so both see bit-identical gates for a given seed.
+
+Workloads follow the paper's random-circuit construction (Sec. V.A, "Three
+quantum circuits"): every cycle applies a random one-qubit gate on every qubit,
+drawn from {sqrt(X), sqrt(Y), sqrt(W)}, followed by two-qubit gates on the
+pairs of one coupler pattern, patterns cycling ABCD-CDAB.  The paper's
+Sycamore lattice is replaced by a rectangular grid read in snake order along
+its short side (one qubit per MPS site, Sec. IV.A with r_tau = 1).
+
+Conventions shared with the C ABI:
+  * a gate is ``(q0, q1, U)``; ``q1 = -1`` for one-qubit gates;
+  * one-qubit ``U`` is 2x2 with ``U[out, in]``;
+  * two-qubit ``U`` is 4x4 with row/column index ``2*s_q0 + s_q1``;
+  * inside one layer every one-qubit gate acts before every two-qubit gate,
+    and the two-qubit gates act on disjoint sites.
+
+Draw order of cycle d (``numpy.random.default_rng(seed)``, PCG64):
+  1. ``integers(0, 3, size=n)`` one-qubit choices, qubits in row-major grid
+     order;
+  2. for each pair of pattern ``SEQUENCE[d % 8]``, sorted by chain site, its
+     two-qubit gate: Haar = 32 ``standard_normal`` draws, fSim = theta then phi.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+# ---------------------------------------------------------------- gate set --
+I2 = np.eye(2, dtype=np.complex128)
+PAULI_X = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+PAULI_Y = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+PAULI_W = (PAULI_X + PAULI_Y) / np.sqrt(2.0)
+
+
+def sqrt_pauli(g: np.ndarray) -> np.ndarray:
+    """Square root of a Pauli-like involution G (G @ G = I): (I - iG)/sqrt(2).
+
+    Its square is -iG, i.e. G up to a global phase.
+    """
+    return (I2 - 1j * g) / np.sqrt(2.0)
+
+
+SQRT_X = sqrt_pauli(PAULI_X)
+SQRT_Y = sqrt_pauli(PAULI_Y)
+SQRT_W = sqrt_pauli(PAULI_W)
+ONE_QUBIT_SET = (SQRT_X, SQRT_Y, SQRT_W)
+
+
+def fsim(theta: float, phi: float) -> np.ndarray:
+    """fSim(theta, phi) in the basis |00>,|01>,|10>,|11> (index 2*s0 + s1)."""
+    c, s = np.cos(theta), np.sin(theta)
+    return np.array([[1, 0, 0, 0],
+                     [0, c, -1j * s, 0],
+                     [0, -1j * s, c, 0],
+                     [0, 0, 0, np.exp(-1j * phi)]], dtype=np.complex128)
+
+
+def haar_unitary_from_normals(z: np.ndarray, dim: int = 4) -> np.ndarray:
+    """Haar-distributed U(dim) from 2*dim*dim standard normal draws.
+
+    QR of a complex Ginibre matrix with the phases of diag(R) moved into Q
+    (Mezzadri, Notices AMS 54 (2007) 592).
+    """
+    z = np.asarray(z, dtype=np.float64).reshape(2, dim, dim)
+    g = (z[0] + 1j * z[1]) / np.sqrt(2.0)
+    q, r = np.linalg.qr(g)
+    d = np.diag(r)
+    return q * (d / np.abs(d))[None, :]
+
+
+def zz_phase(gamma: float) -> np.ndarray:
+    """exp(-i gamma Z x Z), diagonal in the computational basis."""
+    z = np.array([1, -1, -1, 1], dtype=np.float64)
+    return np.diag(np.exp(-1j * gamma * z)).astype(np.complex128)
+
+
+def rx(beta2: float) -> np.ndarray:
+    """RX(beta2) = exp(-i beta2/2 X); the QAOA mixer exp(-i beta X) is RX(2 beta)."""
+    c, s = np.cos(beta2 / 2), np.sin(beta2 / 2)
+    return np.array([[c, -1j * s], [-1j * s, c]], dtype=np.complex128)
+
+
+SWAP = np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]],
+                dtype=np.complex128)
+
+# ------------------------------------------------------------ geometry -----
+@dataclasses.dataclass(frozen=True)
+class Grid:
+    """Rectangular grid of ``n`` qubits, ``width`` columns, rows filled in order.
+
+    The last row may be partial.  Qubit (r, c) sits on chain site
+    ``r*width + c`` on even rows and ``r*width + (m_r - 1 - c)`` on odd rows,
+    m_r being the number of qubits in row r (snake order).
+    """
+    n: int
+    width: int
+
+    @property
+    def rows(self) -> int:
+        return -(-self.n // self.width)
+
+    def row_len(self, r: int) -> int:
+        return min(self.width, self.n - r * self.width)
+
+    def coords(self) -> List[Tuple[int, int]]:
+        return [(r, c) for r in range(self.rows) for c in range(self.row_len(r))]
+
+    def site(self, r: int, c: int) -> int:
+        m = self.row_len(r)
+        if not (0 <= c < m):
+            raise ValueError("no qubit at (%d, %d)" % (r, c))
+        return r * self.width + (c if r % 2 == 0 else m - 1 - c)
+
+    def pattern_pairs(self, letter: str) -> List[Tuple[int, int]]:
+        """Chain-site pairs of coupler pattern A/B (along a row) or C/D (between rows).
+
+        A: (r,c)-(r,c+1), r+c even.  B: same, r+c odd.
+        C: (r,c)-(r+1,c), r+c even.  D: same, r+c odd.
+        Pairs are sorted by (site_i, site_j) with site_i < site_j.
+        """
+        parity = 0 if letter in "AC" else 1
+        pairs = []
+        for r, c in self.coords():
+            if (r + c) % 2 != parity:
+                continue
+            if letter in "AB":
+                if c + 1 < self.row_len(r):
+                    pairs.append((self.site(r, c), self.site(r, c + 1)))
+            else:
+                if r + 1 < self.rows and c < self.row_len(r + 1):
+                    pairs.append((self.site(r, c), self.site(r + 1, c)))
+        pairs = [(min(a, b), max(a, b)) for a, b in pairs]
+        return sorted(pairs)
+
+
+def grid_from_shape(rows: int, cols: int) -> Grid:
+    """A full rows x cols grid, read in snake order along its short side."""
+    return Grid(n=rows * cols, width=min(rows, cols))
+
+
+SEQUENCE = "ABCDCDAB"
+
+Gate = Tuple[int, int, np.ndarray]
+
+
+@dataclasses.dataclass
+class Circuit:
+    n: int
+    layers: List[List[Gate]]
+    label: str = ""
+
+    @property
+    def n_2q(self) -> int:
+        return sum(1 for layer in self.layers for g in layer if g[1] >= 0)
+
+    def layer_n_2q(self, d: int) -> int:
+        return sum(1 for g in self.layers[d] if g[1] >= 0)
+
+
+def random_circuit(grid: Grid, depth: int, seed: int, two_qubit: str = "haar",
+                   sequence: str = SEQUENCE) -> Circuit:
+    """Random circuit on ``grid``: per cycle, 1q layer then one coupler pattern.
+
+    ``two_qubit`` is ``"haar"`` (Haar U(4)) or ``"fsim"`` (fSim with
+    theta ~ U(0, pi/2), phi ~ U(0, pi), drawn per gate instance).
+    """
+    rng = np.random.default_rng(seed)
+    coords = grid.coords()
+    layers: List[List[Gate]] = []
+    for d in range(depth):
+        choice = rng.integers(0, 3, size=grid.n)
+        layer: List[Gate] = []
+        one_q = {}
+        for (r, c), ch in zip(coords, choice):
+            one_q[grid.site(r, c)] = ONE_QUBIT_SET[int(ch)]
+        for s in sorted(one_q):
+            layer.append((s, -1, one_q[s]))
+        for (i, j) in grid.pattern_pairs(sequence[d % len(sequence)]):
+            if two_qubit == "haar":
+                u = haar_unitary_from_normals(rng.standard_normal(32))
+            elif two_qubit == "fsim":
+                theta = rng.uniform(0.0, np.pi / 2)
+                phi = rng.uniform(0.0, np.pi)
+                u = fsim(theta, phi)
+            else:
+                raise ValueError(two_qubit)
+            layer.append((i, j, u))
+        layers.append(layer)
+    return Circuit(n=grid.n, layers=layers,
+                   label="grid%dx%d_d%d_%s_s%d" % (grid.rows, grid.width, depth,
+                                                  two_qubit, seed))
+
+
+def random_brickwork(n: int, depth: int, seed: int) -> Circuit:
+    """Nearest-neighbour chain brickwork of Haar gates with random 1q gates.
+
+    Small-n helper (bond growth is slow and regular), used by the tests.
+    """
+    rng = np.random.default_rng(seed)
+    layers = []
+    for d in range(depth):
+        choice = rng.integers(0, 3, size=n)
+        layer: List[Gate] = [(s, -1, ONE_QUBIT_SET[int(choice[s])]) for s in range(n)]
+        for i in range(d % 2, n - 1, 2):
+            layer.append((i, i + 1, haar_unitary_from_normals(rng.standard_normal(32))))
+        layers.append(layer)
+    return Circuit(n=n, layers=layers, label="brick_n%d_d%d_s%d" % (n, depth, seed))
+
+
+# ------------------------------------------------------------ workloads ----
+def plain_fp64_workload(seed: int = 0) -> Circuit:
+    """12 qubits on a 3x4 grid, depth 8, Haar 2q gates (chi = 64 is exact)."""
+    return random_circuit(grid_from_shape(3, 4), 8, seed, "haar")
+
+
+def grid36_workload(seed: int) -> Circuit:
+    """36 qubits on a 6x6 grid, depth 14, Haar 2q gates."""
+    return random_circuit(grid_from_shape(6, 6), 14, seed, "haar")
+
+
+def sycamore_like_54_workload(seed: int = 0, depth: int = 20) -> Circuit:
+    """54 qubits on a 6x9 grid (snake over width 6), fSim(theta, phi) 2q gates."""
+    return random_circuit(grid_from_shape(9, 6), depth, seed, "fsim")
+
+
+def batched_instances(count: int = 64, seed: int = 0):
+    """Ragged instances: n ~ U{20..40}, depth ~ U{8..20}, chi from {32..512}, width ~ U{4,5,6}.
+
+    Returns a list of ``(circuit, chi)``; instance i draws its gates from seed 1000+i.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(20, 41))
+        depth = int(rng.integers(8, 21))
+        chi = int(rng.choice([32, 64, 128, 256, 512]))
+        width = int(rng.integers(4, 7))
+        out.append((random_circuit(Grid(n, width), depth, 1000 + i, "haar"), chi))
+    return out
+
+
+# -------------------------------------------------------------- packing ----
+GATE_DTYPE = np.dtype([("q0", "<i4"), ("q1", "<i4"), ("m", "<f8", (32,))], align=False)
+
+
+def pack_layer(layer: Sequence[Gate]) -> np.ndarray:
+    """Pack a layer into the C ABI gate record array (interleaved complex128)."""
+    arr = np.zeros(len(layer), dtype=GATE_DTYPE)
+    for idx, (q0, q1, u) in enumerate(layer):
+        arr[idx]["q0"] = q0
+        arr[idx]["q1"] = q1
+        flat = np.asarray(u, dtype=np.complex128).reshape(-1)
+        m = np.zeros(32)
+        m[0:2 * flat.size:2] = flat.real
+        m[1:2 * flat.size:2] = flat.imag
+        arr[idx]["m"] = m
+    return arr
+
+
+def save_npz(path: str, circuit: Circuit) -> None:
+    recs = [pack_layer(layer) for layer in circuit.layers]
+    np.savez(path, n=circuit.n, n_layers=len(recs), label=circuit.label,
+             **{"layer%d" % i: r for i, r in enumerate(recs)})
+
+
+def load_npz(path: str) -> Circuit:
+    z = np.load(path, allow_pickle=False)
+    layers = []
+    for i in range(int(z["n_layers"])):
+        rec = z["layer%d" % i]
+        layer = []
+        for g in rec:
+            m = g["m"][0::2] + 1j * g["m"][1::2]
+            q0, q1 = int(g["q0"]), int(g["q1"])
+            u = m[:4].reshape(2, 2) if q1 < 0 else m[:16].reshape(4, 4)
+            layer.append((q0, q1, u))
+        layers.append(layer)
+    return Circuit(n=int(z["n"]), layers=layers, label=str(z["label"]))
+
+
+def bits_to_index(bits: Sequence[int]) -> int:
+    """Statevector index of a bitstring: site 0 is the most significant bit."""
+    x = 0
+    for b in bits:
+        x = (x << 1) | int(b)
+    return x
