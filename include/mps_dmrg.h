@@ -1,0 +1,199 @@
+/*
+ * mps_dmrg.h -- C ABI of the MI355X (gfx950) DMRG compression-step library.
+ *
+ * The library keeps a matrix product state (MPS) of n qubits, one qubit per
+ * tensor, on one GPU and applies circuit layers to it with the compression
+ * step of Ayral et al., "A density-matrix renormalization group algorithm for
+ * simulating quantum circuits with a finite fidelity" (Sec. IV.B): the layer
+ * is written as an MPO, a TEBD-like zip-up gives the initial guess, and
+ * alternating two-site sweeps fit a bond-chi MPS to W|psi>, each local update
+ * being F / sqrt(f) (eq:optimization) split back by a truncated SVD that keeps
+ * the chi largest singular values (Sec. VI.A).  The partial fidelities f_delta
+ * multiply into F~ (eq:Ftilde-sup).
+ *
+ * Conventions
+ *   - Sites are chain positions 0..n-1; the caller applies any qubit -> site
+ *     map.  Statevector index x = sum_k s_k 2^(n-1-k) (site 0 most
+ *     significant), i.e. the tensor index order of the paper's Psi_{i1..iN}.
+ *   - Bond k lies left of site k; bond 0 and bond n have dimension 1.
+ *   - Complex numbers crossing the ABI are interleaved (re, im) doubles.
+ *   - All pointers in this header are HOST pointers unless stated otherwise;
+ *     every call copies what it needs and is synchronous with respect to the
+ *     host: when it returns, output buffers are filled and input buffers may
+ *     be reused.  Device work runs on the HIP stream given to mps_create.
+ *   - A state is not thread-safe.  Distinct states may be used from distinct
+ *     threads on distinct streams.
+ *
+ * Errors
+ *   Every entry point returns an mps_status.  MPS_OK is 0, errors are
+ *   negative; mps_last_error() returns a thread-local message describing the
+ *   last error.  Argument errors (MPS_ERR_ARG) leave the state unchanged.
+ *   Device, allocation or numerical failures inside apply_layer_dmrg mark the
+ *   state invalid; every later call on it returns MPS_ERR_STATE.
+ */
+#ifndef MPS_DMRG_H
+#define MPS_DMRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mps_state mps_state;
+
+typedef enum {
+    MPS_OK = 0,
+    MPS_ERR_ARG = -1,     /* invalid argument; state unchanged               */
+    MPS_ERR_OOM = -2,     /* device allocation failed                        */
+    MPS_ERR_DEVICE = -3,  /* HIP / rocSOLVER error                           */
+    MPS_ERR_NUMERIC = -4, /* non-finite or zero norm, fidelity out of range  */
+    MPS_ERR_STATE = -5    /* the state was invalidated by an earlier failure */
+} mps_status;
+
+/* Arithmetic of the environment and local-tensor contractions.  The
+ * truncation (Gram matrix, Hermitian eigensolver), the fidelity bookkeeping
+ * and the stored MPS tensors are FP64 in every mode. */
+typedef enum {
+    MPS_FP64 = 0,   /* complex FP64 contractions on FP64 MFMA                  */
+    MPS_FP32 = 1    /* complex FP32 contractions on FP32 MFMA, FP32 environments */
+} mps_precision;
+
+/* One gate.  q1 = -1 for a one-qubit gate.  m holds the matrix as interleaved
+ * complex128, row-major with rows = output and columns = input:
+ *   one-qubit: 2x2 in m[0..7];
+ *   two-qubit: 4x4 in m[0..31], row/column index 2*s_q0 + s_q1.
+ * Within one layer every one-qubit gate acts before every two-qubit gate
+ * (the cycle structure of Sec. V.A); one-qubit gates on the same site compose
+ * in array order; two-qubit gates must act on disjoint sites; q0 > q1 is
+ * allowed. */
+typedef struct {
+    int32_t q0;
+    int32_t q1;
+    double m[32];
+} mps_gate;
+
+/* Create the product state |x> (Sec. IV.A: an MPS of bond dimension 1).
+ *   n_sites    number of sites, 1 <= n_sites <= 4096.
+ *   init_bits  n_sites bytes, each 0 or 1; NULL means |0...0>.
+ *   max_chi    largest bond dimension any later call may request (>= 1);
+ *              used for argument checks only.
+ *   precision  an mps_precision value.
+ *   hip_stream hipStream_t to run on (NULL = the default stream).
+ *   out        receives the new state; the caller releases it with
+ *              mps_destroy.  The state owns all of its device memory. */
+mps_status mps_create(int n_sites, const uint8_t* init_bits, int max_chi,
+                      int precision, void* hip_stream, mps_state** out);
+
+/* Release a state and all device memory it owns.  NULL is accepted. */
+mps_status mps_destroy(mps_state* state);
+
+/* One compression step (Sec. IV.B with K = 1): replace |psi> by the bond-chi
+ * MPS |phi> that maximises |<phi|U|psi>|^2, U being the layer given by
+ * `gates`.  The initial guess is a zip-up of the layer's MPO into |psi>
+ * starting at the end of the chain that holds the orthogonality centre; then
+ * n_sweeps two-site sweeps alternate direction.  Each local update keeps
+ * chi' = min(chi, #{S_i^2 > 1e-12 sum_j S_j^2}) singular values of the
+ * two-site tensor F and normalises it (eq:optimization); f = sum of the kept
+ * S^2.  f_layer (may be NULL) receives f_delta, the f of the last update
+ * (eq:fa-sup), which is also multiplied into F~.
+ *   gates     n_gates records (see mps_gate), host memory, copied.
+ *   chi       1 <= chi <= max_chi.
+ *   n_sweeps  >= 0 (0 = zip-up only).
+ * On error the state is unchanged for MPS_ERR_ARG, and invalid otherwise. */
+mps_status apply_layer_dmrg(mps_state* state, const mps_gate* gates, int n_gates,
+                            int chi, int n_sweeps, double* f_layer);
+
+/* The fidelity estimate F~ = prod_delta f_delta (eq:Ftilde-sup), its natural
+ * logarithm, the number of layers applied and the number of two-qubit gates
+ * N_2g applied; the error per gate is eps~ = 1 - F~^(1/N_2g).  Any output
+ * pointer may be NULL. */
+mps_status fidelity(const mps_state* state, double* F_tilde, double* log_F_tilde,
+                    int* n_layers, int64_t* n_2q_gates);
+
+/* Draw n_samples bitstrings from |phi(x)|^2 by exact sequential sampling from
+ * the orthogonality centre outwards (weak simulation, Sec. II.C).  The uniform
+ * number of sample j at site k is a Philox-4x32-10 draw (Salmon et al., SC'11)
+ * keyed by (seed_lo, seed_hi) with counter (k, j_lo, j_hi, 0x5A4D5053), its
+ * words 0 and 1 forming a 53-bit fraction; site k takes 0 when the fraction is
+ * below p(0 | earlier sites).
+ *   bits  host array of n_samples * ceil(n/64) uint64 words; bit (k % 64) of
+ *         word (j * ceil(n/64) + k / 64) is the value of site k in sample j. */
+mps_status sample(mps_state* state, int64_t n_samples, uint64_t seed, uint64_t* bits);
+
+/* Thread-local description of the last error ("" if none). */
+const char* mps_last_error(void);
+
+/* ---- inspection (parity tests, analysis) -------------------------------- */
+
+/* Amplitudes <x|phi> for n_strings bitstrings (n_strings * n bytes, 0/1),
+ * evaluated in FP64 on the device; re_im receives 2 * n_strings doubles. */
+mps_status mps_amplitude(const mps_state* state, int n_strings, const uint8_t* bits,
+                         double* re_im);
+
+/* The full statevector (n <= 26) in FP64: 2 * 2^n doubles, index as above. */
+mps_status mps_to_statevector(const mps_state* state, double* re_im);
+
+/* Bond dimensions: n + 1 ints. */
+mps_status mps_bond_dims(const mps_state* state, int* dims);
+
+/* Copy of site tensor A_site, shape (D_site, 2, D_site+1), row-major, as
+ * interleaved complex128. */
+mps_status mps_get_tensor(const mps_state* state, int site, double* re_im);
+
+/* Per-update log of all layers applied so far, oldest first: partial fidelity
+ * f, sum of all squared singular values of the local tensor, and the number
+ * of singular values kept.  The zip-up of each layer logs one entry (f = its
+ * final norm squared).  At most `cap` entries are written; *n receives the
+ * total number available. */
+mps_status mps_step_log(const mps_state* state, double* f, double* sum_s2,
+                        int* chi_kept, int cap, int* n);
+
+/* <phi| Z_i Z_j |phi> (or <Z_i> when i == j) in FP64. */
+mps_status mps_expect_zz(const mps_state* state, int i, int j, double* value);
+
+/* ---- measurement -------------------------------------------------------- */
+
+/* Kernel classes timed when profiling is on (hipEvents around every launch on
+ * the state's stream). */
+typedef enum {
+    MPS_KCLASS_CONTRACT = 0,  /* complex GEMMs of the environment / local tensor */
+    MPS_KCLASS_MPO = 1,       /* structured MPO application                      */
+    MPS_KCLASS_GRAM = 2,      /* FP64 Gram matrices of the truncation            */
+    MPS_KCLASS_EIGH = 3,      /* FP64 Hermitian eigensolver                      */
+    MPS_KCLASS_OTHER = 4,     /* conversions, reductions, small FP64 GEMMs       */
+    MPS_KCLASS_COUNT = 5
+} mps_kernel_class;
+
+/* Turn per-launch timing on (1) or off (0) and reset the counters. */
+mps_status mps_set_profiling(mps_state* state, int on);
+
+/* Launch count, summed launch duration in milliseconds, summed algorithmic
+ * real flops and summed algorithmic HBM bytes of one kernel class since
+ * profiling was turned on.  Algorithmic flops count 8 per complex
+ * multiply-add; bytes count each operand read once and each result written
+ * once. */
+mps_status mps_kernel_stats(const mps_state* state, int kernel_class, int64_t* launches,
+                            double* total_ms, double* flops, double* bytes);
+
+/* ---- kernel self-test ---------------------------------------------------- */
+
+/* Run the library's complex GEMM kernel once, C = op(A) op(B), on host data:
+ * the operands are copied to the device, converted to the arithmetic of
+ * `precision`, multiplied by the same kernel the compression step uses, and
+ * the result is copied back.  All buffers are HOST, interleaved complex128,
+ * row-major:
+ *   opa 0 (N): a is M x K;   opa 2 (C): a is K x M and op(A) = a^H.
+ *   opb 0 (N): b is K x N;   opb 1 (T): b is N x K, op(B) = b^T;
+ *   opb 2 (C): b is N x K, op(B) = b^H.
+ *   c receives M x N.
+ * For kernel-level parity tests; not used by the compression step. */
+mps_status mps_kernel_selftest_cgemm(int precision, int opa, int opb, int M, int N, int K,
+                                     const double* a, const double* b, double* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPS_DMRG_H */

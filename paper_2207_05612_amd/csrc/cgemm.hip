@@ -1,0 +1,272 @@
+// Complex planar GEMM on CDNA4 matrix cores (gfx950).
+//
+// Every contraction of the compression step (environments, two-site local
+// tensor, Gram matrices of the truncation, sampling) is a dense complex
+// matrix product; here each complex multiply-add is four real MFMA products
+// on planar (separate real / imaginary) operands:
+//   Cr += Ar Br - Ai Bi,   Ci += Ar Bi + Ai Br.
+//
+// Tiling: 256 threads = 4 wavefronts of 64 lanes in a 2 x 2 arrangement.
+// FP32 uses v_mfma_f32_32x32x2_f32 (wave tile 64 x 64 complex, block tile
+// 128 x 128, BK = 16); FP64 uses v_mfma_f64_16x16x4_f64 (wave tile 64 x 32,
+// block tile 128 x 64, BK = 8).  Operand tiles go global -> registers -> LDS
+// with k-major rows ([k][m] and [k][n]) so that the lanes of one MFMA operand
+// read consecutive LDS words; two LDS buffers let the next tile's global loads
+// overlap the current tile's MFMAs with one barrier per k-tile.  Launches map
+// block ids to tiles XCD-first (8 XCDs, each with its own L2) and then in
+// groups of 8 tile rows so that neighbouring tiles share operand panels in L2.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace mpsk {
+
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<float> {
+    static constexpr int MT = 32;  // output tile edge
+    static constexpr int KT = 2;   // k per instruction
+    static constexpr int NACC = 16;
+    typedef float acc_t __attribute__((ext_vector_type(16)));
+    __device__ static inline acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+    }
+    // row of accumulator element v held by lane l (column = l % 32)
+    __device__ static inline int row(int v, int lane) { return (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3); }
+};
+
+template <>
+struct Mfma<double> {
+    static constexpr int MT = 16;
+    static constexpr int KT = 4;
+    static constexpr int NACC = 4;
+    typedef double acc_t __attribute__((ext_vector_type(4)));
+    __device__ static inline acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int row(int v, int lane) { return v * 4 + (lane >> 4); }
+};
+
+template <typename TIn, typename TAcc>
+struct GemmArgs {
+    const TIn* a_re;
+    const TIn* a_im;
+    const TIn* b_re;
+    const TIn* b_im;
+    TAcc* c_re;
+    TAcc* c_im;
+    int64_t lda, ldb, ldc;
+    int M, N, K;
+    int gm, gn;
+};
+
+template <typename TIn, typename TAcc, int OPA, int OPB, int BM, int BN, int BK>
+__global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
+    using MF = Mfma<TAcc>;
+    constexpr int MT = MF::MT;
+    constexpr int WM = BM / 2, WN = BN / 2;        // wave tile
+    constexpr int TM = WM / MT, TN = WN / MT;       // MFMA tiles per wave
+    constexpr int PADA = (sizeof(TAcc) == 8) ? 4 : 4;
+    constexpr int LDA_S = BM + PADA, LDB_S = BN + PADA;
+    constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
+    static_assert(BM * BK % 256 == 0 && BN * BK % 256 == 0, "tile/thread mismatch");
+
+    __shared__ TAcc As[2][2][BK][LDA_S];
+    __shared__ TAcc Bs[2][2][BK][LDB_S];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm0 = (wave >> 1) * WM;
+    const int wn0 = (wave & 1) * WN;
+
+    // ---- tile mapping: XCD-contiguous, then grouped rows
+    int pid = blockIdx.x;
+    const int nb = g.gm * g.gn;
+    if ((nb & 7) == 0) pid = (pid & 7) * (nb >> 3) + (pid >> 3);
+    constexpr int GROUP = 8;
+    const int group = pid / (GROUP * g.gn);
+    const int first_m = group * GROUP;
+    const int gsz = min(g.gm - first_m, GROUP);
+    const int tm = first_m + (pid % gsz);
+    const int tn = (pid % (GROUP * g.gn)) / gsz;
+    const int m0 = tm * BM, n0 = tn * BN;
+
+    const int M = g.M, N = g.N, K = g.K;
+
+    TIn ra_re[EA], ra_im[EA], rb_re[EB], rb_im[EB];
+
+    auto load_tiles = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < EA; ++i) {
+            const int idx = tid + 256 * i;
+            int m, k;
+            if (OPA == OP_N) { k = idx % BK; m = idx / BK; }
+            else             { m = idx % BM; k = idx / BM; }
+            const int gm_ = m0 + m, gk = k0 + k;
+            TIn vr = 0, vi = 0;
+            if (gm_ < M && gk < K) {
+                const int64_t off = (OPA == OP_N) ? (int64_t)gm_ * g.lda + gk : (int64_t)gk * g.lda + gm_;
+                vr = g.a_re[off];
+                vi = g.a_im[off];
+                if (OPA == OP_C) vi = -vi;
+            }
+            ra_re[i] = vr;
+            ra_im[i] = vi;
+        }
+#pragma unroll
+        for (int i = 0; i < EB; ++i) {
+            const int idx = tid + 256 * i;
+            int n, k;
+            if (OPB == OP_N) { n = idx % BN; k = idx / BN; }
+            else             { k = idx % BK; n = idx / BK; }
+            const int gn_ = n0 + n, gk = k0 + k;
+            TIn vr = 0, vi = 0;
+            if (gn_ < N && gk < K) {
+                const int64_t off = (OPB == OP_N) ? (int64_t)gk * g.ldb + gn_ : (int64_t)gn_ * g.ldb + gk;
+                vr = g.b_re[off];
+                vi = g.b_im[off];
+                if (OPB == OP_C) vi = -vi;
+            }
+            rb_re[i] = vr;
+            rb_im[i] = vi;
+        }
+    };
+    auto store_tiles = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < EA; ++i) {
+            const int idx = tid + 256 * i;
+            int m, k;
+            if (OPA == OP_N) { k = idx % BK; m = idx / BK; }
+            else             { m = idx % BM; k = idx / BM; }
+            As[buf][0][k][m] = (TAcc)ra_re[i];
+            As[buf][1][k][m] = (TAcc)ra_im[i];
+        }
+#pragma unroll
+        for (int i = 0; i < EB; ++i) {
+            const int idx = tid + 256 * i;
+            int n, k;
+            if (OPB == OP_N) { n = idx % BN; k = idx / BN; }
+            else             { k = idx % BK; n = idx / BK; }
+            Bs[buf][0][k][n] = (TAcc)rb_re[i];
+            Bs[buf][1][k][n] = (TAcc)rb_im[i];
+        }
+    };
+
+    typename MF::acc_t acc_re[TM][TN], acc_im[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < MF::NACC; ++v) { acc_re[i][j][v] = 0; acc_im[i][j][v] = 0; }
+
+    const int nk = (K + BK - 1) / BK;
+    load_tiles(0);
+    store_tiles(0);
+    __syncthreads();
+
+    const int lrow = lane % MT;
+    const int lk = lane / MT;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += MF::KT) {
+            TAcc ar[TM], ai[TM], nai[TM], br[TN], bi[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                ar[i] = As[buf][0][kk + lk][wm0 + i * MT + lrow];
+                ai[i] = As[buf][1][kk + lk][wm0 + i * MT + lrow];
+                nai[i] = -ai[i];
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                br[j] = Bs[buf][0][kk + lk][wn0 + j * MT + lrow];
+                bi[j] = Bs[buf][1][kk + lk][wn0 + j * MT + lrow];
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc_re[i][j] = MF::mma(ar[i], br[j], acc_re[i][j]);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc_im[i][j] = MF::mma(ar[i], bi[j], acc_im[i][j]);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc_re[i][j] = MF::mma(nai[i], bi[j], acc_re[i][j]);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc_im[i][j] = MF::mma(ai[i], br[j], acc_im[i][j]);
+        }
+        if (kt + 1 < nk) store_tiles(buf ^ 1);
+        __syncthreads();
+    }
+
+    // ---- epilogue
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < MF::NACC; ++v) {
+                const int r = m0 + wm0 + i * MT + MF::row(v, lane);
+                const int c = n0 + wn0 + j * MT + lrow;
+                if (r < M && c < N) {
+                    const int64_t off = (int64_t)r * g.ldc + c;
+                    g.c_re[off] = acc_re[i][j][v];
+                    g.c_im[off] = acc_im[i][j][v];
+                }
+            }
+}
+
+template <typename TIn, typename TAcc, int BM, int BN, int BK>
+static hipError_t launch(int opa, int opb, int M, int N, int K, CView<TIn> A, CView<TIn> B,
+                         CViewMut<TAcc> C, hipStream_t stream) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    GemmArgs<TIn, TAcc> g;
+    g.a_re = A.re; g.a_im = A.im; g.lda = A.ld;
+    g.b_re = B.re; g.b_im = B.im; g.ldb = B.ld;
+    g.c_re = C.re; g.c_im = C.im; g.ldc = C.ld;
+    g.M = M; g.N = N; g.K = K;
+    g.gm = (M + BM - 1) / BM;
+    g.gn = (N + BN - 1) / BN;
+    const int64_t nblocks = (int64_t)g.gm * g.gn;
+    if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
+    dim3 grid((unsigned)nblocks), block(256);
+#define MPS_GEMM_CASE(OA, OB)                                                                     \
+    if (opa == OA && opb == OB) {                                                                 \
+        hipLaunchKernelGGL((cgemm_kernel<TIn, TAcc, OA, OB, BM, BN, BK>), grid, block, 0, stream, g); \
+        return hipGetLastError();                                                                 \
+    }
+    MPS_GEMM_CASE(OP_N, OP_N)
+    MPS_GEMM_CASE(OP_N, OP_T)
+    MPS_GEMM_CASE(OP_N, OP_C)
+    MPS_GEMM_CASE(OP_C, OP_N)
+    MPS_GEMM_CASE(OP_C, OP_T)
+    MPS_GEMM_CASE(OP_C, OP_C)
+#undef MPS_GEMM_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t cgemm_f32(int opa, int opb, int M, int N, int K, CView<float> A, CView<float> B,
+                     CViewMut<float> C, hipStream_t stream) {
+    return launch<float, float, 128, 128, 16>(opa, opb, M, N, K, A, B, C, stream);
+}
+
+hipError_t cgemm_f64(int opa, int opb, int M, int N, int K, CView<double> A, CView<double> B,
+                     CViewMut<double> C, hipStream_t stream) {
+    return launch<double, double, 128, 64, 8>(opa, opb, M, N, K, A, B, C, stream);
+}
+
+hipError_t cgemm_f32in_f64(int opa, int opb, int M, int N, int K, CView<float> A,
+                           CView<float> B, CViewMut<double> C, hipStream_t stream) {
+    return launch<float, double, 128, 64, 8>(opa, opb, M, N, K, A, B, C, stream);
+}
+
+}  // namespace mpsk

@@ -1,0 +1,1211 @@
+// Host driver of the DMRG compression step: the C ABI of include/mps_dmrg.h.
+//
+// One compression step (Sec. IV.B of Ayral et al.) on one GPU:
+//   1. the layer becomes a structured MPO on the host (one-qubit gates
+//      absorbed, two-qubit gates split by a 4x4 SVD, eq:SVD / App. A.1);
+//   2. zip-up initial guess (the TEBD-like start of Sec. V.D.1) from the end
+//      of the chain that holds the orthogonality centre;
+//   3. n_sweeps two-site sweeps in alternating directions; each step builds
+//      the local tensor F of the pair in the vertical contraction order of
+//      Sec. IV.B.2, keeps the chi largest singular values (Sec. VI.A) and
+//      normalises (eq:optimization);
+//   4. f_delta, the f of the last step, multiplies into F~ (eq:Ftilde-sup).
+//
+// Every pass is executed as a left-to-right pass over a "view" of the chain:
+// view 0 is the chain itself, view 1 the mirrored chain (site j of view 1 is
+// site n-1-j, and its tensors have their two virtual legs swapped).  The
+// environments are stored per bond of the chain, so the left environments
+// written by a pass in one view are exactly the right environments read by
+// the next pass in the other view.  Only one kernel pipeline is needed.
+//
+// Contractions run in the state's working precision (FP32 or FP64 complex
+// MFMA GEMMs).  The truncation is FP64: the Gram matrix of the local tensor
+// (FP64 MFMA), rocSOLVER's Hermitian eigensolver, and the kept-weight sums.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <array>
+#include <functional>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mps_dmrg.h"
+#include "internal.h"
+
+using namespace mpsk;
+typedef std::complex<double> cd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct MpsFail {
+    mps_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(mps_status code, const std::string& msg) { throw MpsFail{code, msg}; }
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            fail(e_ == hipErrorOutOfMemory ? MPS_ERR_OOM : MPS_ERR_DEVICE,                    \
+                 std::string(#expr) + ": " + hipGetErrorString(e_));                          \
+    } while (0)
+
+constexpr double EPS_TRUNC = 1e-12;        // kept: S^2 > EPS_TRUNC * sum S^2
+constexpr double GATE_RANK_CUTOFF = 1e-14; // operator-Schmidt terms kept: sigma > cutoff * sigma_0
+
+// ------------------------------------------------------------ device memory
+void* dalloc(size_t bytes, hipStream_t s) {
+    if (bytes == 0) bytes = 256;
+    void* p = nullptr;
+    hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e != hipSuccess || p == nullptr) {
+        (void)hipGetLastError();
+        fail(MPS_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    return p;
+}
+void dfree(void* p, hipStream_t s) {
+    if (p) (void)hipFreeAsync(p, s);
+}
+
+// Planar complex buffer: re = p, im = p + cap.
+template <typename T>
+struct Planar {
+    T* p = nullptr;
+    int64_t cap = 0;
+    T* re() const { return p; }
+    T* im() const { return p + cap; }
+    void ensure(int64_t n, hipStream_t s) {
+        if (n <= cap && p) return;
+        dfree(p, s);
+        p = (T*)dalloc(sizeof(T) * 2 * (size_t)std::max<int64_t>(n, 1), s);
+        cap = std::max<int64_t>(n, 1);
+    }
+    void release(hipStream_t s) {
+        dfree(p, s);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+template <typename T>
+struct Raw {
+    T* p = nullptr;
+    int64_t cap = 0;
+    void ensure(int64_t n, hipStream_t s) {
+        if (n <= cap && p) return;
+        dfree(p, s);
+        p = (T*)dalloc(sizeof(T) * (size_t)std::max<int64_t>(n, 1), s);
+        cap = std::max<int64_t>(n, 1);
+    }
+    void release(hipStream_t s) {
+        dfree(p, s);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+// ------------------------------------------------------------ profiling ----
+struct KStat {
+    int64_t launches = 0;
+    double ms = 0, flops = 0, bytes = 0;
+};
+struct PendingTiming {
+    int cls;
+    hipEvent_t a, b;
+    double flops, bytes;
+};
+
+// ------------------------------------------------------- 4x4 complex SVD ---
+// One-sided Jacobi (Hestenes): rotate the columns of m until they are
+// mutually orthogonal; singular values are the column norms.
+void svd4(const cd m_in[4][4], double sigma[4], cd u[4][4], cd v[4][4]) {
+    cd a[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            a[i][j] = m_in[i][j];
+            v[i][j] = (i == j) ? 1.0 : 0.0;
+        }
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0;
+        for (int p = 0; p < 3; ++p)
+            for (int q = p + 1; q < 4; ++q) {
+                double al = 0, be = 0;
+                cd ga = 0;
+                for (int i = 0; i < 4; ++i) {
+                    al += std::norm(a[i][p]);
+                    be += std::norm(a[i][q]);
+                    ga += std::conj(a[i][p]) * a[i][q];
+                }
+                const double ag = std::abs(ga);
+                if (ag == 0.0 || ag <= 1e-17 * std::sqrt(al * be)) continue;
+                off = std::max(off, ag / std::sqrt(al * be));
+                const cd ph = ga / ag;  // e^{i phi}
+                const double zeta = (be - al) / (2.0 * ag);
+                const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
+                const cd phc = std::conj(ph);
+                for (int i = 0; i < 4; ++i) {
+                    const cd xp = a[i][p], xq = a[i][q];
+                    a[i][p] = c * xp - s * phc * xq;
+                    a[i][q] = s * xp + c * phc * xq;
+                    const cd vp = v[i][p], vq = v[i][q];
+                    v[i][p] = c * vp - s * phc * vq;
+                    v[i][q] = s * vp + c * phc * vq;
+                }
+            }
+        if (off < 1e-16) break;
+    }
+    double nrm[4];
+    int order[4] = {0, 1, 2, 3};
+    for (int j = 0; j < 4; ++j) {
+        nrm[j] = 0;
+        for (int i = 0; i < 4; ++i) nrm[j] += std::norm(a[i][j]);
+        nrm[j] = std::sqrt(nrm[j]);
+    }
+    std::sort(order, order + 4, [&](int x, int y) { return nrm[x] > nrm[y]; });
+    cd vv[4][4];
+    for (int jj = 0; jj < 4; ++jj) {
+        const int j = order[jj];
+        sigma[jj] = nrm[j];
+        for (int i = 0; i < 4; ++i) {
+            u[i][jj] = nrm[j] > 0 ? a[i][j] / nrm[j] : cd(0);
+            vv[i][jj] = v[i][j];
+        }
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) v[i][j] = vv[i][j];
+}
+
+// ------------------------------------------------------------ layer MPO ----
+struct HostGate {
+    int i, j, r;
+    cd x[4][2][2], y[4][2][2];  // [a][s][t]
+};
+
+struct LayerMpo {
+    std::vector<int64_t> w;              // n + 1 bond dims
+    std::vector<MpoSiteOp> view[2];      // per view-site
+    int n_2q = 0;
+};
+
+void mul2(const cd a[2][2], const cd b[2][2], cd out[2][2]) {
+    for (int s = 0; s < 2; ++s)
+        for (int t = 0; t < 2; ++t) out[s][t] = a[s][0] * b[0][t] + a[s][1] * b[1][t];
+}
+
+void set_op(MpoSiteOp& op, int r_in, int r_out, int lo, int64_t H, const cd (*ops)[2][2]) {
+    op.r_in = r_in;
+    op.r_out = r_out;
+    op.lo = lo;
+    op.H = (int)H;
+    for (int i = 0; i < 16; ++i) op.re[i] = op.im[i] = 0;
+    const int r = std::max(r_in, r_out);
+    for (int a = 0; a < r; ++a)
+        for (int s = 0; s < 2; ++s)
+            for (int t = 0; t < 2; ++t) {
+                const int ao = (r_out > 1) ? a : 0, ai = (r_in > 1) ? a : 0;
+                const int c = ((ao * r_in + ai) * 2 + s) * 2 + t;
+                op.re[c] = ops[a][s][t].real();
+                op.im[c] = ops[a][s][t].imag();
+            }
+}
+
+LayerMpo build_layer_mpo(int n, const mps_gate* gates, int n_gates) {
+    std::vector<cd> g1m(4 * (size_t)n);
+    auto G1 = [&](int k, int s, int t) -> cd& { return g1m[(size_t)k * 4 + s * 2 + t]; };
+    for (int k = 0; k < n; ++k) {
+        G1(k, 0, 0) = 1; G1(k, 0, 1) = 0; G1(k, 1, 0) = 0; G1(k, 1, 1) = 1;
+    }
+    std::vector<int> used(n, 0);
+    std::vector<HostGate> hg;
+    for (int gi = 0; gi < n_gates; ++gi) {
+        const mps_gate& g = gates[gi];
+        for (int e = 0; e < 32; ++e)
+            if (!std::isfinite(g.m[e])) fail(MPS_ERR_ARG, "gate matrix has a non-finite entry");
+        if (g.q1 < 0) {
+            if (g.q1 != -1 || g.q0 < 0 || g.q0 >= n) fail(MPS_ERR_ARG, "one-qubit gate site out of range");
+            cd u[2][2], cur[2][2], out[2][2];
+            for (int s = 0; s < 2; ++s)
+                for (int t = 0; t < 2; ++t) {
+                    u[s][t] = cd(g.m[2 * (s * 2 + t)], g.m[2 * (s * 2 + t) + 1]);
+                    cur[s][t] = G1(g.q0, s, t);
+                }
+            mul2(u, cur, out);
+            for (int s = 0; s < 2; ++s)
+                for (int t = 0; t < 2; ++t) G1(g.q0, s, t) = out[s][t];
+            continue;
+        }
+        if (g.q0 < 0 || g.q0 >= n || g.q1 >= n || g.q0 == g.q1)
+            fail(MPS_ERR_ARG, "two-qubit gate sites out of range or equal");
+        if (used[g.q0] || used[g.q1]) fail(MPS_ERR_ARG, "two-qubit gates of one layer must be disjoint");
+        used[g.q0] = used[g.q1] = 1;
+        // U[(s0 s1), (t0 t1)] -> Ut[(s_i t_i), (s_j t_j)] with i = min site
+        cd u4[2][2][2][2];
+        for (int s0 = 0; s0 < 2; ++s0)
+            for (int s1 = 0; s1 < 2; ++s1)
+                for (int t0 = 0; t0 < 2; ++t0)
+                    for (int t1 = 0; t1 < 2; ++t1) {
+                        const int e = (s0 * 2 + s1) * 4 + (t0 * 2 + t1);
+                        u4[s0][s1][t0][t1] = cd(g.m[2 * e], g.m[2 * e + 1]);
+                    }
+        const bool swapq = g.q0 > g.q1;
+        cd mt[4][4];
+        for (int si = 0; si < 2; ++si)
+            for (int ti = 0; ti < 2; ++ti)
+                for (int sj = 0; sj < 2; ++sj)
+                    for (int tj = 0; tj < 2; ++tj)
+                        mt[si * 2 + ti][sj * 2 + tj] = swapq ? u4[sj][si][tj][ti] : u4[si][sj][ti][tj];
+        double sig[4];
+        cd uu[4][4], vv[4][4];
+        svd4(mt, sig, uu, vv);
+        HostGate h;
+        h.i = std::min(g.q0, g.q1);
+        h.j = std::max(g.q0, g.q1);
+        h.r = 0;
+        for (int a = 0; a < 4; ++a)
+            if (sig[a] > GATE_RANK_CUTOFF * sig[0]) h.r = a + 1;
+        for (int a = 0; a < h.r; ++a) {
+            const double rs = std::sqrt(sig[a]);
+            for (int s = 0; s < 2; ++s)
+                for (int t = 0; t < 2; ++t) {
+                    h.x[a][s][t] = rs * uu[s * 2 + t][a];
+                    h.y[a][s][t] = rs * std::conj(vv[s * 2 + t][a]);
+                }
+        }
+        hg.push_back(h);
+    }
+    std::sort(hg.begin(), hg.end(), [](const HostGate& a, const HostGate& b) { return a.i < b.i; });
+    // absorb the one-qubit gates (they act first, on the input leg)
+    for (auto& h : hg) {
+        for (int a = 0; a < h.r; ++a) {
+            cd gi[2][2], gj[2][2], tmp[2][2];
+            for (int s = 0; s < 2; ++s)
+                for (int t = 0; t < 2; ++t) { gi[s][t] = G1(h.i, s, t); gj[s][t] = G1(h.j, s, t); }
+            mul2(h.x[a], gi, tmp);
+            std::memcpy(h.x[a], tmp, sizeof(tmp));
+            mul2(h.y[a], gj, tmp);
+            std::memcpy(h.y[a], tmp, sizeof(tmp));
+        }
+    }
+    LayerMpo L;
+    L.n_2q = (int)hg.size();
+    L.w.assign(n + 1, 1);
+    std::vector<int> start_at(n, -1), end_at(n, -1);
+    for (int g = 0; g < (int)hg.size(); ++g) {
+        start_at[hg[g].i] = g;
+        end_at[hg[g].j] = g;
+    }
+    for (int c = 0; c <= n; ++c) {
+        int64_t w = 1;
+        for (auto& h : hg)
+            if (h.i < c && c <= h.j) w *= h.r;
+        L.w[c] = w;
+        if (w > (int64_t)1 << 24) fail(MPS_ERR_ARG, "MPO bond dimension exceeds 2^24");
+    }
+    L.view[0].resize(n);
+    L.view[1].resize(n);
+    for (int k = 0; k < n; ++k) {
+        MpoSiteOp& f = L.view[0][k];
+        MpoSiteOp& b = L.view[1][n - 1 - k];
+        if (start_at[k] >= 0) {
+            const HostGate& h = hg[start_at[k]];
+            // the opening gate has the largest left site of bond k+1: least significant
+            set_op(f, 1, h.r, 1, L.w[k], h.x);
+            set_op(b, h.r, 1, 1, L.w[k], h.x);
+        } else if (end_at[k] >= 0) {
+            const HostGate& h = hg[end_at[k]];
+            int64_t lo = 1;
+            for (auto& o : hg)
+                if (o.i < k && k <= o.j && o.i > h.i) lo *= o.r;
+            set_op(f, h.r, 1, (int)lo, L.w[k] / (h.r * lo), h.y);
+            set_op(b, 1, h.r, (int)lo, L.w[k + 1] / lo, h.y);
+        } else {
+            cd g[1][2][2];
+            for (int s = 0; s < 2; ++s)
+                for (int t = 0; t < 2; ++t) g[0][s][t] = G1(k, s, t);
+            set_op(f, 1, 1, 1, L.w[k], g);
+            set_op(b, 1, 1, 1, L.w[k], g);
+        }
+    }
+    return L;
+}
+
+}  // namespace
+
+// ================================================================ state ====
+struct mps_state {
+    int n = 0, max_chi = 1, prec = MPS_FP64;
+    hipStream_t stream = nullptr;
+    int orient = 0;               // stored tensor layout: 0 = [D_k][2][D_k+1], 1 = legs swapped
+    int center = 0;               // site holding the norm: 0 or n-1
+    std::vector<int> bond;        // n + 1 bond dimensions
+    std::vector<Planar<double>> ten;  // per site, FP64 planar
+    double log_f = 0;
+    int n_layers = 0;
+    int64_t n_2q = 0;
+    std::vector<double> log_step_f, log_step_s2;
+    std::vector<int> log_step_chi;
+    bool invalid = false;
+    rocblas_handle blas = nullptr;
+    // scratch
+    Raw<double> dscal;             // small device scalars
+    Raw<double> partial;           // reduction partials
+    bool prof = false;
+    KStat stats[MPS_KCLASS_COUNT];
+    std::vector<PendingTiming> pending;
+    std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+hipEvent_t get_event(mps_state* st) {
+    if (!st->event_pool.empty()) {
+        hipEvent_t e = st->event_pool.back();
+        st->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+}
+
+struct Timer {
+    mps_state* st;
+    int cls;
+    double flops, bytes;
+    hipEvent_t a = nullptr;
+    Timer(mps_state* s, int c, double f, double b) : st(s), cls(c), flops(f), bytes(b) {
+        if (st->prof) {
+            a = get_event(st);
+            HIPCHK(hipEventRecord(a, st->stream));
+        }
+    }
+    void done() {
+        if (!st->prof) return;
+        hipEvent_t b = get_event(st);
+        HIPCHK(hipEventRecord(b, st->stream));
+        st->pending.push_back({cls, a, b, flops, bytes});
+    }
+};
+
+void flush_timings(mps_state* st) {
+    if (st->pending.empty()) return;
+    HIPCHK(hipStreamSynchronize(st->stream));
+    for (auto& p : st->pending) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+        KStat& k = st->stats[p.cls];
+        k.launches += 1;
+        k.ms += ms;
+        k.flops += p.flops;
+        k.bytes += p.bytes;
+        st->event_pool.push_back(p.a);
+        st->event_pool.push_back(p.b);
+    }
+    st->pending.clear();
+}
+
+// ---------------------------------------------------------- GEMM helpers ---
+template <typename R>
+hipError_t gemm_raw(int opa, int opb, int M, int N, int K, const R* ar, const R* ai, int64_t lda,
+                    const R* br, const R* bi, int64_t ldb, R* cr, R* ci, int64_t ldc, hipStream_t s);
+template <>
+hipError_t gemm_raw<float>(int opa, int opb, int M, int N, int K, const float* ar, const float* ai,
+                           int64_t lda, const float* br, const float* bi, int64_t ldb, float* cr,
+                           float* ci, int64_t ldc, hipStream_t s) {
+    return cgemm_f32(opa, opb, M, N, K, {ar, ai, lda}, {br, bi, ldb}, {cr, ci, ldc}, s);
+}
+template <>
+hipError_t gemm_raw<double>(int opa, int opb, int M, int N, int K, const double* ar, const double* ai,
+                            int64_t lda, const double* br, const double* bi, int64_t ldb, double* cr,
+                            double* ci, int64_t ldc, hipStream_t s) {
+    return cgemm_f64(opa, opb, M, N, K, {ar, ai, lda}, {br, bi, ldb}, {cr, ci, ldc}, s);
+}
+
+template <typename R>
+void gemm(mps_state* st, int cls, int opa, int opb, int64_t M, int64_t N, int64_t K, const R* ar,
+          const R* ai, int64_t lda, const R* br, const R* bi, int64_t ldb, R* cr, R* ci, int64_t ldc) {
+    if (M > 0x7fffffff || N > 0x7fffffff || K > 0x7fffffff) fail(MPS_ERR_ARG, "GEMM dimension too large");
+    const double fl = 8.0 * (double)M * (double)N * (double)K;
+    const double by = 2.0 * sizeof(R) * ((double)M * K + (double)K * N + (double)M * N);
+    Timer t(st, cls, fl, by);
+    HIPCHK(gemm_raw<R>(opa, opb, (int)M, (int)N, (int)K, ar, ai, lda, br, bi, ldb, cr, ci, ldc, st->stream));
+    t.done();
+}
+
+// =========================================================== the engine ====
+template <typename R>
+struct Engine {
+    mps_state* st;
+    hipStream_t s;
+    int n, chi;
+    LayerMpo mpo;
+    std::vector<int> cb;              // bond dims of phi (being built)
+    std::vector<Planar<R>> env;       // per bond
+    std::vector<Planar<R>> psi[2];    // per view-site, view layout
+    std::vector<Planar<double>> phi;  // per site, layout of the pass that wrote it
+    Planar<R> X, T2, T4, TH, UR;
+    Planar<double> TH64, GR, U64, V64, M64;
+    Raw<double> Z, evals, evwork, svec;
+    Raw<int> info;
+    std::vector<double> hvals;
+
+    Engine(mps_state* state, int chi_) : st(state), s(state->stream), n(state->n), chi(chi_) {}
+
+    ~Engine() {
+        for (auto& e : env) e.release(s);
+        for (int o = 0; o < 2; ++o)
+            for (auto& e : psi[o]) e.release(s);
+        X.release(s); T2.release(s); T4.release(s); TH.release(s); UR.release(s);
+        TH64.release(s); GR.release(s); U64.release(s); V64.release(s); M64.release(s);
+        Z.release(s); evals.release(s); evwork.release(s); svec.release(s); info.release(s);
+        for (auto& p : phi) p.release(s);
+    }
+
+    int site(int o, int j) const { return o == 0 ? j : n - 1 - j; }
+    int bnd(int o, int j) const { return o == 0 ? j : n - j; }
+
+    // ---------------------------------------------------------- truncation
+    struct Trunc {
+        int k;
+        double f, total;
+        bool caseA;
+    };
+
+    // FP64 eigen-decomposition of the Hermitian n x n Gram matrix in GR.
+    void eigh(int dim) {
+        Z.ensure(2 * (int64_t)dim * dim, s);
+        evals.ensure(dim, s);
+        evwork.ensure(dim, s);
+        info.ensure(1, s);
+        {
+            Timer t(st, MPS_KCLASS_OTHER, 0, 32.0 * dim * dim);
+            HIPCHK(pack_hermitian(GR.re(), GR.im(), dim, Z.p, s));
+            t.done();
+        }
+        Timer t(st, MPS_KCLASS_EIGH, 0, 0);
+        rocblas_status rs = rocsolver_zheevd(st->blas, rocblas_evect_original, rocblas_fill_upper, dim,
+                                             (rocblas_double_complex*)Z.p, dim, evals.p, evwork.p, info.p);
+        t.done();
+        if (rs != rocblas_status_success) fail(MPS_ERR_DEVICE, "rocsolver_zheevd failed: status " + std::to_string((int)rs));
+    }
+
+    // Kept count and weights from the eigenvalues of the Gram matrix.
+    Trunc select(int dim, int chi_) {
+        hvals.resize(dim);
+        int hinfo = 0;
+        HIPCHK(hipMemcpyAsync(hvals.data(), evals.p, sizeof(double) * dim, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (hinfo != 0) fail(MPS_ERR_NUMERIC, "eigensolver did not converge (info " + std::to_string(hinfo) + ")");
+        double total = 0;
+        for (int i = dim - 1; i >= 0; --i) total += hvals[i];
+        if (!(total > 0) || !std::isfinite(total)) fail(MPS_ERR_NUMERIC, "local tensor has zero or non-finite norm");
+        int keep = 0;
+        for (int i = dim - 1; i >= 0; --i)
+            if (hvals[i] > EPS_TRUNC * total) ++keep;
+        const int k = std::max(1, std::min(chi_, keep));
+        double f = 0;
+        for (int i = 0; i < k; ++i) f += hvals[dim - 1 - i];
+        return Trunc{k, f, total, true};
+    }
+
+    // Truncated SVD of the rows x cols matrix M (working precision, planar,
+    // row-major).  On return U64 holds U (rows x k).  When want_right is set,
+    // V64 holds the right factor S V^H / sqrt(f) (k x cols).
+    Trunc truncate(const R* m_re, const R* m_im, int64_t rows, int64_t cols, bool want_right,
+                   const double* m64_re, const double* m64_im) {
+        if (rows <= cols) {
+            const int dim = (int)rows;
+            GR.ensure((int64_t)dim * dim, s);
+            {
+                Timer t(st, MPS_KCLASS_GRAM, 8.0 * rows * rows * cols, 2.0 * sizeof(R) * rows * cols + 16.0 * rows * rows);
+                if (m64_re) {
+                    HIPCHK(cgemm_f64(OP_N, OP_C, dim, dim, (int)cols, {m64_re, m64_im, cols}, {m64_re, m64_im, cols},
+                                     {GR.re(), GR.im(), dim}, s));
+                } else {
+                    gram_from_working(m_re, m_im, dim, cols);
+                }
+                t.done();
+            }
+            eigh(dim);
+            Trunc tr = select(dim, chi);
+            U64.ensure(rows * tr.k, s);
+            HIPCHK(take_top_eigvecs(Z.p, dim, tr.k, nullptr, U64.re(), U64.im(), s));
+            if (want_right) {
+                if (!m64_re) fail(MPS_ERR_ARG, "internal: right factor needs FP64 input");
+                V64.ensure((int64_t)tr.k * cols, s);
+                gemm<double>(st, MPS_KCLASS_OTHER, OP_C, OP_N, tr.k, cols, rows, U64.re(), U64.im(), tr.k,
+                             m64_re, m64_im, cols, V64.re(), V64.im(), cols);
+                set_scalar(0, 1.0 / std::sqrt(tr.f));
+                HIPCHK(scale_by_device_scalar<double>(V64.re(), V64.im(), (int64_t)tr.k * cols, st->dscal.p, s));
+            }
+            tr.caseA = true;
+            return tr;
+        }
+        // rows > cols: eigen-decompose M^H M, U = M V S^{-1}
+        const int dim = (int)cols;
+        if (!m64_re) {
+            M64.ensure(rows * cols, s);
+            HIPCHK((convert_planar<R, double>(m_re, m_im, rows * cols, M64.re(), M64.im(), s)));
+            m64_re = M64.re();
+            m64_im = M64.im();
+        }
+        GR.ensure((int64_t)dim * dim, s);
+        {
+            Timer t(st, MPS_KCLASS_GRAM, 8.0 * cols * cols * rows, 16.0 * (rows * cols + cols * cols));
+            HIPCHK(cgemm_f64(OP_C, OP_N, dim, dim, (int)rows, {m64_re, m64_im, cols}, {m64_re, m64_im, cols},
+                             {GR.re(), GR.im(), dim}, s));
+            t.done();
+        }
+        eigh(dim);
+        Trunc tr = select(dim, chi);
+        V64.ensure((int64_t)dim * tr.k, s);
+        HIPCHK(take_top_eigvecs(Z.p, dim, tr.k, nullptr, V64.re(), V64.im(), s));
+        std::vector<double> inv_s(tr.k), s_over(tr.k);
+        for (int i = 0; i < tr.k; ++i) {
+            const double sv = std::sqrt(std::max(hvals[dim - 1 - i], 0.0));
+            inv_s[i] = sv > 0 ? 1.0 / sv : 0.0;
+            s_over[i] = sv / std::sqrt(tr.f);
+        }
+        svec.ensure(2 * tr.k, s);
+        HIPCHK(hipMemcpyAsync(svec.p, inv_s.data(), sizeof(double) * tr.k, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(svec.p + tr.k, s_over.data(), sizeof(double) * tr.k, hipMemcpyHostToDevice, s));
+        U64.ensure(rows * tr.k, s);
+        gemm<double>(st, MPS_KCLASS_OTHER, OP_N, OP_N, rows, tr.k, cols, m64_re, m64_im, cols, V64.re(), V64.im(),
+                     tr.k, U64.re(), U64.im(), tr.k);
+        HIPCHK(scale_columns(U64.re(), U64.im(), rows, tr.k, svec.p, s));
+        if (want_right) {
+            // S V^H / sqrt(f): (k x cols) from V (cols x k)
+            Planar<double> tmp;
+            tmp.ensure((int64_t)tr.k * cols, s);
+            HIPCHK(scaled_adjoint(V64.re(), V64.im(), dim, tr.k, svec.p + tr.k, tmp.re(), tmp.im(), s));
+            std::swap(tmp, V64);
+            tmp.release(s);
+        }
+        HIPCHK(hipStreamSynchronize(s));  // host vectors above must outlive their copies
+        tr.caseA = false;
+        return tr;
+    }
+
+    void gram_from_working(const R* m_re, const R* m_im, int dim, int64_t cols);
+
+    void set_scalar(int idx, double v) {
+        HIPCHK(hipMemcpyAsync(st->dscal.p + idx, &v, sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+
+    // ------------------------------------------------------------ layer
+    // Buffers grow when written: the zip-up may keep more singular values
+    // than 2^min(c, n-c) at bond c (its right factor carries the MPO bond),
+    // so no static cap is used.
+    void setup() {
+        env.resize(n + 1);
+        env[0].ensure(1, s);
+        env[n].ensure(1, s);
+        HIPCHK(fill_planar<R>(env[0].re(), env[0].im(), 1, 1.0, s));
+        HIPCHK(fill_planar<R>(env[n].re(), env[n].im(), 1, 1.0, s));
+        // psi in both views
+        for (int o = 0; o < 2; ++o) {
+            psi[o].resize(n);
+            for (int j = 0; j < n; ++j) {
+                const int k = site(o, j);
+                const int64_t sz = (int64_t)st->bond[k] * 2 * st->bond[k + 1];
+                psi[o][j].ensure(sz, s);
+                const int Dl = st->orient == 0 ? st->bond[k] : st->bond[k + 1];
+                const int Dr = st->orient == 0 ? st->bond[k + 1] : st->bond[k];
+                Timer t(st, MPS_KCLASS_OTHER, 0, (8.0 + sizeof(R) * 2) * sz);
+                HIPCHK(site_to_view<R>(st->ten[k].re(), st->ten[k].im(), Dl, Dr, st->orient != o ? 1 : 0,
+                                       psi[o][j].re(), psi[o][j].im(), s));
+                t.done();
+            }
+        }
+        phi.resize(n);
+        cb.assign(n + 1, 1);
+    }
+
+    // L_j A_j W_j for view o, view-site j, into T2 ([cL][2][wM][DM]).
+    void left_block(int o, int j) {
+        const int bL = bnd(o, j), bM = bnd(o, j + 1);
+        const int64_t cL = cb[bL], wL = mpo.w[bL], wM = mpo.w[bM];
+        const int64_t DL = st->bond[bL], DM = st->bond[bM];
+        X.ensure(cL * wL * 2 * DM, s);
+        T2.ensure(cL * 2 * wM * DM, s);
+        gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_N, cL * wL, 2 * DM, DL, env[bL].re(), env[bL].im(), DL,
+                psi[o][j].re(), psi[o][j].im(), 2 * DM, X.re(), X.im(), 2 * DM);
+        const MpoSiteOp& op = mpo.view[o][j];
+        Timer t(st, MPS_KCLASS_MPO, 0, 2.0 * sizeof(R) * (cL * wL * 2 * DM + cL * 2 * wM * DM));
+        HIPCHK(mpo_apply<R>(op, cL, DM, X.re(), X.im(), T2.re(), T2.im(), s));
+        t.done();
+    }
+
+    // Store U64 (rows x k) as the phi tensor of site k0 and update the left
+    // environment of bond bM from T2: env = U^H T2 (k x (wM DM)).
+    void finish_left(int o, int j, const Trunc& tr, bool update_env) {
+        const int k0 = site(o, j);
+        const int bL = bnd(o, j), bM = bnd(o, j + 1);
+        const int64_t cL = cb[bL], wM = mpo.w[bM], DM = st->bond[bM];
+        const int64_t rows = 2 * cL;
+        phi[k0].ensure(rows * tr.k, s);
+        HIPCHK((convert_planar<double, double>(U64.re(), U64.im(), rows * tr.k, phi[k0].re(), phi[k0].im(), s)));
+        cb[bM] = tr.k;
+        if (!update_env) return;
+        env[bM].ensure(tr.k * wM * DM, s);
+        UR.ensure(rows * tr.k, s);
+        HIPCHK((convert_planar<double, R>(U64.re(), U64.im(), rows * tr.k, UR.re(), UR.im(), s)));
+        gemm<R>(st, MPS_KCLASS_CONTRACT, OP_C, OP_N, tr.k, wM * DM, rows, UR.re(), UR.im(), tr.k, T2.re(), T2.im(),
+                wM * DM, env[bM].re(), env[bM].im(), wM * DM);
+    }
+
+    double zipup(int o) {
+        double f0 = 0;
+        for (int j = 0; j < n; ++j) {
+            left_block(o, j);
+            const int bL = bnd(o, j), bM = bnd(o, j + 1);
+            const int64_t cL = cb[bL], wM = mpo.w[bM], DM = st->bond[bM];
+            if (j == n - 1) {
+                const int64_t sz = cL * 2;  // wM = DM = 1
+                HIPCHK(norm2<R>(T2.re(), T2.im(), sz, st->partial.p, st->dscal.p + 1, s));
+                HIPCHK(hipMemcpyAsync(&f0, st->dscal.p + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                if (!(f0 > 0) || !std::isfinite(f0)) fail(MPS_ERR_NUMERIC, "zip-up produced a zero or non-finite state");
+                const int k0 = site(o, j);
+                phi[k0].ensure(sz, s);
+                HIPCHK((convert_planar<R, double>(T2.re(), T2.im(), sz, phi[k0].re(), phi[k0].im(), s)));
+                set_scalar(0, 1.0 / std::sqrt(f0));
+                HIPCHK(scale_by_device_scalar<double>(phi[k0].re(), phi[k0].im(), sz, st->dscal.p, s));
+                cb[bM] = 1;
+                log_step(f0, f0, (int)cL);
+                break;
+            }
+            Trunc tr = truncate(T2.re(), T2.im(), 2 * cL, wM * DM, false, nullptr, nullptr);
+            finish_left(o, j, tr, true);
+        }
+        return f0;
+    }
+
+    double sweep(int o) {
+        double f = 0;
+        for (int j = 0; j + 1 < n; ++j) {
+            const bool last = (j + 2 == n);
+            left_block(o, j);
+            const int bL = bnd(o, j), bM = bnd(o, j + 1), bR = bnd(o, j + 2);
+            const int64_t cL = cb[bL], cR = cb[bR], wM = mpo.w[bM], wR = mpo.w[bR];
+            const int64_t DM = st->bond[bM], DR = st->bond[bR];
+            X.ensure(cL * 2 * wM * 2 * DR, s);
+            T4.ensure(cL * 4 * wR * DR, s);
+            TH.ensure(4 * cL * cR, s);
+            TH64.ensure(4 * cL * cR, s);
+            // T2 . A_{j+1}
+            gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_N, cL * 2 * wM, 2 * DR, DM, T2.re(), T2.im(), DM,
+                    psi[o][j + 1].re(), psi[o][j + 1].im(), 2 * DR, X.re(), X.im(), 2 * DR);
+            {
+                Timer t(st, MPS_KCLASS_MPO, 0, 2.0 * sizeof(R) * (cL * 2 * wM * 2 * DR + cL * 4 * wR * DR));
+                HIPCHK(mpo_apply<R>(mpo.view[o][j + 1], 2 * cL, DR, X.re(), X.im(), T4.re(), T4.im(), s));
+                t.done();
+            }
+            // Theta = T4 . R^T
+            gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_T, 4 * cL, cR, wR * DR, T4.re(), T4.im(), wR * DR,
+                    env[bR].re(), env[bR].im(), wR * DR, TH.re(), TH.im(), cR);
+            const int64_t rows = 2 * cL, cols = 2 * cR;
+            HIPCHK((convert_planar<R, double>(TH.re(), TH.im(), rows * cols, TH64.re(), TH64.im(), s)));
+            Trunc tr = truncate(TH.re(), TH.im(), rows, cols, last, TH64.re(), TH64.im());
+            f = tr.f;
+            if (f > 1.0 + 1e-3) fail(MPS_ERR_NUMERIC, "partial fidelity above 1: " + std::to_string(f));
+            finish_left(o, j, tr, !last);
+            if (last) {
+                const int k1 = site(o, j + 1);
+                phi[k1].ensure((int64_t)tr.k * cols, s);
+                HIPCHK((convert_planar<double, double>(V64.re(), V64.im(), (int64_t)tr.k * cols, phi[k1].re(),
+                                                       phi[k1].im(), s)));
+            }
+            log_step(tr.f, tr.total, tr.k);
+        }
+        return f;
+    }
+
+    void log_step(double f, double s2, int k) {
+        st->log_step_f.push_back(f);
+        st->log_step_s2.push_back(s2);
+        st->log_step_chi.push_back(k);
+    }
+
+    double run(const mps_gate* gates, int n_gates, int n_sweeps) {
+        mpo = build_layer_mpo(n, gates, n_gates);
+        setup();
+        const int oz = st->center == 0 ? 0 : 1;
+        double f = zipup(oz);
+        int last = oz;
+        if (n >= 2) {
+            int o = 1 - oz;
+            for (int sw = 0; sw < n_sweeps; ++sw) {
+                f = sweep(o);
+                last = o;
+                o = 1 - o;
+            }
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        // commit
+        for (auto& t : st->ten) t.release(s);
+        st->ten.swap(phi);
+        phi.clear();
+        st->bond = cb;
+        st->orient = last;
+        st->center = last == 0 ? n - 1 : 0;
+        st->n_2q += mpo.n_2q;
+        return f;
+    }
+};
+
+template <>
+void Engine<float>::gram_from_working(const float* m_re, const float* m_im, int dim, int64_t cols) {
+    HIPCHK(cgemm_f32in_f64(OP_N, OP_C, dim, dim, (int)cols, {m_re, m_im, cols}, {m_re, m_im, cols},
+                           {GR.re(), GR.im(), dim}, s));
+}
+template <>
+void Engine<double>::gram_from_working(const double* m_re, const double* m_im, int dim, int64_t cols) {
+    HIPCHK(cgemm_f64(OP_N, OP_C, dim, dim, (int)cols, {m_re, m_im, cols}, {m_re, m_im, cols},
+                     {GR.re(), GR.im(), dim}, s));
+}
+
+// Forward-layout FP64 copy of site k into dst ([D_k][2][D_k+1]).
+void forward_tensor(const mps_state* st, int k, Planar<double>& dst) {
+    const int64_t sz = (int64_t)st->bond[k] * 2 * st->bond[k + 1];
+    dst.ensure(sz, st->stream);
+    const int Dl = st->orient == 0 ? st->bond[k] : st->bond[k + 1];
+    const int Dr = st->orient == 0 ? st->bond[k + 1] : st->bond[k];
+    HIPCHK(site_to_view<double>(st->ten[k].re(), st->ten[k].im(), Dl, Dr, st->orient, dst.re(), dst.im(),
+                                st->stream));
+}
+
+mps_status run_guarded(const std::function<void()>& fn) {
+    try {
+        fn();
+        g_last_error.clear();
+        return MPS_OK;
+    } catch (const MpsFail& e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return MPS_ERR_DEVICE;
+    }
+}
+
+void check_state(const mps_state* st) {
+    if (!st) fail(MPS_ERR_ARG, "state is NULL");
+    if (st->invalid) fail(MPS_ERR_STATE, "state was invalidated by an earlier failure");
+}
+
+}  // namespace
+
+// ================================================================= C ABI ===
+extern "C" {
+
+const char* mps_last_error(void) { return g_last_error.c_str(); }
+
+mps_status mps_create(int n_sites, const uint8_t* init_bits, int max_chi, int precision, void* hip_stream,
+                      mps_state** out) {
+    return run_guarded([&] {
+        if (!out) fail(MPS_ERR_ARG, "out is NULL");
+        *out = nullptr;
+        if (n_sites < 1 || n_sites > 4096) fail(MPS_ERR_ARG, "n_sites must be in [1, 4096]");
+        if (max_chi < 1) fail(MPS_ERR_ARG, "max_chi must be >= 1");
+        if (precision != MPS_FP64 && precision != MPS_FP32) fail(MPS_ERR_ARG, "unknown precision");
+        if (init_bits)
+            for (int k = 0; k < n_sites; ++k)
+                if (init_bits[k] > 1) fail(MPS_ERR_ARG, "init_bits must be 0 or 1");
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(MPS_ERR_DEVICE, "no HIP device available");
+        mps_state* st = new mps_state();
+        st->n = n_sites;
+        st->max_chi = max_chi;
+        st->prec = precision;
+        st->stream = (hipStream_t)hip_stream;
+        try {
+            if (rocblas_create_handle(&st->blas) != rocblas_status_success) fail(MPS_ERR_DEVICE, "rocblas_create_handle failed");
+            rocblas_set_stream(st->blas, st->stream);
+            st->dscal.ensure(16, st->stream);
+            st->partial.ensure(1024, st->stream);
+            st->bond.assign(n_sites + 1, 1);
+            st->ten.resize(n_sites);
+            std::vector<double> host(4);
+            for (int k = 0; k < n_sites; ++k) {
+                st->ten[k].ensure(2, st->stream);
+                const int b = init_bits ? init_bits[k] : 0;
+                host[0] = b == 0 ? 1.0 : 0.0;
+                host[1] = b == 1 ? 1.0 : 0.0;
+                host[2] = host[3] = 0.0;
+                HIPCHK(hipMemcpyAsync(st->ten[k].p, host.data(), sizeof(double) * 4, hipMemcpyHostToDevice, st->stream));
+                HIPCHK(hipStreamSynchronize(st->stream));
+            }
+        } catch (...) {
+            mps_destroy(st);
+            throw;
+        }
+        *out = st;
+    });
+}
+
+mps_status mps_destroy(mps_state* st) {
+    if (!st) return MPS_OK;
+    (void)hipStreamSynchronize(st->stream);
+    for (auto& t : st->ten) t.release(st->stream);
+    st->dscal.release(st->stream);
+    st->partial.release(st->stream);
+    for (auto& p : st->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : st->event_pool) (void)hipEventDestroy(e);
+    if (st->blas) rocblas_destroy_handle(st->blas);
+    (void)hipStreamSynchronize(st->stream);
+    delete st;
+    return MPS_OK;
+}
+
+mps_status apply_layer_dmrg(mps_state* st, const mps_gate* gates, int n_gates, int chi, int n_sweeps,
+                            double* f_layer) {
+    return run_guarded([&] {
+        check_state(st);
+        if (n_gates < 0 || (n_gates > 0 && !gates)) fail(MPS_ERR_ARG, "gates is NULL");
+        if (chi < 1 || chi > st->max_chi) fail(MPS_ERR_ARG, "chi must be in [1, max_chi]");
+        if (n_sweeps < 0) fail(MPS_ERR_ARG, "n_sweeps must be >= 0");
+        // argument validation happens in the MPO build, before any device work
+        (void)build_layer_mpo(st->n, gates, n_gates);
+        const size_t log_mark = st->log_step_f.size();
+        double f = 0;
+        try {
+            if (st->prec == MPS_FP32) {
+                Engine<float> e(st, chi);
+                f = e.run(gates, n_gates, n_sweeps);
+            } else {
+                Engine<double> e(st, chi);
+                f = e.run(gates, n_gates, n_sweeps);
+            }
+            HIPCHK(hipStreamSynchronize(st->stream));
+            if (!(f > 0) || !std::isfinite(f)) fail(MPS_ERR_NUMERIC, "non-positive layer fidelity");
+        } catch (const MpsFail& e) {
+            st->invalid = true;
+            st->log_step_f.resize(log_mark);
+            st->log_step_s2.resize(log_mark);
+            st->log_step_chi.resize(log_mark);
+            (void)hipStreamSynchronize(st->stream);
+            throw;
+        }
+        flush_timings(st);
+        st->log_f += std::log(f);
+        st->n_layers += 1;
+        if (f_layer) *f_layer = f;
+    });
+}
+
+mps_status fidelity(const mps_state* st, double* F_tilde, double* log_F_tilde, int* n_layers, int64_t* n_2q) {
+    return run_guarded([&] {
+        check_state(st);
+        if (F_tilde) *F_tilde = std::exp(st->log_f);
+        if (log_F_tilde) *log_F_tilde = st->log_f;
+        if (n_layers) *n_layers = st->n_layers;
+        if (n_2q) *n_2q = st->n_2q;
+    });
+}
+
+mps_status mps_bond_dims(const mps_state* st, int* dims) {
+    return run_guarded([&] {
+        check_state(st);
+        if (!dims) fail(MPS_ERR_ARG, "dims is NULL");
+        for (int c = 0; c <= st->n; ++c) dims[c] = st->bond[c];
+    });
+}
+
+mps_status mps_get_tensor(const mps_state* st, int site, double* re_im) {
+    return run_guarded([&] {
+        check_state(st);
+        if (site < 0 || site >= st->n || !re_im) fail(MPS_ERR_ARG, "bad site or NULL output");
+        Planar<double> tmp;
+        forward_tensor(st, site, tmp);
+        const int64_t sz = (int64_t)st->bond[site] * 2 * st->bond[site + 1];
+        std::vector<double> h(2 * sz);
+        HIPCHK(hipMemcpyAsync(h.data(), tmp.p, sizeof(double) * sz, hipMemcpyDeviceToHost, st->stream));
+        HIPCHK(hipMemcpyAsync(h.data() + sz, tmp.p + tmp.cap, sizeof(double) * sz, hipMemcpyDeviceToHost, st->stream));
+        HIPCHK(hipStreamSynchronize(st->stream));
+        tmp.release(st->stream);
+        for (int64_t i = 0; i < sz; ++i) {
+            re_im[2 * i] = h[i];
+            re_im[2 * i + 1] = h[sz + i];
+        }
+    });
+}
+
+mps_status mps_step_log(const mps_state* st, double* f, double* sum_s2, int* chi_kept, int cap, int* n) {
+    return run_guarded([&] {
+        if (!st) fail(MPS_ERR_ARG, "state is NULL");
+        const int total = (int)st->log_step_f.size();
+        if (n) *n = total;
+        const int m = std::min(cap, total);
+        for (int i = 0; i < m; ++i) {
+            if (f) f[i] = st->log_step_f[i];
+            if (sum_s2) sum_s2[i] = st->log_step_s2[i];
+            if (chi_kept) chi_kept[i] = st->log_step_chi[i];
+        }
+    });
+}
+
+mps_status mps_to_statevector(const mps_state* st_c, double* re_im) {
+    return run_guarded([&] {
+        check_state(st_c);
+        mps_state* st = const_cast<mps_state*>(st_c);
+        if (!re_im) fail(MPS_ERR_ARG, "output is NULL");
+        if (st->n > 26) fail(MPS_ERR_ARG, "statevector limited to n <= 26");
+        const hipStream_t s = st->stream;
+        // rows x (2 D_{k+1}) intermediate; bonds may exceed 2^min(c, n-c) after a zip-up-only layer
+        int64_t need = (int64_t)1 << st->n;
+        for (int k = 0; k < st->n; ++k) need = std::max<int64_t>(need, ((int64_t)2 << k) * st->bond[k + 1]);
+        if (need > ((int64_t)1 << 31)) fail(MPS_ERR_ARG, "statevector intermediate too large");
+        Planar<double> v, w, a;
+        v.ensure(need, s);
+        w.ensure(need, s);
+        HIPCHK(fill_planar<double>(v.re(), v.im(), 1, 1.0, s));
+        int64_t rows = 1;
+        for (int k = 0; k < st->n; ++k) {
+            forward_tensor(st, k, a);
+            const int64_t Dk = st->bond[k], Dn = st->bond[k + 1];
+            gemm<double>(st, MPS_KCLASS_OTHER, OP_N, OP_N, rows, 2 * Dn, Dk, v.re(), v.im(), Dk, a.re(), a.im(),
+                         2 * Dn, w.re(), w.im(), 2 * Dn);
+            std::swap(v, w);
+            rows *= 2;
+        }
+        const int64_t N = (int64_t)1 << st->n;
+        std::vector<double> h(2 * N);
+        HIPCHK(hipMemcpyAsync(h.data(), v.re(), sizeof(double) * N, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h.data() + N, v.im(), sizeof(double) * N, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int64_t i = 0; i < N; ++i) {
+            re_im[2 * i] = h[i];
+            re_im[2 * i + 1] = h[N + i];
+        }
+        v.release(s); w.release(s); a.release(s);
+        flush_timings(st);
+    });
+}
+
+mps_status mps_amplitude(const mps_state* st_c, int n_strings, const uint8_t* bits, double* re_im) {
+    return run_guarded([&] {
+        check_state(st_c);
+        mps_state* st = const_cast<mps_state*>(st_c);
+        if (n_strings < 0 || (n_strings > 0 && (!bits || !re_im))) fail(MPS_ERR_ARG, "bad amplitude arguments");
+        if (n_strings == 0) return;
+        const int n = st->n;
+        for (int64_t i = 0; i < (int64_t)n_strings * n; ++i)
+            if (bits[i] > 1) fail(MPS_ERR_ARG, "bits must be 0 or 1");
+        const hipStream_t s = st->stream;
+        int maxD = 1;
+        for (int c = 0; c <= n; ++c) maxD = std::max(maxD, st->bond[c]);
+        const int64_t S = n_strings;
+        Planar<double> v, u, a;
+        v.ensure(S * maxD, s);
+        u.ensure(S * 2 * maxD, s);
+        Raw<uint8_t> bdev;
+        bdev.ensure(S, s);
+        std::vector<uint8_t> col(S);
+        HIPCHK(fill_planar<double>(v.re(), v.im(), S, 1.0, s));
+        for (int k = 0; k < n; ++k) {
+            forward_tensor(st, k, a);
+            const int64_t Dk = st->bond[k], Dn = st->bond[k + 1];
+            gemm<double>(st, MPS_KCLASS_OTHER, OP_N, OP_N, S, 2 * Dn, Dk, v.re(), v.im(), Dk, a.re(), a.im(), 2 * Dn,
+                         u.re(), u.im(), 2 * Dn);
+            for (int64_t r = 0; r < S; ++r) col[r] = bits[r * n + k];
+            HIPCHK(hipMemcpyAsync(bdev.p, col.data(), S, hipMemcpyHostToDevice, s));
+            HIPCHK(select_rows<double>(u.re(), u.im(), S, (int)Dn, 0, bdev.p, 0, 0, k, v.re(), v.im(), nullptr, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        std::vector<double> h(2 * S);
+        HIPCHK(hipMemcpyAsync(h.data(), v.re(), sizeof(double) * S, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h.data() + S, v.im(), sizeof(double) * S, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int64_t r = 0; r < S; ++r) {
+            re_im[2 * r] = h[r];
+            re_im[2 * r + 1] = h[S + r];
+        }
+        v.release(s); u.release(s); a.release(s); bdev.release(s);
+        flush_timings(st);
+    });
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename R>
+void sample_impl(mps_state* st, int64_t n_samples, uint64_t seed, uint64_t* out) {
+    const int n = st->n;
+    const hipStream_t s = st->stream;
+    const int words = (n + 63) / 64;
+    std::memset(out, 0, sizeof(uint64_t) * words * n_samples);
+    // the view whose site 0 is the orthogonality centre: tensors there are right isometries
+    const int oc = st->center == 0 ? 0 : 1;
+    int maxD = 1;
+    for (int c = 0; c <= n; ++c) maxD = std::max(maxD, st->bond[c]);
+    const int64_t chunk = std::min<int64_t>(n_samples, std::max<int64_t>(1024, (int64_t)(1 << 26) / (2 * maxD)));
+    std::vector<Planar<R>> views(n);
+    for (int j = 0; j < n; ++j) {
+        const int k = oc == 0 ? j : n - 1 - j;
+        views[j].ensure((int64_t)st->bond[k] * 2 * st->bond[k + 1], s);
+        const int Dl = st->orient == 0 ? st->bond[k] : st->bond[k + 1];
+        const int Dr = st->orient == 0 ? st->bond[k + 1] : st->bond[k];
+        HIPCHK(site_to_view<R>(st->ten[k].re(), st->ten[k].im(), Dl, Dr, st->orient != oc ? 1 : 0,
+                               views[j].re(), views[j].im(), s));
+    }
+    Planar<R> v, u;
+    v.ensure(chunk * maxD, s);
+    u.ensure(chunk * 2 * maxD, s);
+    Raw<uint8_t> bdev;
+    bdev.ensure(chunk * n, s);
+    std::vector<uint8_t> hb(chunk * n);
+    for (int64_t s0 = 0; s0 < n_samples; s0 += chunk) {
+        const int64_t S = std::min(chunk, n_samples - s0);
+        HIPCHK(fill_planar<R>(v.re(), v.im(), S, 1.0, s));
+        for (int j = 0; j < n; ++j) {
+            const int k = oc == 0 ? j : n - 1 - j;
+            const int64_t Dv = oc == 0 ? st->bond[k] : st->bond[k + 1];
+            const int64_t Dn = oc == 0 ? st->bond[k + 1] : st->bond[k];
+            gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_N, S, 2 * Dn, Dv, v.re(), v.im(), Dv, views[j].re(),
+                    views[j].im(), 2 * Dn, u.re(), u.im(), 2 * Dn);
+            Timer t(st, MPS_KCLASS_OTHER, 0, 3.0 * sizeof(R) * S * 2 * Dn);
+            HIPCHK(select_rows<R>(u.re(), u.im(), S, (int)Dn, 1, nullptr, seed, s0, k, v.re(), v.im(),
+                                  bdev.p + (int64_t)k * S, s));
+            t.done();
+        }
+        HIPCHK(hipMemcpyAsync(hb.data(), bdev.p, (size_t)S * n, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int k = 0; k < n; ++k)
+            for (int64_t r = 0; r < S; ++r)
+                if (hb[(size_t)k * S + r]) out[(s0 + r) * words + k / 64] |= (uint64_t)1 << (k % 64);
+    }
+    for (auto& vv : views) vv.release(s);
+    v.release(s); u.release(s); bdev.release(s);
+    flush_timings(st);
+}
+
+}  // namespace
+
+extern "C" {
+
+mps_status sample(mps_state* st, int64_t n_samples, uint64_t seed, uint64_t* bits) {
+    return run_guarded([&] {
+        check_state(st);
+        if (n_samples < 0 || (n_samples > 0 && !bits)) fail(MPS_ERR_ARG, "bad sample arguments");
+        if (n_samples == 0) return;
+        if (st->prec == MPS_FP32) sample_impl<float>(st, n_samples, seed, bits);
+        else sample_impl<double>(st, n_samples, seed, bits);
+    });
+}
+
+mps_status mps_expect_zz(const mps_state* st_c, int i, int j, double* value) {
+    return run_guarded([&] {
+        check_state(st_c);
+        mps_state* st = const_cast<mps_state*>(st_c);
+        if (i < 0 || j < 0 || i >= st->n || j >= st->n || !value) fail(MPS_ERR_ARG, "bad site or NULL output");
+        const hipStream_t s = st->stream;
+        int maxD = 1;
+        for (int c = 0; c <= st->n; ++c) maxD = std::max(maxD, st->bond[c]);
+        Planar<double> e, x, a, az;
+        e.ensure((int64_t)maxD * maxD, s);
+        x.ensure((int64_t)maxD * 2 * maxD, s);
+        az.ensure((int64_t)maxD * 2 * maxD, s);
+        HIPCHK(fill_planar<double>(e.re(), e.im(), 1, 1.0, s));
+        for (int k = 0; k < st->n; ++k) {
+            forward_tensor(st, k, a);
+            const int64_t Dk = st->bond[k], Dn = st->bond[k + 1];
+            gemm<double>(st, MPS_KCLASS_OTHER, OP_N, OP_N, Dk, 2 * Dn, Dk, e.re(), e.im(), Dk, a.re(), a.im(), 2 * Dn,
+                         x.re(), x.im(), 2 * Dn);
+            const double* xr = x.re();
+            const double* xi = x.im();
+            if (k == i || k == j) {
+                HIPCHK(apply_z_phys(x.re(), x.im(), (int)Dk, (int)Dn, az.re(), az.im(), s));
+                xr = az.re();
+                xi = az.im();
+            }
+            gemm<double>(st, MPS_KCLASS_OTHER, OP_C, OP_N, Dn, Dn, 2 * Dk, a.re(), a.im(), Dn, xr, xi, Dn, e.re(),
+                         e.im(), Dn);
+        }
+        double v = 0;
+        HIPCHK(hipMemcpyAsync(&v, e.re(), sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        *value = v;
+        e.release(s); x.release(s); a.release(s); az.release(s);
+        flush_timings(st);
+    });
+}
+
+mps_status mps_set_profiling(mps_state* st, int on) {
+    return run_guarded([&] {
+        if (!st) fail(MPS_ERR_ARG, "state is NULL");
+        flush_timings(st);
+        st->prof = on != 0;
+        for (auto& k : st->stats) k = KStat();
+    });
+}
+
+mps_status mps_kernel_stats(const mps_state* st, int cls, int64_t* launches, double* total_ms, double* flops,
+                            double* bytes) {
+    return run_guarded([&] {
+        if (!st) fail(MPS_ERR_ARG, "state is NULL");
+        if (cls < 0 || cls >= MPS_KCLASS_COUNT) fail(MPS_ERR_ARG, "bad kernel class");
+        const KStat& k = st->stats[cls];
+        if (launches) *launches = k.launches;
+        if (total_ms) *total_ms = k.ms;
+        if (flops) *flops = k.flops;
+        if (bytes) *bytes = k.bytes;
+    });
+}
+
+}  // extern "C"
+
+namespace {
+template <typename R>
+void selftest_cgemm_impl(int opa, int opb, int M, int N, int K, const double* a, const double* b, double* c) {
+    hipStream_t s = nullptr;
+    const int64_t na = (int64_t)M * K, nb = (int64_t)K * N, nc = (int64_t)M * N;
+    std::vector<R> ha(2 * na), hb(2 * nb), hc(2 * nc);
+    for (int64_t i = 0; i < na; ++i) { ha[i] = (R)a[2 * i]; ha[na + i] = (R)a[2 * i + 1]; }
+    for (int64_t i = 0; i < nb; ++i) { hb[i] = (R)b[2 * i]; hb[nb + i] = (R)b[2 * i + 1]; }
+    R* da = (R*)dalloc(sizeof(R) * 2 * std::max<int64_t>(na, 1), s);
+    R* db = (R*)dalloc(sizeof(R) * 2 * std::max<int64_t>(nb, 1), s);
+    R* dc = (R*)dalloc(sizeof(R) * 2 * std::max<int64_t>(nc, 1), s);
+    HIPCHK(hipMemcpyAsync(da, ha.data(), sizeof(R) * 2 * na, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(db, hb.data(), sizeof(R) * 2 * nb, hipMemcpyHostToDevice, s));
+    const int64_t lda = (opa == OP_N) ? K : M;
+    const int64_t ldb = (opb == OP_N) ? N : K;
+    HIPCHK(gemm_raw<R>(opa, opb, M, N, K, da, da + na, lda, db, db + nb, ldb, dc, dc + nc, N, s));
+    HIPCHK(hipMemcpyAsync(hc.data(), dc, sizeof(R) * 2 * nc, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    dfree(da, s); dfree(db, s); dfree(dc, s);
+    HIPCHK(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < nc; ++i) { c[2 * i] = hc[i]; c[2 * i + 1] = hc[nc + i]; }
+}
+}  // namespace
+
+extern "C" mps_status mps_kernel_selftest_cgemm(int precision, int opa, int opb, int M, int N, int K,
+                                                const double* a, const double* b, double* c) {
+    return run_guarded([&] {
+        if (M < 1 || N < 1 || K < 1 || !a || !b || !c) fail(MPS_ERR_ARG, "bad GEMM self-test arguments");
+        if (opa != OP_N && opa != OP_C) fail(MPS_ERR_ARG, "opa must be 0 (N) or 2 (C)");
+        if (opb != OP_N && opb != OP_T && opb != OP_C) fail(MPS_ERR_ARG, "opb must be 0, 1 or 2");
+        if ((int64_t)M * K > (1 << 28) || (int64_t)K * N > (1 << 28) || (int64_t)M * N > (1 << 28))
+            fail(MPS_ERR_ARG, "self-test operands too large");
+        if (precision == MPS_FP32) selftest_cgemm_impl<float>(opa, opb, M, N, K, a, b, c);
+        else if (precision == MPS_FP64) selftest_cgemm_impl<double>(opa, opb, M, N, K, a, b, c);
+        else fail(MPS_ERR_ARG, "unknown precision");
+    });
+}

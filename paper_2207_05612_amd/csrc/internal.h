@@ -1,0 +1,113 @@
+// Internal declarations shared by the HIP sources of the DMRG library.
+// Not part of the public ABI (see include/mps_dmrg.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpsk {
+
+// Operand modes of the complex GEMM C = op(A) op(B).
+//   A: OP_N = row-major M x K;  OP_C = conj-transpose of a row-major K x M.
+//   B: OP_N = row-major K x N;  OP_T = transpose of a row-major N x K;
+//      OP_C = conj-transpose of a row-major N x K.
+enum Op { OP_N = 0, OP_T = 1, OP_C = 2 };
+
+// A planar complex matrix view: re[] and im[] with row stride ld (elements).
+template <typename T>
+struct CView {
+    const T* re;
+    const T* im;
+    int64_t ld;
+};
+template <typename T>
+struct CViewMut {
+    T* re;
+    T* im;
+    int64_t ld;
+};
+
+// Complex GEMM, C (M x N) = op(A) op(B), overwriting C.
+//   TIn  element type of A and B (float or double)
+//   TAcc arithmetic / output type (float with TIn=float; double with either)
+// Returns hipSuccess or the launch error.
+hipError_t cgemm_f32(int opa, int opb, int M, int N, int K, CView<float> A, CView<float> B,
+                     CViewMut<float> C, hipStream_t stream);
+hipError_t cgemm_f64(int opa, int opb, int M, int N, int K, CView<double> A, CView<double> B,
+                     CViewMut<double> C, hipStream_t stream);
+hipError_t cgemm_f32in_f64(int opa, int opb, int M, int N, int K, CView<float> A,
+                           CView<float> B, CViewMut<double> C, hipStream_t stream);
+
+// Structured MPO application on one site.
+//   in  [P][w_in][2 (t)][Q],  out [P][2 (s)][w_out][Q]
+//   w_in = H * r_in * lo, w_out = H * r_out * lo; one of r_in, r_out is 1.
+//   out[p][s][(h r_out + a_out) lo + l][q] =
+//       sum_{a_in, t} op[a_out][a_in][s][t] in[p][(h r_in + a_in) lo + l][t][q]
+struct MpoSiteOp {
+    int r_in, r_out, lo, H;
+    double re[16], im[16];     // [(a_out * r_in + a_in) * 4 + s * 2 + t]
+};
+template <typename T>
+hipError_t mpo_apply(const MpoSiteOp& op, int64_t P, int64_t Q, const T* in_re, const T* in_im,
+                     T* out_re, T* out_im, hipStream_t stream);
+
+// Site tensor (FP64 planar, [Dl][2][Dr]) -> working copy, optionally with the
+// virtual legs swapped ([Dr][2][Dl]) and converted to T.
+template <typename T>
+hipError_t site_to_view(const double* re, const double* im, int Dl, int Dr, int swap_legs,
+                        T* out_re, T* out_im, hipStream_t stream);
+
+// Element-wise conversion of a planar array of n complex numbers.
+template <typename TI, typename TO>
+hipError_t convert_planar(const TI* re, const TI* im, int64_t n, TO* ore, TO* oim,
+                          hipStream_t stream);
+
+// Fill a planar array with (value, 0).
+template <typename T>
+hipError_t fill_planar(T* re, T* im, int64_t n, double value, hipStream_t stream);
+
+// sum |x|^2 of a planar array, deterministic two-pass reduction in FP64.
+// partial must hold at least 1024 doubles; result written to *out (device).
+template <typename T>
+hipError_t norm2(const T* re, const T* im, int64_t n, double* partial, double* out,
+                 hipStream_t stream);
+
+// Row-major planar Hermitian n x n -> interleaved column-major (LAPACK layout).
+hipError_t pack_hermitian(const double* re, const double* im, int n, double* out_z,
+                          hipStream_t stream);
+
+// From rocSOLVER's eigenvectors (interleaved, column-major, ascending
+// eigenvalues) take the k columns of the largest eigenvalues, largest first,
+// into a row-major planar n x k matrix; optionally scale column c by scale[c].
+hipError_t take_top_eigvecs(const double* evec_z, int n, int k, const double* scale_dev,
+                            double* out_re, double* out_im, hipStream_t stream);
+
+// out (k x m row-major) = diag(s) * in^H where in is m x k row-major; planar.
+hipError_t scaled_adjoint(const double* in_re, const double* in_im, int m, int k,
+                          const double* s_dev, double* out_re, double* out_im,
+                          hipStream_t stream);
+
+// Scale the columns of a planar row-major m x k matrix by s[c] (device array).
+hipError_t scale_columns(double* re, double* im, int64_t m, int k, const double* s_dev,
+                         hipStream_t stream);
+
+// Scale a planar array by a device scalar: x *= (*s).
+template <typename T>
+hipError_t scale_by_device_scalar(T* re, T* im, int64_t n, const double* s_dev,
+                                  hipStream_t stream);
+
+// Sequential-product step of sampling / amplitude evaluation.
+//   U [S][2][D] (planar); for row r choose t: given (bits_in) or sampled from
+//   p_t = ||U[r][t][:]||^2 with the Philox draw of (seed, sample0 + r, site);
+//   V_out[r][:] = U[r][t][:] (normalised when sampling).  bits_out[r] = t.
+template <typename T>
+hipError_t select_rows(const T* u_re, const T* u_im, int64_t S, int D, int sampling,
+                       const uint8_t* bits_in, uint64_t seed, int64_t sample0, int site,
+                       T* v_re, T* v_im, uint8_t* bits_out, hipStream_t stream);
+
+// Transfer-matrix step for <Z_i Z_j>: E'[b][b'] = sum_{a,a',s} conj(A[a][s][b]) w_s E[a][a'] A[a'][s][b']
+// done with two GEMMs by the caller; this applies w_s = (+1, -1) to the physical leg.
+hipError_t apply_z_phys(const double* re, const double* im, int Dl, int Dr, double* out_re,
+                        double* out_im, hipStream_t stream);
+
+}  // namespace mpsk

@@ -1,0 +1,236 @@
+"""Python binding of the C ABI in ``include/mps_dmrg.h`` (argument marshalling only).
+
+Every computation runs in the HIP library ``libmpsdmrg.so``; this module only
+converts NumPy arrays to pointers and status codes to exceptions.  Loading
+fails loudly when the library has not been built: there is no fallback.
+
+PyTorch supplies the HIP stream (``torch.cuda.current_stream()``) when it is
+importable and a GPU is visible; otherwise the default stream is used.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import circuits
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpsdmrg.so")
+
+MPS_OK, MPS_ERR_ARG, MPS_ERR_OOM, MPS_ERR_DEVICE, MPS_ERR_NUMERIC, MPS_ERR_STATE = 0, -1, -2, -3, -4, -5
+MPS_FP64, MPS_FP32 = 0, 1
+KCLASS = {"contract": 0, "mpo": 1, "gram": 2, "eigh": 3, "other": 4}
+
+# every symbol declared in include/mps_dmrg.h
+EXPORTS = ("mps_create", "mps_destroy", "apply_layer_dmrg", "fidelity", "sample", "mps_last_error",
+           "mps_amplitude", "mps_to_statevector", "mps_bond_dims", "mps_get_tensor", "mps_step_log",
+           "mps_expect_zz", "mps_set_profiling", "mps_kernel_stats", "mps_kernel_selftest_cgemm")
+
+_lib = None
+
+
+class MpsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("mps status %d: %s" % (code, msg))
+        self.code = code
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmpsdmrg.so and declare the ABI; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("HIP library %s is not built; run `python -m paper_2207_05612_amd.build`" % path)
+    try:
+        # the library shares PyTorch's HIP runtime; let PyTorch map it first
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i32, i64, u64, dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    sig = {
+        "mps_create": (i32, [i32, P, i32, i32, P, ctypes.POINTER(P)]),
+        "mps_destroy": (i32, [P]),
+        "apply_layer_dmrg": (i32, [P, P, i32, i32, i32, dp]),
+        "fidelity": (i32, [P, dp, dp, ip, ctypes.POINTER(i64)]),
+        "sample": (i32, [P, i64, u64, P]),
+        "mps_last_error": (ctypes.c_char_p, []),
+        "mps_amplitude": (i32, [P, i32, P, dp]),
+        "mps_to_statevector": (i32, [P, dp]),
+        "mps_bond_dims": (i32, [P, ip]),
+        "mps_get_tensor": (i32, [P, i32, dp]),
+        "mps_step_log": (i32, [P, dp, dp, ip, i32, ip]),
+        "mps_expect_zz": (i32, [P, i32, i32, dp]),
+        "mps_set_profiling": (i32, [P, i32]),
+        "mps_kernel_stats": (i32, [P, i32, ctypes.POINTER(i64), dp, dp, dp]),
+        "mps_kernel_selftest_cgemm": (i32, [i32, i32, i32, i32, i32, i32, dp, dp, dp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code: int) -> None:
+    if code != MPS_OK:
+        raise MpsError(code, _lib.mps_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _iptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def current_stream() -> Optional[int]:
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except ImportError:
+        pass
+    return None
+
+
+class MPS:
+    """Handle of one on-GPU MPS (owns an ``mps_state*``)."""
+
+    def __init__(self, n: int, bits: Optional[Sequence[int]] = None, max_chi: int = 1024,
+                 precision: int = MPS_FP32, stream: Optional[int] = None):
+        lib = load_library()
+        self.n = n
+        self.precision = precision
+        self._h = ctypes.c_void_p()
+        bits_arr = None if bits is None else np.ascontiguousarray(bits, dtype=np.uint8)
+        if stream is None:
+            stream = current_stream()
+        _check(lib.mps_create(n, None if bits_arr is None else bits_arr.ctypes.data, max_chi, precision,
+                              stream, ctypes.byref(self._h)))
+
+    def close(self) -> None:
+        if self._h:
+            _lib.mps_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the compression step ------------------------------------------------
+    def apply_layer_dmrg(self, layer, chi: int, n_sweeps: int) -> float:
+        rec = layer if isinstance(layer, np.ndarray) else circuits.pack_layer(layer)
+        rec = np.ascontiguousarray(rec, dtype=circuits.GATE_DTYPE)
+        f = ctypes.c_double(0.0)
+        _check(_lib.apply_layer_dmrg(self._h, rec.ctypes.data, len(rec), chi, n_sweeps, ctypes.byref(f)))
+        return f.value
+
+    def fidelity(self):
+        F, lf, nl, n2 = ctypes.c_double(), ctypes.c_double(), ctypes.c_int(), ctypes.c_int64()
+        _check(_lib.fidelity(self._h, ctypes.byref(F), ctypes.byref(lf), ctypes.byref(nl), ctypes.byref(n2)))
+        eps = 1.0 - F.value ** (1.0 / n2.value) if n2.value > 0 else 0.0
+        return {"F_tilde": F.value, "log_F_tilde": lf.value, "n_layers": nl.value,
+                "n_2q": n2.value, "eps_tilde": eps}
+
+    def sample(self, n_samples: int, seed: int) -> np.ndarray:
+        """(n_samples, n) uint8 bits."""
+        words = (self.n + 63) // 64
+        out = np.zeros((n_samples, words), dtype=np.uint64)
+        _check(_lib.sample(self._h, n_samples, seed, out.ctypes.data))
+        bits = np.zeros((n_samples, self.n), dtype=np.uint8)
+        for k in range(self.n):
+            bits[:, k] = ((out[:, k // 64] >> np.uint64(k % 64)) & np.uint64(1)).astype(np.uint8)
+        return bits
+
+    # -- inspection --------------------------------------------------------------
+    def amplitudes(self, bits: np.ndarray) -> np.ndarray:
+        b = np.ascontiguousarray(np.atleast_2d(bits), dtype=np.uint8)
+        out = np.zeros(2 * b.shape[0])
+        _check(_lib.mps_amplitude(self._h, b.shape[0], b.ctypes.data, _dptr(out)))
+        return out[0::2] + 1j * out[1::2]
+
+    def statevector(self) -> np.ndarray:
+        out = np.zeros(2 * 2 ** self.n)
+        _check(_lib.mps_to_statevector(self._h, _dptr(out)))
+        return out[0::2] + 1j * out[1::2]
+
+    def bond_dims(self):
+        out = np.zeros(self.n + 1, dtype=np.int32)
+        _check(_lib.mps_bond_dims(self._h, _iptr(out)))
+        return [int(x) for x in out]
+
+    def tensor(self, site: int) -> np.ndarray:
+        d = self.bond_dims()
+        out = np.zeros(2 * d[site] * 2 * d[site + 1])
+        _check(_lib.mps_get_tensor(self._h, site, _dptr(out)))
+        return (out[0::2] + 1j * out[1::2]).reshape(d[site], 2, d[site + 1])
+
+    def step_log(self):
+        n = ctypes.c_int()
+        _check(_lib.mps_step_log(self._h, None, None, None, 0, ctypes.byref(n)))
+        m = n.value
+        f, s2 = np.zeros(max(m, 1)), np.zeros(max(m, 1))
+        k = np.zeros(max(m, 1), dtype=np.int32)
+        _check(_lib.mps_step_log(self._h, _dptr(f), _dptr(s2), _iptr(k), m, ctypes.byref(n)))
+        return f[:m], s2[:m], k[:m]
+
+    def expect_zz(self, i: int, j: int) -> float:
+        v = ctypes.c_double()
+        _check(_lib.mps_expect_zz(self._h, i, j, ctypes.byref(v)))
+        return v.value
+
+    # -- measurement -------------------------------------------------------------
+    def set_profiling(self, on: bool) -> None:
+        _check(_lib.mps_set_profiling(self._h, 1 if on else 0))
+
+    def kernel_stats(self, cls: str):
+        n, ms, fl, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(_lib.mps_kernel_stats(self._h, KCLASS[cls], ctypes.byref(n), ctypes.byref(ms),
+                                     ctypes.byref(fl), ctypes.byref(by)))
+        return {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
+
+
+def selftest_cgemm(precision: int, opa: int, opb: int, a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """C = op(a) op(b) through the library's GEMM kernel (see mps_kernel_selftest_cgemm)."""
+    lib = load_library()
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    b = np.ascontiguousarray(b, dtype=np.complex128)
+    M, K = (a.shape[0], a.shape[1]) if opa == 0 else (a.shape[1], a.shape[0])
+    N = b.shape[1] if opb == 0 else b.shape[0]
+    c = np.zeros((M, N), dtype=np.complex128)
+    _check(lib.mps_kernel_selftest_cgemm(precision, opa, opb, M, N, K, _dptr(a.view(np.float64)),
+                                         _dptr(b.view(np.float64)), _dptr(c.view(np.float64))))
+    return c
+
+
+# free functions with the ABI's names
+def mps_create(n, bits=None, max_chi=1024, precision=MPS_FP32, stream=None) -> MPS:
+    return MPS(n, bits, max_chi, precision, stream)
+
+
+def apply_layer_dmrg(state: MPS, layer, chi: int, n_sweeps: int) -> float:
+    return state.apply_layer_dmrg(layer, chi, n_sweeps)
+
+
+def fidelity(state: MPS):
+    return state.fidelity()
+
+
+def sample(state: MPS, n_samples: int, seed: int) -> np.ndarray:
+    return state.sample(n_samples, seed)
+
+
+def mps_destroy(state: MPS) -> None:
+    state.close()

@@ -1,0 +1,235 @@
+"""GPU parity: the HIP library against the FP64 oracle, through the C ABI.
+
+Tolerances:
+  * GEMM kernel alone: |C - C_ref| <= 4 eps K max|A| max|B| (eps of the
+    working precision; operands are rounded to it first);
+  * FP64 path: per-layer f_delta within 1e-10 relative, amplitudes within
+    1e-9 relative L2, kept bond dimensions identical;
+  * FP32 path: per-layer f_delta within 1e-4 relative and amplitudes within
+    1e-5 relative L2 of the oracle (the targets of the FP32 contraction mode),
+    except where the truncated problem is ill-conditioned: there the bound is
+    4x the amplitude change that FP32 rounding of each layer's input tensors
+    alone causes in the FP64 oracle (measured by `fp32_sensitivity`).  In
+    well-conditioned cases that product is below 1e-5 and the bound stays 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2207_05612_amd import circuits, mps
+from oracle import dmrg
+from oracle import statevector as sv
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = mps.MPS_FP64, mps.MPS_FP32
+F_TOL = {FP64: 1e-10, FP32: 1e-4}
+AMP_TOL = {FP64: 1e-9, FP32: 1e-5}
+EPS = {FP64: 2.2e-16, FP32: 1.2e-7}
+
+
+def _rc(rng, *shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+GEMM_SHAPES = [(1, 1, 1), (5, 7, 3), (37, 45, 29), (64, 64, 8), (128, 128, 16), (130, 257, 70), (300, 64, 513)]
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("opa,opb", [(0, 0), (0, 1), (0, 2), (2, 0), (2, 1), (2, 2)])
+def test_cgemm_kernel_matches_numpy(prec, opa, opb):
+    rng = np.random.default_rng(100 + 10 * opa + opb)
+    for M, N, K in GEMM_SHAPES:
+        a = _rc(rng, M, K) if opa == 0 else _rc(rng, K, M)
+        b = _rc(rng, K, N) if opb == 0 else _rc(rng, N, K)
+        A = a if opa == 0 else a.conj().T
+        B = b if opb == 0 else (b.T if opb == 1 else b.conj().T)
+        want = A @ B
+        got = mps.selftest_cgemm(prec, opa, opb, a, b)
+        bound = 4 * EPS[prec] * K * np.abs(A).max() * np.abs(B).max()
+        assert np.abs(got - want).max() <= bound, (M, N, K)
+
+
+def run_gpu(circuit, chi, n_sweeps, prec, depth=None, bits=None):
+    st = mps.MPS(circuit.n, bits, max_chi=max(chi, 1), precision=prec)
+    layers = circuit.layers if depth is None else circuit.layers[:depth]
+    fs = [st.apply_layer_dmrg(layer, chi, n_sweeps) for layer in layers]
+    return st, np.array(fs)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def fp32_sensitivity(circuit, chi, n_sweeps, trials=3):
+    """Largest amplitude change of the FP64 oracle when every layer's input
+    tensors carry FP32-sized (6e-8) relative noise."""
+    ref = dmrg.to_statevector(dmrg.run_circuit(circuit, chi=chi, n_sweeps=n_sweeps))
+    worst = 0.0
+    for trial in range(trials):
+        rng = np.random.default_rng(trial)
+        st = dmrg.product_state(circuit.n)
+        for layer in circuit.layers:
+            st.tensors = [t * (1 + 6e-8 * rng.standard_normal(t.shape)) for t in st.tensors]
+            dmrg.apply_layer(st, layer, chi, n_sweeps)
+        worst = max(worst, rel_l2(dmrg.to_statevector(st), ref))
+    return worst
+
+
+def amp_tol(prec, circuit, chi, n_sweeps):
+    if prec == FP64:
+        return AMP_TOL[FP64]
+    return max(AMP_TOL[FP32], 4.0 * fp32_sensitivity(circuit, chi, n_sweeps))
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_exact_regime_plain_workload(prec):
+    """12 qubits, 3x4 grid, depth 8, chi = 64 (exact), 2 sweeps, seed 0."""
+    c = circuits.plain_fp64_workload(0)
+    st, fs = run_gpu(c, 64, 2, prec)
+    psi = sv.run(c)
+    assert rel_l2(st.statevector(), psi) < AMP_TOL[prec]
+    fid = st.fidelity()
+    assert abs(fid["F_tilde"] - 1.0) < F_TOL[prec] * 10
+    assert fid["n_2q"] == c.n_2q == 34
+    ora = dmrg.run_circuit(c, chi=64, n_sweeps=2)
+    assert st.bond_dims() == ora.bond_dims()
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("chi", [4, 8, 16])
+def test_truncated_parity_plain_workload(prec, chi):
+    c = circuits.plain_fp64_workload(1)
+    st, fs = run_gpu(c, chi, 2, prec)
+    ora = dmrg.run_circuit(c, chi=chi, n_sweeps=2)
+    of = np.array(ora.layer_f)
+    assert np.max(np.abs(fs - of) / of) < F_TOL[prec]
+    tol = amp_tol(prec, c, chi, 2)
+    if chi >= 8:
+        assert tol == AMP_TOL[prec]            # well conditioned: the plain bound applies
+    assert rel_l2(st.statevector(), dmrg.to_statevector(ora)) < tol
+    f_log, s2_log, k_log = st.step_log()
+    assert len(f_log) == len(ora.step_log)
+    ofl = np.array([r.f for r in ora.step_log])
+    assert np.max(np.abs(f_log - ofl) / ofl) < F_TOL[prec]
+    if prec == FP64:
+        assert list(k_log) == [r.chi_kept for r in ora.step_log]
+        assert st.bond_dims() == ora.bond_dims()
+    gf = st.fidelity()
+    assert abs(gf["log_F_tilde"] - ora.log_f) < F_TOL[prec] * 10 * len(c.layers)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_grid_20_qubits_truncated(prec):
+    """20 qubits on a 4x5 grid (snake width 4), Haar gates, depth 10, chi 16."""
+    c = circuits.random_circuit(circuits.grid_from_shape(5, 4), 10, seed=3)
+    st, fs = run_gpu(c, 16, 2, prec)
+    ora = dmrg.run_circuit(c, chi=16, n_sweeps=2)
+    of = np.array(ora.layer_f)
+    assert np.max(np.abs(fs - of) / of) < F_TOL[prec]
+    rng = np.random.default_rng(0)
+    bits = rng.integers(0, 2, size=(64, c.n)).astype(np.uint8)
+    amp_gpu = st.amplitudes(bits)
+    amp_ora = np.array([dmrg.amplitude(ora, b) for b in bits])
+    assert rel_l2(amp_gpu, amp_ora) < AMP_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_zero_sweeps_and_initial_bits(prec):
+    c = circuits.random_brickwork(9, 6, seed=8)
+    bits = [1, 0, 0, 1, 1, 0, 1, 0, 1]
+    st, fs = run_gpu(c, 4, 0, prec, bits=bits)
+    ora = dmrg.run_circuit(c, chi=4, n_sweeps=0, bits=bits)
+    assert np.max(np.abs(fs - np.array(ora.layer_f)) / np.array(ora.layer_f)) < F_TOL[prec]
+    assert rel_l2(st.statevector(), dmrg.to_statevector(ora)) < AMP_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_odd_sweeps_and_reversed_gates(prec):
+    """Three sweeps per layer and two-qubit gates given with q0 > q1."""
+    c = circuits.random_brickwork(8, 6, seed=9)
+    layers = [[(q1, q0, u.reshape(2, 2, 2, 2).transpose(1, 0, 3, 2).reshape(4, 4)) if q1 >= 0 else (q0, q1, u)
+               for (q0, q1, u) in layer] for layer in c.layers]
+    rc = circuits.Circuit(n=c.n, layers=layers)
+    st, fs = run_gpu(rc, 4, 3, prec)
+    ora = dmrg.run_circuit(c, chi=4, n_sweeps=3)
+    assert np.max(np.abs(fs - np.array(ora.layer_f)) / np.array(ora.layer_f)) < F_TOL[prec]
+    assert rel_l2(st.statevector(), dmrg.to_statevector(ora)) < AMP_TOL[prec]
+
+
+def test_degenerate_sizes():
+    # one site: only one-qubit gates; f = 1
+    st = mps.MPS(1, None, max_chi=4, precision=FP64)
+    f = st.apply_layer_dmrg([(0, -1, circuits.SQRT_X)], 4, 2)
+    assert abs(f - 1.0) < 1e-14
+    assert np.allclose(st.statevector(), circuits.SQRT_X[:, 0], atol=1e-14)
+    # an empty layer is the identity
+    st2 = mps.MPS(5, [1, 0, 1, 1, 0], max_chi=4, precision=FP64)
+    assert abs(st2.apply_layer_dmrg([], 4, 2) - 1.0) < 1e-14
+    psi = sv.zero_state(5, [1, 0, 1, 1, 0])
+    assert rel_l2(st2.statevector(), psi) < 1e-14
+    # two sites, one Haar gate, chi = 1 truncates to the largest Schmidt value
+    u = circuits.haar_unitary_from_normals(np.random.default_rng(4).standard_normal(32))
+    st3 = mps.MPS(2, None, max_chi=2, precision=FP64)
+    f3 = st3.apply_layer_dmrg([(0, 1, u)], 1, 2)
+    s = np.linalg.svd(u[:, 0].reshape(2, 2), compute_uv=False)
+    assert abs(f3 - s[0] ** 2) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_sampler_matches_oracle_bitstrings(prec):
+    c = circuits.random_brickwork(10, 6, seed=12)
+    st, _ = run_gpu(c, 8, 2, prec)
+    ora = dmrg.run_circuit(c, chi=8, n_sweeps=2)
+    n_s = 400
+    got = st.sample(n_s, seed=2024)
+    want = dmrg.sample(ora, n_s, seed=2024)
+    same = np.mean(np.all(got == want, axis=1))
+    assert same >= (0.995 if prec == FP64 else 0.98)
+
+
+def test_sampler_born_rule_gpu():
+    c = circuits.random_brickwork(6, 6, seed=21)
+    st, _ = run_gpu(c, 4, 1, FP32)
+    probs = np.abs(st.statevector()) ** 2
+    ns = 200000
+    bits = st.sample(ns, seed=5)
+    idx = bits.astype(np.int64) @ (1 << np.arange(5, -1, -1))
+    counts = np.bincount(idx, minlength=64)
+    expect = probs * ns
+    mask = expect > 5
+    chi2 = float(np.sum((counts[mask] - expect[mask]) ** 2 / expect[mask]))
+    dof = int(mask.sum()) - 1
+    assert chi2 < dof + 6 * math.sqrt(2 * dof)
+
+
+def test_expect_zz_matches_oracle():
+    c = circuits.random_brickwork(8, 5, seed=13)
+    st, _ = run_gpu(c, 8, 2, FP64)
+    ora = dmrg.run_circuit(c, chi=8, n_sweeps=2)
+    for i, j in [(0, 1), (2, 5), (3, 3), (7, 0)]:
+        assert abs(st.expect_zz(i, j) - dmrg.expectation_zz(ora, min(i, j), max(i, j))) < 1e-10
+
+
+def test_argument_errors_leave_state_usable():
+    c = circuits.random_brickwork(6, 3, seed=1)
+    st = mps.MPS(6, None, max_chi=8, precision=FP64)
+    with pytest.raises(mps.MpsError) as e:
+        st.apply_layer_dmrg(c.layers[0], 16, 2)             # chi > max_chi
+    assert e.value.code == mps.MPS_ERR_ARG
+    with pytest.raises(mps.MpsError) as e:
+        st.apply_layer_dmrg([(0, 1, np.eye(4)), (1, 2, np.eye(4))], 4, 2)   # overlapping
+    assert e.value.code == mps.MPS_ERR_ARG
+    with pytest.raises(mps.MpsError) as e:
+        st.apply_layer_dmrg([(0, 9, np.eye(4))], 4, 2)        # site out of range
+    assert e.value.code == mps.MPS_ERR_ARG
+    bad = circuits.pack_layer([(0, 1, np.eye(4))])
+    bad[0]["m"][0] = np.nan
+    with pytest.raises(mps.MpsError) as e:
+        st.apply_layer_dmrg(bad, 4, 2)
+    assert e.value.code == mps.MPS_ERR_ARG
+    for layer in c.layers:
+        st.apply_layer_dmrg(layer, 8, 2)
+    ora = dmrg.run_circuit(c, chi=8, n_sweeps=2)
+    assert rel_l2(st.statevector(), dmrg.to_statevector(ora)) < 1e-9
