@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark: gate-layers/s of the DMRG compression step at chi = 1024 on one GPU.
+
+Workload: 54 qubits on a 6x9 grid read in snake order along its width 6,
+random one-qubit gates from {sqrt(X), sqrt(Y), sqrt(W)} and fSim(theta, phi)
+two-qubit gates (theta ~ U(0, pi/2), phi ~ U(0, pi)) on the coupler patterns
+ABCDCDAB, depth 20, seed 0 (synthetic, generated in-process).  One step is one
+``apply_layer_dmrg`` call (zip-up + n_sweeps two-site sweeps of one layer).
+The first ``--warmup`` layers bring the bond dimension to chi and are not
+timed; the next ``--steps`` layers are timed between two device
+synchronisations.  All inputs are resident on the GPU when timing starts (the
+gate list of a layer is a few KiB and is copied inside the call).
+
+Prints one JSON line.  ``roofline`` describes the complex-GEMM contraction
+kernels (the dominant kernels of this library): algorithmic flops (8 per
+complex multiply-add) over the summed launch durations measured with HIP
+events on the library's stream.  ``cpu_baseline`` times the FP64 oracle on a
+bounded sample (see ``cpu_baseline()``).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32": 157.3, "fp64": 78.6}          # dense MFMA TFLOP/s, MI355X
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cgemm_54q_chi1024.json")
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=4)
+    p.add_argument("--warmup", type=int, default=4)
+    p.add_argument("--chi", type=int, default=1024)
+    p.add_argument("--sweeps", type=int, default=2)
+    p.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
+    p.add_argument("--seed", type=int, default=0)
+    p.add_argument("--compare-fp64", type=int, default=1,
+                   help="also time the same layers with FP64 contractions (1 = yes)")
+    p.add_argument("--cpu-baseline", type=int, default=1)
+    p.add_argument("--progress", action="store_true", help="print one line per layer to stderr")
+    p.add_argument("--calibrate-copy-mib", type=int, default=0,
+                   help="launch a plain device copy of this many MiB (HBM counter calibration)")
+    return p.parse_args()
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("cgemm.hip",):
+        with open(os.path.join(ROOT, "paper_2207_05612_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def run_layers(mps, circuit, precision, chi, sweeps, warmup, steps, torch, progress=False):
+    st = mps.MPS(circuit.n, None, max_chi=chi, precision=precision)
+    for d in range(warmup):
+        f = st.apply_layer_dmrg(circuit.layers[d], chi, sweeps)
+        if progress:
+            print("warmup layer %d f=%.6f" % (d, f), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    st.set_profiling(True)
+    fs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d in range(warmup, warmup + steps):
+        fs.append(st.apply_layer_dmrg(circuit.layers[d], chi, sweeps))
+        if progress:
+            print("timed layer %d f=%.6f" % (d, fs[-1]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = {k: st.kernel_stats(k) for k in ("contract", "mpo", "gram", "eigh", "other")}
+    bonds = st.bond_dims()
+    fid = st.fidelity()
+    st.close()
+    return dt, fs, stats, bonds, fid
+
+
+def cpu_baseline(chi: int, sweeps: int, stats_per_layer_flops: float, n_steps_per_layer: int):
+    """Time the FP64 oracle on a bounded sample of the chi = 1024 workload.
+
+    Sample: one two-site update of the oracle (local tensor, truncated SVD and
+    environment update) at the workload's chi = 1024 with MPO bonds w = 4
+    (an A/B-layer cut), on random inputs of those shapes.  The time per layer
+    is extrapolated as (steps per layer) x (SVD time) + (contraction flops of
+    the GPU's measured layers) / (oracle contraction rate), and reported in
+    gate-layers/s.
+    """
+    import numpy as np
+    from oracle import dmrg
+    rng = np.random.default_rng(0)
+
+    def rc(*shape):
+        return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(np.prod(shape[1:]))
+
+    w = 4
+    lenv, renv = rc(chi, 1, chi), rc(chi, w, chi)
+    a1, a2 = rc(chi, 2, chi), rc(chi, 2, chi)
+    w1, w2 = rc(1, 2, 2, w), rc(w, 2, 2, w)
+    t0 = time.perf_counter()
+    th = dmrg.two_site_tensor(lenv, a1, w1, a2, w2, renv)
+    t1 = time.perf_counter()
+    u, s, vh, total = dmrg.truncated_svd(th.reshape(2 * chi, 2 * chi), chi)
+    t2 = time.perf_counter()
+    b = u.reshape(chi, 2, -1)
+    dmrg.env_left_step(lenv, a1, w1, b)
+    t3 = time.perf_counter()
+    flops_contract = 8.0 * (chi * 1 * chi * 2 * chi + chi * 2 * w * chi * 2 * chi + 4 * chi * w * chi * chi
+                            + chi * 2 * chi * w * chi) + 8.0 * 4 * chi * chi * w * w
+    rate = flops_contract / ((t1 - t0) + (t3 - t2))
+    t_svd = t2 - t1
+    t_layer = n_steps_per_layer * t_svd + stats_per_layer_flops / rate
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    return {"value": 1.0 / t_layer, "unit": "gate-layers/s", "cores": min(cores, threads), "kind": "oracle",
+            "sample": "one oracle two-site update (local tensor + zgesdd truncation + environment update) at "
+                      "chi=%d, MPO bond 4, random inputs: %.1f s (SVD %.1f s, contraction %.1f GFLOP/s); "
+                      "per-layer time extrapolated from %d updates per layer and the GPU run's algorithmic "
+                      "contraction flops per layer" % (chi, t3 - t0, t_svd, rate / 1e9, n_steps_per_layer)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: the compression step has no multi-GPU path in this build "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_2207_05612_amd import circuits, mps
+    if not os.path.exists(mps.LIB_PATH):
+        from paper_2207_05612_amd import build as _b
+        _b.build()
+    mps.load_library()
+
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    c = circuits.sycamore_like_54_workload(args.seed, depth=20)
+    if args.warmup + args.steps > len(c.layers):
+        raise SystemExit("warmup + steps must not exceed the circuit depth (20)")
+    prec = mps.MPS_FP32 if args.precision == "fp32" else mps.MPS_FP64
+    dt, fs, stats, bonds, fid = run_layers(mps, c, prec, args.chi, args.sweeps, args.warmup, args.steps, torch,
+                                           args.progress)
+    value = args.steps / dt
+    con = stats["contract"]
+    achieved = con["flops"] / (con["ms"] * 1e-3) / 1e12 if con["ms"] > 0 else 0.0
+    peak = PEAK[args.precision]
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        rec = json.load(open(TRAFFIC_FILE))
+        if rec.get("source_hash") == source_hash() and rec.get("precision") == args.precision:
+            traffic = rec.get("bytes_per_launch")
+    total_flops = sum(v["flops"] for v in stats.values())
+
+    out = {
+        "metric": "gate-layers/s & TFLOP/s at chi=1024, split-FP32 vs FP64 on 1 GPU, equal fidelity",
+        "value": value,
+        "unit": "gate-layers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "54-qubit 6x9 snake, fSim + random 1q gates, depth 20, seed %d; layers %d..%d timed"
+                               % (args.seed, args.warmup, args.warmup + args.steps - 1),
+                   "chi": args.chi, "n_sweeps": args.sweeps, "contraction_precision": args.precision,
+                   "truncation_precision": "fp64", "max_bond": max(bonds)},
+        "contraction_tflops": achieved,
+        "all_kernels_algorithmic_tflops": total_flops / dt / 1e12,
+        "time_split_ms": {k: round(v["ms"], 1) for k, v in stats.items()},
+        "f_delta": fs,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic,
+                     "kernel": "cgemm_kernel<%s> (complex planar GEMM, %d launches, %.1f ms)"
+                               % (args.precision, con["launches"], con["ms"])},
+    }
+    if args.compare_fp64 and args.precision == "fp32":
+        dt64, fs64, stats64, _, _ = run_layers(mps, c, mps.MPS_FP64, args.chi, args.sweeps, args.warmup,
+                                               args.steps, torch, args.progress)
+        c64 = stats64["contract"]
+        out["fp64_path"] = {"value": args.steps / dt64, "unit": "gate-layers/s",
+                            "contraction_tflops": c64["flops"] / (c64["ms"] * 1e-3) / 1e12,
+                            "time_split_ms": {k: round(v["ms"], 1) for k, v in stats64.items()},
+                            "f_delta": fs64}
+        out["speedup_vs_fp64"] = value / (args.steps / dt64)
+        out["max_rel_f_delta_diff_vs_fp64"] = max(abs(a - b) / b for a, b in zip(fs, fs64))
+    if args.cpu_baseline:
+        layer_flops = con["flops"] / args.steps
+        out["cpu_baseline"] = cpu_baseline(args.chi, args.sweeps, layer_flops, (c.n - 1) * (1 + args.sweeps))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
