@@ -105,6 +105,23 @@ mps_status mps_destroy(mps_state* state);
 mps_status apply_layer_dmrg(mps_state* state, const mps_gate* gates, int n_gates,
                             int chi, int n_sweeps, double* f_layer);
 
+/* Apply one layer to each of `batch` independent states (the compression
+ * step above, per instance), concurrently: instances are driven by up to 8
+ * host threads and run on their own streams, so give every state its own
+ * stream in mps_create for the work to overlap (states sharing a stream are
+ * still correct, only serialised).
+ *   states   batch distinct state handles.
+ *   gates    batch host pointers; gates[i] holds n_gates[i] records.
+ *   chi      batch bond dimensions, 1 <= chi[i] <= max_chi of state i.
+ *   f_layers batch outputs (may be NULL): f_delta of each instance.
+ * Arguments of all instances are checked before any device work
+ * (MPS_ERR_ARG leaves every state unchanged).  If an instance fails, the
+ * first failing instance's status is returned with its message; that state
+ * is invalid, the others have completed their layer. */
+mps_status apply_layer_dmrg_batched(mps_state* const* states, int batch,
+                                    const mps_gate* const* gates, const int* n_gates,
+                                    const int* chi, int n_sweeps, double* f_layers);
+
 /* The fidelity estimate F~ = prod_delta f_delta (eq:Ftilde-sup), its natural
  * logarithm, the number of layers applied and the number of two-qubit gates
  * N_2g applied; the error per gate is eps~ = 1 - F~^(1/N_2g).  Any output

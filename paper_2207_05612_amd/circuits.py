@@ -291,3 +291,83 @@ def bits_to_index(bits: Sequence[int]) -> int:
     for b in bits:
         x = (x << 1) | int(b)
     return x
+
+
+# ----------------------------------------------------------------- QAOA ----
+HADAMARD = np.array([[1, 1], [1, -1]], dtype=np.complex128) / np.sqrt(2.0)
+
+
+def random_regular_graph(n: int, degree: int, seed: int, max_tries: int = 10000):
+    """Random d-regular simple graph by the pairing (configuration) model with rejection."""
+    if (n * degree) % 2:
+        raise ValueError("n * degree must be even")
+    rng = np.random.default_rng(seed)
+    for _ in range(max_tries):
+        stubs = np.repeat(np.arange(n), degree)
+        rng.shuffle(stubs)
+        pairs = stubs.reshape(-1, 2)
+        edges = set()
+        ok = True
+        for a, b in pairs:
+            a, b = int(a), int(b)
+            if a == b or (min(a, b), max(a, b)) in edges:
+                ok = False
+                break
+            edges.add((min(a, b), max(a, b)))
+        if ok:
+            return sorted(edges)
+    raise RuntimeError("no simple regular graph found")
+
+
+@dataclasses.dataclass
+class QaoaCircuit:
+    circuit: Circuit
+    edges: List[Tuple[int, int]]
+    final_position: List[int]      # chain site holding logical qubit q at the end
+
+
+def qaoa_maxcut_swap_network(n: int, edges, gammas: Sequence[float], betas: Sequence[float]) -> QaoaCircuit:
+    """QAOA MaxCut U = prod_k U_B(beta_k) U_C(gamma_k) on a chain (Sec. V.A, sequence III).
+
+    U_C(gamma) = prod_E exp(-i gamma Z_u Z_v) is routed by a full odd-even
+    transposition (SWAP) network of n brick layers: every pair of logical
+    qubits is adjacent exactly once, and where the pair is a graph edge the
+    SWAP is fused with exp(-i gamma ZZ).  The network reverses the logical
+    order; the next cost layer runs on the reversed order.  U_B(beta) =
+    prod exp(-i beta X) = RX(2 beta) on every qubit, placed as one-qubit gates
+    of the next brick layer (or of a final one-qubit layer).  The initial
+    |+>^n is prepared by Hadamards in the first layer.
+    """
+    edge_set = {(min(a, b), max(a, b)) for a, b in edges}
+    pos_of = list(range(n))        # logical -> site
+    at = list(range(n))            # site -> logical
+    layers: List[List[Gate]] = []
+    pending_1q = {s: HADAMARD for s in range(n)}
+    for gamma, beta in zip(gammas, betas):
+        zz_swap = SWAP @ zz_phase(gamma)
+        for d in range(n):
+            layer: List[Gate] = [(s, -1, u) for s, u in sorted(pending_1q.items())]
+            pending_1q = {}
+            for i in range(d % 2, n - 1, 2):
+                a, b = at[i], at[i + 1]
+                u = zz_swap if (min(a, b), max(a, b)) in edge_set else SWAP
+                layer.append((i, i + 1, u))
+                at[i], at[i + 1] = b, a
+                pos_of[a], pos_of[b] = i + 1, i
+            layers.append(layer)
+        mixer = rx(2.0 * beta)
+        pending_1q = {s: mixer for s in range(n)}
+    layers.append([(s, -1, u) for s, u in sorted(pending_1q.items())])
+    return QaoaCircuit(circuit=Circuit(n=n, layers=layers, label="qaoa_n%d_p%d" % (n, len(gammas))),
+                       edges=sorted(edge_set), final_position=pos_of)
+
+
+def qaoa_parameter_sets(count: int, p: int, seed: int = 0):
+    """(gamma, beta) sets: gamma ~ U[0, pi], beta ~ U[0, pi/2], one pair per QAOA layer."""
+    rng = np.random.default_rng(seed)
+    return [(rng.uniform(0, np.pi, p), rng.uniform(0, np.pi / 2, p)) for _ in range(count)]
+
+
+def maxcut_expectation_from_zz(edges, final_position, zz) -> float:
+    """<C> = sum_E (1 - <Z_u Z_v>)/2, zz(i, j) giving <Z_i Z_j> on chain sites."""
+    return float(sum(0.5 * (1.0 - zz(final_position[u], final_position[v])) for u, v in edges))

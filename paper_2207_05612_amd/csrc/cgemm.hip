@@ -60,6 +60,7 @@ struct GemmArgs {
     int64_t lda, ldb, ldc;
     int M, N, K;
     int gm, gn;
+    int lower_only;   // skip tiles that hold no element with column <= row
 };
 
 template <typename TIn, typename TAcc, int OPA, int OPB, int BM, int BN, int BK>
@@ -93,6 +94,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
     const int tm = first_m + (pid % gsz);
     const int tn = (pid % (GROUP * g.gn)) / gsz;
     const int m0 = tm * BM, n0 = tn * BN;
+    if (g.lower_only && n0 > m0 + BM - 1) return;   // whole tile above the diagonal (uniform per block)
 
     const int M = g.M, N = g.N, K = g.K;
 
@@ -227,7 +229,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
 
 template <typename TIn, typename TAcc, int BM, int BN, int BK>
 static hipError_t launch(int opa, int opb, int M, int N, int K, CView<TIn> A, CView<TIn> B,
-                         CViewMut<TAcc> C, hipStream_t stream) {
+                         CViewMut<TAcc> C, hipStream_t stream, int lower_only = 0) {
     if (M <= 0 || N <= 0) return hipSuccess;
     GemmArgs<TIn, TAcc> g;
     g.a_re = A.re; g.a_im = A.im; g.lda = A.ld;
@@ -236,6 +238,7 @@ static hipError_t launch(int opa, int opb, int M, int N, int K, CView<TIn> A, CV
     g.M = M; g.N = N; g.K = K;
     g.gm = (M + BM - 1) / BM;
     g.gn = (N + BN - 1) / BN;
+    g.lower_only = lower_only;
     const int64_t nblocks = (int64_t)g.gm * g.gn;
     if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
     dim3 grid((unsigned)nblocks), block(256);
@@ -260,13 +263,13 @@ hipError_t cgemm_f32(int opa, int opb, int M, int N, int K, CView<float> A, CVie
 }
 
 hipError_t cgemm_f64(int opa, int opb, int M, int N, int K, CView<double> A, CView<double> B,
-                     CViewMut<double> C, hipStream_t stream) {
-    return launch<double, double, 128, 64, 8>(opa, opb, M, N, K, A, B, C, stream);
+                     CViewMut<double> C, hipStream_t stream, int lower_only) {
+    return launch<double, double, 128, 64, 8>(opa, opb, M, N, K, A, B, C, stream, lower_only);
 }
 
 hipError_t cgemm_f32in_f64(int opa, int opb, int M, int N, int K, CView<float> A,
-                           CView<float> B, CViewMut<double> C, hipStream_t stream) {
-    return launch<float, double, 128, 64, 8>(opa, opb, M, N, K, A, B, C, stream);
+                           CView<float> B, CViewMut<double> C, hipStream_t stream, int lower_only) {
+    return launch<float, double, 128, 64, 8>(opa, opb, M, N, K, A, B, C, stream, lower_only);
 }
 
 }  // namespace mpsk

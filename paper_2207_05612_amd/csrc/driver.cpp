@@ -26,6 +26,8 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <array>
 #include <functional>
 #include <cmath>
@@ -529,10 +531,11 @@ struct Engine {
             const int dim = (int)rows;
             GR.ensure((int64_t)dim * dim, s);
             {
-                Timer t(st, MPS_KCLASS_GRAM, 8.0 * rows * rows * cols, 2.0 * sizeof(R) * rows * cols + 16.0 * rows * rows);
+                // Hermitian product: rows (rows + 1) / 2 distinct entries of cols MACs each
+                Timer t(st, MPS_KCLASS_GRAM, 4.0 * rows * (rows + 1) * cols, 2.0 * sizeof(R) * rows * cols + 8.0 * rows * (rows + 1));
                 if (m64_re) {
                     HIPCHK(cgemm_f64(OP_N, OP_C, dim, dim, (int)cols, {m64_re, m64_im, cols}, {m64_re, m64_im, cols},
-                                     {GR.re(), GR.im(), dim}, s));
+                                     {GR.re(), GR.im(), dim}, s, 1));
                 } else {
                     gram_from_working(m_re, m_im, dim, cols);
                 }
@@ -563,9 +566,9 @@ struct Engine {
         }
         GR.ensure((int64_t)dim * dim, s);
         {
-            Timer t(st, MPS_KCLASS_GRAM, 8.0 * cols * cols * rows, 16.0 * (rows * cols + cols * cols));
+            Timer t(st, MPS_KCLASS_GRAM, 4.0 * cols * (cols + 1) * rows, 16.0 * rows * cols + 8.0 * cols * (cols + 1));
             HIPCHK(cgemm_f64(OP_C, OP_N, dim, dim, (int)rows, {m64_re, m64_im, cols}, {m64_re, m64_im, cols},
-                             {GR.re(), GR.im(), dim}, s));
+                             {GR.re(), GR.im(), dim}, s, 1));
             t.done();
         }
         eigh(dim);
@@ -770,12 +773,12 @@ struct Engine {
 template <>
 void Engine<float>::gram_from_working(const float* m_re, const float* m_im, int dim, int64_t cols) {
     HIPCHK(cgemm_f32in_f64(OP_N, OP_C, dim, dim, (int)cols, {m_re, m_im, cols}, {m_re, m_im, cols},
-                           {GR.re(), GR.im(), dim}, s));
+                           {GR.re(), GR.im(), dim}, s, 1));
 }
 template <>
 void Engine<double>::gram_from_working(const double* m_re, const double* m_im, int dim, int64_t cols) {
     HIPCHK(cgemm_f64(OP_N, OP_C, dim, dim, (int)cols, {m_re, m_im, cols}, {m_re, m_im, cols},
-                     {GR.re(), GR.im(), dim}, s));
+                     {GR.re(), GR.im(), dim}, s, 1));
 }
 
 // Forward-layout FP64 copy of site k into dst ([D_k][2][D_k+1]).
@@ -805,6 +808,40 @@ mps_status run_guarded(const std::function<void()>& fn) {
 void check_state(const mps_state* st) {
     if (!st) fail(MPS_ERR_ARG, "state is NULL");
     if (st->invalid) fail(MPS_ERR_STATE, "state was invalidated by an earlier failure");
+}
+
+
+void apply_layer_impl(mps_state* st, const mps_gate* gates, int n_gates, int chi, int n_sweeps, double* f_layer) {
+    check_state(st);
+    if (n_gates < 0 || (n_gates > 0 && !gates)) fail(MPS_ERR_ARG, "gates is NULL");
+    if (chi < 1 || chi > st->max_chi) fail(MPS_ERR_ARG, "chi must be in [1, max_chi]");
+    if (n_sweeps < 0) fail(MPS_ERR_ARG, "n_sweeps must be >= 0");
+    // argument validation happens in the MPO build, before any device work
+    (void)build_layer_mpo(st->n, gates, n_gates);
+    const size_t log_mark = st->log_step_f.size();
+    double f = 0;
+    try {
+        if (st->prec == MPS_FP32) {
+            Engine<float> e(st, chi);
+            f = e.run(gates, n_gates, n_sweeps);
+        } else {
+            Engine<double> e(st, chi);
+            f = e.run(gates, n_gates, n_sweeps);
+        }
+        HIPCHK(hipStreamSynchronize(st->stream));
+        if (!(f > 0) || !std::isfinite(f)) fail(MPS_ERR_NUMERIC, "non-positive layer fidelity");
+    } catch (const MpsFail& e) {
+        st->invalid = true;
+        st->log_step_f.resize(log_mark);
+        st->log_step_s2.resize(log_mark);
+        st->log_step_chi.resize(log_mark);
+        (void)hipStreamSynchronize(st->stream);
+        throw;
+    }
+    flush_timings(st);
+    st->log_f += std::log(f);
+    st->n_layers += 1;
+    if (f_layer) *f_layer = f;
 }
 
 }  // namespace
@@ -876,37 +913,46 @@ mps_status mps_destroy(mps_state* st) {
 
 mps_status apply_layer_dmrg(mps_state* st, const mps_gate* gates, int n_gates, int chi, int n_sweeps,
                             double* f_layer) {
+    return run_guarded([&] { apply_layer_impl(st, gates, n_gates, chi, n_sweeps, f_layer); });
+}
+
+mps_status apply_layer_dmrg_batched(mps_state* const* states, int batch, const mps_gate* const* gates,
+                                    const int* n_gates, const int* chi, int n_sweeps, double* f_layers) {
     return run_guarded([&] {
-        check_state(st);
-        if (n_gates < 0 || (n_gates > 0 && !gates)) fail(MPS_ERR_ARG, "gates is NULL");
-        if (chi < 1 || chi > st->max_chi) fail(MPS_ERR_ARG, "chi must be in [1, max_chi]");
-        if (n_sweeps < 0) fail(MPS_ERR_ARG, "n_sweeps must be >= 0");
-        // argument validation happens in the MPO build, before any device work
-        (void)build_layer_mpo(st->n, gates, n_gates);
-        const size_t log_mark = st->log_step_f.size();
-        double f = 0;
-        try {
-            if (st->prec == MPS_FP32) {
-                Engine<float> e(st, chi);
-                f = e.run(gates, n_gates, n_sweeps);
-            } else {
-                Engine<double> e(st, chi);
-                f = e.run(gates, n_gates, n_sweeps);
-            }
-            HIPCHK(hipStreamSynchronize(st->stream));
-            if (!(f > 0) || !std::isfinite(f)) fail(MPS_ERR_NUMERIC, "non-positive layer fidelity");
-        } catch (const MpsFail& e) {
-            st->invalid = true;
-            st->log_step_f.resize(log_mark);
-            st->log_step_s2.resize(log_mark);
-            st->log_step_chi.resize(log_mark);
-            (void)hipStreamSynchronize(st->stream);
-            throw;
+        if (batch < 0) fail(MPS_ERR_ARG, "batch must be >= 0");
+        if (batch == 0) return;
+        if (!states || !gates || !n_gates || !chi) fail(MPS_ERR_ARG, "NULL batched argument");
+        for (int i = 0; i < batch; ++i) {
+            if (!states[i]) fail(MPS_ERR_ARG, "states[" + std::to_string(i) + "] is NULL");
+            for (int j = 0; j < i; ++j)
+                if (states[j] == states[i]) fail(MPS_ERR_ARG, "a state appears twice in the batch");
         }
-        flush_timings(st);
-        st->log_f += std::log(f);
-        st->n_layers += 1;
-        if (f_layer) *f_layer = f;
+        // argument checks of every instance before any device work
+        for (int i = 0; i < batch; ++i) {
+            check_state(states[i]);
+            if (n_gates[i] < 0 || (n_gates[i] > 0 && !gates[i])) fail(MPS_ERR_ARG, "bad gates of instance " + std::to_string(i));
+            if (chi[i] < 1 || chi[i] > states[i]->max_chi) fail(MPS_ERR_ARG, "bad chi of instance " + std::to_string(i));
+            (void)build_layer_mpo(states[i]->n, gates[i], n_gates[i]);
+        }
+        if (n_sweeps < 0) fail(MPS_ERR_ARG, "n_sweeps must be >= 0");
+        // one host thread per concurrently driven instance; each instance runs on its own stream
+        const int n_threads = std::max(1, std::min(batch, 8));
+        std::vector<mps_status> status(batch, MPS_OK);
+        std::vector<std::string> msg(batch);
+        std::vector<std::thread> pool;
+        std::atomic<int> next(0);
+        for (int t = 0; t < n_threads; ++t)
+            pool.emplace_back([&] {
+                for (int i = next.fetch_add(1); i < batch; i = next.fetch_add(1)) {
+                    double f = 0;
+                    status[i] = run_guarded([&] { apply_layer_impl(states[i], gates[i], n_gates[i], chi[i], n_sweeps, &f); });
+                    if (status[i] != MPS_OK) msg[i] = g_last_error;
+                    if (f_layers) f_layers[i] = f;
+                }
+            });
+        for (auto& th : pool) th.join();
+        for (int i = 0; i < batch; ++i)
+            if (status[i] != MPS_OK) fail(status[i], "instance " + std::to_string(i) + ": " + msg[i]);
     });
 }
 

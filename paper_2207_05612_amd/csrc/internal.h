@@ -30,13 +30,15 @@ struct CViewMut {
 // Complex GEMM, C (M x N) = op(A) op(B), overwriting C.
 //   TIn  element type of A and B (float or double)
 //   TAcc arithmetic / output type (float with TIn=float; double with either)
+// lower_only: only tiles holding elements with column <= row are computed
+// (for Hermitian products whose consumer reads the lower triangle only).
 // Returns hipSuccess or the launch error.
 hipError_t cgemm_f32(int opa, int opb, int M, int N, int K, CView<float> A, CView<float> B,
                      CViewMut<float> C, hipStream_t stream);
 hipError_t cgemm_f64(int opa, int opb, int M, int N, int K, CView<double> A, CView<double> B,
-                     CViewMut<double> C, hipStream_t stream);
+                     CViewMut<double> C, hipStream_t stream, int lower_only = 0);
 hipError_t cgemm_f32in_f64(int opa, int opb, int M, int N, int K, CView<float> A,
-                           CView<float> B, CViewMut<double> C, hipStream_t stream);
+                           CView<float> B, CViewMut<double> C, hipStream_t stream, int lower_only = 0);
 
 // Structured MPO application on one site.
 //   in  [P][w_in][2 (t)][Q],  out [P][2 (s)][w_out][Q]
@@ -73,6 +75,8 @@ hipError_t norm2(const T* re, const T* im, int64_t n, double* partial, double* o
                  hipStream_t stream);
 
 // Row-major planar Hermitian n x n -> interleaved column-major (LAPACK layout).
+// Only the row-major lower triangle is meaningful on input; it becomes the
+// column-major upper triangle, which is what the eigensolver reads.
 hipError_t pack_hermitian(const double* re, const double* im, int n, double* out_z,
                           hipStream_t stream);
 

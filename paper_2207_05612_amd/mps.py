@@ -25,7 +25,8 @@ MPS_FP64, MPS_FP32 = 0, 1
 KCLASS = {"contract": 0, "mpo": 1, "gram": 2, "eigh": 3, "other": 4}
 
 # every symbol declared in include/mps_dmrg.h
-EXPORTS = ("mps_create", "mps_destroy", "apply_layer_dmrg", "fidelity", "sample", "mps_last_error",
+EXPORTS = ("mps_create", "mps_destroy", "apply_layer_dmrg", "apply_layer_dmrg_batched", "fidelity", "sample",
+           "mps_last_error",
            "mps_amplitude", "mps_to_statevector", "mps_bond_dims", "mps_get_tensor", "mps_step_log",
            "mps_expect_zz", "mps_set_profiling", "mps_kernel_stats", "mps_kernel_selftest_cgemm")
 
@@ -59,6 +60,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mps_create": (i32, [i32, P, i32, i32, P, ctypes.POINTER(P)]),
         "mps_destroy": (i32, [P]),
         "apply_layer_dmrg": (i32, [P, P, i32, i32, i32, dp]),
+        "apply_layer_dmrg_batched": (i32, [ctypes.POINTER(P), i32, ctypes.POINTER(P), ip, ip, i32, dp]),
         "fidelity": (i32, [P, dp, dp, ip, ctypes.POINTER(i64)]),
         "sample": (i32, [P, i64, u64, P]),
         "mps_last_error": (ctypes.c_char_p, []),
@@ -222,6 +224,21 @@ def mps_create(n, bits=None, max_chi=1024, precision=MPS_FP32, stream=None) -> M
 
 def apply_layer_dmrg(state: MPS, layer, chi: int, n_sweeps: int) -> float:
     return state.apply_layer_dmrg(layer, chi, n_sweeps)
+
+
+def apply_layer_dmrg_batched(states: Sequence[MPS], layers, chis: Sequence[int], n_sweeps: int) -> np.ndarray:
+    """One layer per instance, run concurrently (each state should own a stream)."""
+    lib = load_library()
+    b = len(states)
+    recs = [np.ascontiguousarray(layer if isinstance(layer, np.ndarray) else circuits.pack_layer(layer),
+                                 dtype=circuits.GATE_DTYPE) for layer in layers]
+    hs = (ctypes.c_void_p * b)(*[s._h.value for s in states])
+    gp = (ctypes.c_void_p * b)(*[r.ctypes.data if len(r) else None for r in recs])
+    ng = np.ascontiguousarray([len(r) for r in recs], dtype=np.int32)
+    ch = np.ascontiguousarray(chis, dtype=np.int32)
+    f = np.zeros(b)
+    _check(lib.apply_layer_dmrg_batched(hs, b, gp, _iptr(ng), _iptr(ch), n_sweeps, _dptr(f)))
+    return f
 
 
 def fidelity(state: MPS):

@@ -271,3 +271,42 @@ def test_sampler_matches_born_rule(n_sweeps):
     chi2 = float(np.sum((counts[mask] - expect[mask]) ** 2 / expect[mask]))
     dof = int(mask.sum()) - 1
     assert chi2 < dof + 6 * math.sqrt(2 * dof)
+
+
+# ------------------------------------------------------------- QAOA ---------
+def _qaoa_direct(n, edges, gammas, betas):
+    psi = np.ones(2 ** n, dtype=np.complex128) / np.sqrt(2 ** n)
+    for gam, bet in zip(gammas, betas):
+        for u, v in edges:
+            psi = sv.apply_2q(psi, n, u, v, circuits.zz_phase(gam))
+        for s in range(n):
+            psi = sv.apply_1q(psi, n, s, circuits.rx(2 * bet))
+    return psi
+
+
+def test_regular_graph_is_simple_and_regular():
+    edges = circuits.random_regular_graph(54, 3, seed=0)
+    assert len(edges) == 81
+    deg = np.bincount(np.array(edges).reshape(-1), minlength=54)
+    assert np.all(deg == 3) and all(a < b for a, b in edges) and len(set(edges)) == 81
+
+
+def test_qaoa_swap_network_equals_direct_circuit():
+    """The routed chain circuit is the QAOA state, up to the tracked permutation."""
+    n = 8
+    edges = circuits.random_regular_graph(n, 3, seed=2)
+    gammas, betas = circuits.qaoa_parameter_sets(1, 2, seed=3)[0]
+    q = circuits.qaoa_maxcut_swap_network(n, edges, gammas, betas)
+    psi = sv.run(q.circuit)
+    logical = np.transpose(psi.reshape((2,) * n), q.final_position).reshape(-1)
+    assert abs(abs(np.vdot(logical, _qaoa_direct(n, edges, gammas, betas))) - 1.0) < 1e-12
+    # <C> from the oracle MPS (exact chi) equals the statevector value
+    st = dmrg.run_circuit(q.circuit, chi=16, n_sweeps=1)
+    c_mps = circuits.maxcut_expectation_from_zz(edges, q.final_position,
+                                                lambda i, j: dmrg.expectation_zz(st, min(i, j), max(i, j)))
+    probs = np.abs(_qaoa_direct(n, edges, gammas, betas)) ** 2
+    c_sv = 0.0
+    for x in range(2 ** n):
+        bits = [(x >> (n - 1 - k)) & 1 for k in range(n)]
+        c_sv += probs[x] * sum(bits[u] != bits[v] for u, v in edges)
+    assert abs(c_mps - c_sv) < 1e-10
