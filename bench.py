@@ -29,7 +29,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp32": 157.3, "fp64": 78.6}          # dense MFMA TFLOP/s, MI355X
+# dense MFMA TFLOP/s on MI355X; the split path executes six BF16 products per
+# algorithmic real product, so its algorithmic peak is 2500 / 6
+PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0 / 6.0}
+DTYPE = {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3-f32acc"}
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cgemm_54q_chi1024.json")
 
@@ -41,7 +44,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=4)
     p.add_argument("--chi", type=int, default=1024)
     p.add_argument("--sweeps", type=int, default=2)
-    p.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
+    p.add_argument("--precision", choices=("fp32", "bf16x3", "fp64"), default="fp32")
     p.add_argument("--seed", type=int, default=0)
     p.add_argument("--compare-fp64", type=int, default=1,
                    help="also time the same layers with FP64 contractions (1 = yes)")
@@ -54,7 +57,7 @@ def parse():
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("cgemm.hip",):
+    for name in ("cgemm.hip", "cgemm_bf16.hip"):
         with open(os.path.join(ROOT, "paper_2207_05612_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -155,7 +158,7 @@ def main():
     c = circuits.sycamore_like_54_workload(args.seed, depth=20)
     if args.warmup + args.steps > len(c.layers):
         raise SystemExit("warmup + steps must not exceed the circuit depth (20)")
-    prec = mps.MPS_FP32 if args.precision == "fp32" else mps.MPS_FP64
+    prec = {"fp32": mps.MPS_FP32, "bf16x3": mps.MPS_BF16X3, "fp64": mps.MPS_FP64}[args.precision]
     dt, fs, stats, bonds, fid = run_layers(mps, c, prec, args.chi, args.sweeps, args.warmup, args.steps, torch,
                                            args.progress)
     value = args.steps / dt
@@ -180,7 +183,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": "54-qubit 6x9 snake, fSim + random 1q gates, depth 20, seed %d; layers %d..%d timed"
                                % (args.seed, args.warmup, args.warmup + args.steps - 1),
@@ -192,10 +195,12 @@ def main():
         "f_delta": fs,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "kernel": "cgemm_kernel<%s> (complex planar GEMM, %d launches, %.1f ms)"
-                               % (args.precision, con["launches"], con["ms"])},
+                     "kernel": "%s (complex planar GEMM, %d launches, %.1f ms)"
+                               % ("cgemm_bf16x3_nt_kernel" if args.precision == "bf16x3" else
+                                  "cgemm_kernel<%s>" % args.precision, con["launches"], con["ms"])},
+        "contraction_frac_of_fp32_mfma_peak": achieved / PEAK["fp32"],
     }
-    if args.compare_fp64 and args.precision == "fp32":
+    if args.compare_fp64 and args.precision != "fp64":
         dt64, fs64, stats64, _, _ = run_layers(mps, c, mps.MPS_FP64, args.chi, args.sweeps, args.warmup,
                                                args.steps, torch, args.progress)
         c64 = stats64["contract"]

@@ -57,7 +57,10 @@ typedef enum {
  * and the stored MPS tensors are FP64 in every mode. */
 typedef enum {
     MPS_FP64 = 0,   /* complex FP64 contractions on FP64 MFMA                  */
-    MPS_FP32 = 1    /* complex FP32 contractions on FP32 MFMA, FP32 environments */
+    MPS_FP32 = 1,   /* complex FP32 contractions on FP32 MFMA, FP32 environments */
+    MPS_BF16X3 = 3  /* split precision: FP32 operands as three BF16 terms, six
+                       BF16 MFMA products per real product, FP32 accumulation
+                       (about FP32 accuracy), FP32 environments            */
 } mps_precision;
 
 /* One gate.  q1 = -1 for a one-qubit gate.  m holds the matrix as interleaved
@@ -205,7 +208,9 @@ mps_status mps_kernel_stats(const mps_state* state, int kernel_class, int64_t* l
  *   opb 0 (N): b is K x N;   opb 1 (T): b is N x K, op(B) = b^T;
  *   opb 2 (C): b is N x K, op(B) = b^H.
  *   c receives M x N.
- * For kernel-level parity tests; not used by the compression step. */
+ * precision MPS_BF16X3 runs the split-precision kernel, which takes only
+ * opa = 0, opb = 1.  For kernel-level parity tests; not used by the
+ * compression step. */
 mps_status mps_kernel_selftest_cgemm(int precision, int opa, int opb, int M, int N, int K,
                                      const double* a, const double* b, double* c);
 

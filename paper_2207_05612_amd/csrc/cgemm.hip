@@ -61,6 +61,8 @@ struct GemmArgs {
     int M, N, K;
     int gm, gn;
     int lower_only;   // skip tiles that hold no element with column <= row
+    int kchunk;       // k range of split blockIdx.y: [y kchunk, (y+1) kchunk)
+    int64_t split_stride;   // C offset of split y (partial sums); 0 without split
 };
 
 template <typename TIn, typename TAcc, int OPA, int OPB, int BM, int BN, int BK>
@@ -96,7 +98,12 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
     const int m0 = tm * BM, n0 = tn * BN;
     if (g.lower_only && n0 > m0 + BM - 1) return;   // whole tile above the diagonal (uniform per block)
 
-    const int M = g.M, N = g.N, K = g.K;
+    const int M = g.M, N = g.N;
+    // split-K: this block sums k in [kbeg, K) of its own chunk
+    const int kbeg = blockIdx.y * g.kchunk;
+    const int K = min(g.K, kbeg + g.kchunk);
+    TAcc* const c_re = g.c_re + blockIdx.y * g.split_stride;
+    TAcc* const c_im = g.c_im + blockIdx.y * g.split_stride;
 
     TIn ra_re[EA], ra_im[EA], rb_re[EB], rb_im[EB];
 
@@ -165,8 +172,8 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
 #pragma unroll
             for (int v = 0; v < MF::NACC; ++v) { acc_re[i][j][v] = 0; acc_im[i][j][v] = 0; }
 
-    const int nk = (K + BK - 1) / BK;
-    load_tiles(0);
+    const int nk = (K - kbeg + BK - 1) / BK;
+    load_tiles(kbeg);
     store_tiles(0);
     __syncthreads();
 
@@ -174,7 +181,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
     const int lk = lane / MT;
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
-        if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+        if (kt + 1 < nk) load_tiles(kbeg + (kt + 1) * BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += MF::KT) {
             TAcc ar[TM], ai[TM], nai[TM], br[TN], bi[TN];
@@ -221,15 +228,16 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
                 const int c = n0 + wn0 + j * MT + lrow;
                 if (r < M && c < N) {
                     const int64_t off = (int64_t)r * g.ldc + c;
-                    g.c_re[off] = acc_re[i][j][v];
-                    g.c_im[off] = acc_im[i][j][v];
+                    c_re[off] = acc_re[i][j][v];
+                    c_im[off] = acc_im[i][j][v];
                 }
             }
 }
 
 template <typename TIn, typename TAcc, int BM, int BN, int BK>
 static hipError_t launch(int opa, int opb, int M, int N, int K, CView<TIn> A, CView<TIn> B,
-                         CViewMut<TAcc> C, hipStream_t stream, int lower_only = 0) {
+                         CViewMut<TAcc> C, hipStream_t stream, int lower_only = 0, int ksplit = 1,
+                         int64_t split_stride = 0) {
     if (M <= 0 || N <= 0) return hipSuccess;
     GemmArgs<TIn, TAcc> g;
     g.a_re = A.re; g.a_im = A.im; g.lda = A.ld;
@@ -239,9 +247,15 @@ static hipError_t launch(int opa, int opb, int M, int N, int K, CView<TIn> A, CV
     g.gm = (M + BM - 1) / BM;
     g.gn = (N + BN - 1) / BN;
     g.lower_only = lower_only;
+    if (ksplit < 1) ksplit = 1;
+    g.kchunk = (((K + ksplit - 1) / ksplit) + BK - 1) / BK * BK;
+    if (g.kchunk < BK) g.kchunk = BK;
+    ksplit = (K + g.kchunk - 1) / g.kchunk;
+    if (ksplit < 1) ksplit = 1;
+    g.split_stride = ksplit > 1 ? split_stride : 0;
     const int64_t nblocks = (int64_t)g.gm * g.gn;
     if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
-    dim3 grid((unsigned)nblocks), block(256);
+    dim3 grid((unsigned)nblocks, (unsigned)ksplit), block(256);
 #define MPS_GEMM_CASE(OA, OB)                                                                     \
     if (opa == OA && opb == OB) {                                                                 \
         hipLaunchKernelGGL((cgemm_kernel<TIn, TAcc, OA, OB, BM, BN, BK>), grid, block, 0, stream, g); \
@@ -260,6 +274,50 @@ static hipError_t launch(int opa, int opb, int M, int N, int K, CView<TIn> A, CV
 hipError_t cgemm_f32(int opa, int opb, int M, int N, int K, CView<float> A, CView<float> B,
                      CViewMut<float> C, hipStream_t stream) {
     return launch<float, float, 128, 128, 16>(opa, opb, M, N, K, A, B, C, stream);
+}
+
+int splitk_chunks(int K, int ksplit, int bk) {
+    if (ksplit < 1) ksplit = 1;
+    int kc = (((K + ksplit - 1) / ksplit) + bk - 1) / bk * bk;
+    if (kc < bk) kc = bk;
+    return (K + kc - 1) / kc;
+}
+
+hipError_t cgemm_f32_splitk(int opa, int opb, int M, int N, int K, CView<float> A, CView<float> B,
+                            float* ws_re, float* ws_im, int ksplit, hipStream_t stream) {
+    // partial sums of split y go to ws + y M N (row-major, ld = N)
+    return launch<float, float, 128, 128, 16>(opa, opb, M, N, K, A, B, {ws_re, ws_im, N}, stream, 0, ksplit,
+                                              (int64_t)M * N);
+}
+
+// C[r][c] = sum_y ws[y][r][c], summed in FP64 in split order (deterministic)
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restrict__ wre,
+                                                            const float* __restrict__ wim, int nsplit,
+                                                            int64_t M, int64_t N, float* __restrict__ cre,
+                                                            float* __restrict__ cim, int64_t ldc) {
+    const int64_t total = M * N;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        double sr = 0, si = 0;
+        for (int y = 0; y < nsplit; ++y) {
+            sr += wre[y * total + idx];
+            si += wim[y * total + idx];
+        }
+        const int64_t r = idx / N, c = idx % N;
+        cre[r * ldc + c] = (float)sr;
+        cim[r * ldc + c] = (float)si;
+    }
+}
+
+hipError_t splitk_reduce(const float* ws_re, const float* ws_im, int nsplit, int64_t M, int64_t N, float* c_re,
+                         float* c_im, int64_t ldc, hipStream_t stream) {
+    const int64_t total = M * N;
+    if (total <= 0) return hipSuccess;
+    int64_t g = (total + 255) / 256;
+    if (g > 1048576) g = 1048576;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)g), dim3(256), 0, stream, ws_re, ws_im, nsplit, M, N,
+                       c_re, c_im, ldc);
+    return hipGetLastError();
 }
 
 hipError_t cgemm_f64(int opa, int opb, int M, int N, int K, CView<double> A, CView<double> B,

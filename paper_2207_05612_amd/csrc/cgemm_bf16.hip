@@ -1,0 +1,266 @@
+// Split-precision complex GEMM on CDNA4 BF16 matrix cores (gfx950).
+//
+// C (M x N, FP32) = A (M x K) B^T (B stored N x K), planar complex, both
+// operands FP32 with k contiguous.  Every FP32 operand x is split into three
+// BF16 terms x = x_h + x_m + x_l (each the BF16 rounding of what remains), and
+// a real product keeps the six terms x_h y_h + x_h y_m + x_m y_h + x_m y_m +
+// x_h y_l + x_l y_h, accumulated in FP32 by v_mfma_f32_32x32x16_bf16.  The
+// dropped terms are below 2^-24 of the product, so the result carries about
+// FP32 accuracy; a complex product is four such real products.
+//
+// Tiling: 256 threads = 4 wavefronts (2 x 2), wave tile 64 x 64 complex
+// (2 x 2 MFMA tiles of 32 x 32), block tile 128 x 128, BK = 16 (one MFMA k
+// step).  The split happens when a k-tile is staged from registers into LDS;
+// LDS holds [split][re|im][k/8][row][8] so that the 8 consecutive k of one
+// MFMA lane are one 16-byte read and the 32 lanes of a row group read
+// consecutive 16-byte words.  Two LDS buffers (96 KiB) overlap the next
+// tile's global loads with the current tile's 96 MFMAs per wave.  Block ids
+// map to tiles XCD-first, then in groups of 8 tile rows.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace mpsk {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+struct SplitArgs {
+    const float* a_re;
+    const float* a_im;
+    const float* b_re;
+    const float* b_im;
+    float* c_re;
+    float* c_im;
+    int64_t lda, ldb, ldc;
+    int M, N, K;
+    int gm, gn;
+    int kchunk;             // k range of split blockIdx.y
+    int64_t split_stride;   // C offset of split y
+};
+
+// round-to-nearest-even FP32 -> BF16 bits (finite inputs)
+__device__ inline unsigned short bf16_bits(float x) {
+    unsigned int u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_to_float(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
+
+__device__ inline void split3(float x, unsigned short& h, unsigned short& m, unsigned short& l) {
+    h = bf16_bits(x);
+    const float r1 = x - bf16_to_float(h);
+    m = bf16_bits(r1);
+    const float r2 = r1 - bf16_to_float(m);
+    l = bf16_bits(r2);
+}
+
+constexpr int SBM = 128, SBN = 128, SBK = 16;
+// LDS element offset of (split s, part p, chunk c, row r, element e) in a [3][2][2][128][8] tile
+__device__ inline int lds_off(int s, int p, int c, int r) { return ((((s * 2 + p) * 2 + c) * 128) + r) * 8; }
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void cgemm_bf16x3_nt_kernel(SplitArgs g) {
+    __shared__ __attribute__((aligned(16))) unsigned short As[2][3 * 2 * 2 * SBM * 8];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][3 * 2 * 2 * SBN * 8];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm0 = (wave >> 1) * 64;
+    const int wn0 = (wave & 1) * 64;
+
+    int pid = blockIdx.x;
+    const int nb = g.gm * g.gn;
+    if ((nb & 7) == 0) pid = (pid & 7) * (nb >> 3) + (pid >> 3);
+    constexpr int GROUP = 8;
+    const int group = pid / (GROUP * g.gn);
+    const int first_m = group * GROUP;
+    const int gsz = min(g.gm - first_m, GROUP);
+    const int tm = first_m + (pid % gsz);
+    const int tn = (pid % (GROUP * g.gn)) / gsz;
+    const int m0 = tm * SBM, n0 = tn * SBN;
+    const int M = g.M, N = g.N;
+    const int kbeg = blockIdx.y * g.kchunk;
+    const int K = min(g.K, kbeg + g.kchunk);
+    float* const c_re = g.c_re + blockIdx.y * g.split_stride;
+    float* const c_im = g.c_im + blockIdx.y * g.split_stride;
+
+    // staging: each tile plane is 128 rows x 16 k = 512 groups of 4 consecutive k;
+    // thread t stages groups t and t + 256 (row = group / 4, k = 4 (group % 4) .. +3),
+    // so four neighbouring lanes read one 64-byte row segment
+    float4 ar[2], ai[2], br[2], bi[2];
+
+    auto load = [&](int k0) {
+        const bool full_k = VEC && (k0 + SBK <= K);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int grp = tid + 256 * u;
+            const int row = grp >> 2, kq = (grp & 3) * 4;
+            const int gr = m0 + row, gc = n0 + row;
+            const int k = k0 + kq;
+            if (full_k) {
+                const int64_t oa = (int64_t)gr * g.lda + k, ob = (int64_t)gc * g.ldb + k;
+                const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+                ar[u] = gr < M ? *(const float4*)(g.a_re + oa) : z;
+                ai[u] = gr < M ? *(const float4*)(g.a_im + oa) : z;
+                br[u] = gc < N ? *(const float4*)(g.b_re + ob) : z;
+                bi[u] = gc < N ? *(const float4*)(g.b_im + ob) : z;
+            } else {
+                float t[4][4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const bool ka = (gr < M) && (k + e < K);
+                    const bool kb = (gc < N) && (k + e < K);
+                    const int64_t oa = (int64_t)gr * g.lda + k + e, ob = (int64_t)gc * g.ldb + k + e;
+                    t[0][e] = ka ? g.a_re[oa] : 0.f;
+                    t[1][e] = ka ? g.a_im[oa] : 0.f;
+                    t[2][e] = kb ? g.b_re[ob] : 0.f;
+                    t[3][e] = kb ? g.b_im[ob] : 0.f;
+                }
+                ar[u] = make_float4(t[0][0], t[0][1], t[0][2], t[0][3]);
+                ai[u] = make_float4(t[1][0], t[1][1], t[1][2], t[1][3]);
+                br[u] = make_float4(t[2][0], t[2][1], t[2][2], t[2][3]);
+                bi[u] = make_float4(t[3][0], t[3][1], t[3][2], t[3][3]);
+            }
+        }
+    };
+    typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+    auto put = [&](unsigned short* base, int p, int row, int kq, float4 v) {
+        const float x[4] = {v.x, v.y, v.z, v.w};
+        u16x4 h, m, l;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            unsigned short a, b, c;
+            split3(x[e], a, b, c);
+            h[e] = a; m[e] = b; l[e] = c;
+        }
+        const int chunk = kq >> 3, sub = kq & 7;
+        *(u16x4*)&base[lds_off(0, p, chunk, row) + sub] = h;
+        *(u16x4*)&base[lds_off(1, p, chunk, row) + sub] = m;
+        *(u16x4*)&base[lds_off(2, p, chunk, row) + sub] = l;
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int grp = tid + 256 * u;
+            const int row = grp >> 2, kq = (grp & 3) * 4;
+            put(As[buf], 0, row, kq, ar[u]);
+            put(As[buf], 1, row, kq, ai[u]);
+            put(Bs[buf], 0, row, kq, br[u]);
+            put(Bs[buf], 1, row, kq, bi[u]);
+        }
+    };
+
+    f32x16 acc_re[2][2], acc_im[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) { acc_re[i][j][v] = 0.f; acc_im[i][j][v] = 0.f; }
+
+    const int nk = (K - kbeg + SBK - 1) / SBK;
+    load(kbeg);
+    store(0);
+    __syncthreads();
+
+    const int lrow = lane & 31;
+    const int lchunk = lane >> 5;
+    // the six kept split pairs (x split, y split)
+    constexpr int PA[6] = {0, 0, 1, 1, 0, 2};
+    constexpr int PB[6] = {0, 1, 0, 1, 2, 0};
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) load(kbeg + (kt + 1) * SBK);
+        bf16x8 fa[2][2][3], fb[2][2][3], fbn[2][3];   // [tile][re|im][split]; fbn = -B_im
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int s = 0; s < 3; ++s) {
+                    fa[i][p][s] = *(const bf16x8*)&As[buf][lds_off(s, p, lchunk, wm0 + i * 32 + lrow)];
+                    fb[i][p][s] = *(const bf16x8*)&Bs[buf][lds_off(s, p, lchunk, wn0 + i * 32 + lrow)];
+                }
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                u16x8 t = __builtin_bit_cast(u16x8, fb[j][1][s]);
+                t ^= (unsigned short)0x8000;
+                fbn[j][s] = __builtin_bit_cast(bf16x8, t);
+            }
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][0][PA[q]], fb[j][0][PB[q]], acc_re[i][j], 0, 0, 0);
+                    acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][0][PA[q]], fb[j][1][PB[q]], acc_im[i][j], 0, 0, 0);
+                    acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][1][PA[q]], fbn[j][PB[q]], acc_re[i][j], 0, 0, 0);
+                    acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][1][PA[q]], fb[j][0][PB[q]], acc_im[i][j], 0, 0, 0);
+                }
+        if (kt + 1 < nk) store(buf ^ 1);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int r = m0 + wm0 + i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+                const int c = n0 + wn0 + j * 32 + lrow;
+                if (r < M && c < N) {
+                    const int64_t off = (int64_t)r * g.ldc + c;
+                    c_re[off] = acc_re[i][j][v];
+                    c_im[off] = acc_im[i][j][v];
+                }
+            }
+}
+
+static hipError_t launch_split(int M, int N, int K, CView<float> A, CView<float> B, CViewMut<float> C,
+                               int ksplit, int64_t split_stride, hipStream_t stream) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    SplitArgs g;
+    g.a_re = A.re; g.a_im = A.im; g.lda = A.ld;
+    g.b_re = B.re; g.b_im = B.im; g.ldb = B.ld;
+    g.c_re = C.re; g.c_im = C.im; g.ldc = C.ld;
+    g.M = M; g.N = N; g.K = K;
+    g.gm = (M + SBM - 1) / SBM;
+    g.gn = (N + SBN - 1) / SBN;
+    if (ksplit < 1) ksplit = 1;
+    g.kchunk = (((K + ksplit - 1) / ksplit) + SBK - 1) / SBK * SBK;
+    if (g.kchunk < SBK) g.kchunk = SBK;
+    ksplit = (K + g.kchunk - 1) / g.kchunk;
+    if (ksplit < 1) ksplit = 1;
+    g.split_stride = ksplit > 1 ? split_stride : 0;
+    const int64_t nblocks = (int64_t)g.gm * g.gn;
+    if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
+    // float4 staging needs 16-byte aligned rows (leading dimensions and plane bases)
+    const bool vec = (A.ld % 4 == 0) && (B.ld % 4 == 0) &&
+                     ((((uintptr_t)A.re) | ((uintptr_t)A.im) | ((uintptr_t)B.re) | ((uintptr_t)B.im)) & 15) == 0;
+    const dim3 grid((unsigned)nblocks, (unsigned)ksplit);
+    if (vec)
+        hipLaunchKernelGGL(cgemm_bf16x3_nt_kernel<true>, grid, dim3(256), 0, stream, g);
+    else
+        hipLaunchKernelGGL(cgemm_bf16x3_nt_kernel<false>, grid, dim3(256), 0, stream, g);
+    return hipGetLastError();
+}
+
+hipError_t cgemm_bf16x3_nt(int M, int N, int K, CView<float> A, CView<float> B, CViewMut<float> C,
+                           hipStream_t stream) {
+    return launch_split(M, N, K, A, B, C, 1, 0, stream);
+}
+
+hipError_t cgemm_bf16x3_nt_splitk(int M, int N, int K, CView<float> A, CView<float> B, float* ws_re,
+                                  float* ws_im, int ksplit, hipStream_t stream) {
+    return launch_split(M, N, K, A, B, {ws_re, ws_im, N}, ksplit, (int64_t)M * N, stream);
+}
+
+}  // namespace mpsk

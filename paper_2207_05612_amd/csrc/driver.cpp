@@ -89,8 +89,10 @@ struct Planar {
     void ensure(int64_t n, hipStream_t s) {
         if (n <= cap && p) return;
         dfree(p, s);
-        p = (T*)dalloc(sizeof(T) * 2 * (size_t)std::max<int64_t>(n, 1), s);
-        cap = std::max<int64_t>(n, 1);
+        // capacity rounded to 64 elements keeps the imaginary plane 256-byte aligned
+        const int64_t c = (std::max<int64_t>(n, 1) + 63) / 64 * 64;
+        p = (T*)dalloc(sizeof(T) * 2 * (size_t)c, s);
+        cap = c;
     }
     void release(hipStream_t s) {
         dfree(p, s);
@@ -360,6 +362,7 @@ struct mps_state {
     bool invalid = false;
     rocblas_handle blas = nullptr;
     // scratch
+    Planar<float> splitws;         // partial sums of split-K FP32 / split-precision GEMMs
     Raw<double> dscal;             // small device scalars
     Raw<double> partial;           // reduction partials
     bool prof = false;
@@ -434,6 +437,18 @@ hipError_t gemm_raw<double>(int opa, int opb, int M, int N, int K, const double*
     return cgemm_f64(opa, opb, M, N, K, {ar, ai, lda}, {br, bi, ldb}, {cr, ci, ldc}, s);
 }
 
+// FP32 accumulation over a long k range loses accuracy like sqrt(K) eps (one
+// accumulator per output).  Long contractions are cut into chunks of about
+// 4096 terms whose partial sums are added in FP64; short ones with few output
+// tiles are cut too, to occupy all CUs.  Returns the requested chunk count.
+int splitk_for(int64_t M, int64_t N, int64_t K) {
+    int64_t ks = 1;
+    if (K >= 8192) ks = std::min<int64_t>(64, K / 4096);
+    const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
+    if (tiles < 256 && K >= 2048) ks = std::max<int64_t>(ks, std::min<int64_t>((512 + tiles - 1) / tiles, K / 1024));
+    return (int)std::max<int64_t>(1, ks);
+}
+
 template <typename R>
 void gemm(mps_state* st, int cls, int opa, int opb, int64_t M, int64_t N, int64_t K, const R* ar,
           const R* ai, int64_t lda, const R* br, const R* bi, int64_t ldb, R* cr, R* ci, int64_t ldc) {
@@ -441,7 +456,35 @@ void gemm(mps_state* st, int cls, int opa, int opb, int64_t M, int64_t N, int64_
     const double fl = 8.0 * (double)M * (double)N * (double)K;
     const double by = 2.0 * sizeof(R) * ((double)M * K + (double)K * N + (double)M * N);
     Timer t(st, cls, fl, by);
-    HIPCHK(gemm_raw<R>(opa, opb, (int)M, (int)N, (int)K, ar, ai, lda, br, bi, ldb, cr, ci, ldc, st->stream));
+    const int ks = sizeof(R) == 4 ? splitk_chunks((int)K, splitk_for(M, N, K), 16) : 1;
+    if (ks > 1) {
+        st->splitws.ensure(M * N * ks, st->stream);
+        HIPCHK(cgemm_f32_splitk(opa, opb, (int)M, (int)N, (int)K, {(const float*)ar, (const float*)ai, lda},
+                                {(const float*)br, (const float*)bi, ldb}, st->splitws.re(), st->splitws.im(),
+                                splitk_for(M, N, K), st->stream));
+        HIPCHK(splitk_reduce(st->splitws.re(), st->splitws.im(), ks, M, N, (float*)cr, (float*)ci, ldc, st->stream));
+    } else {
+        HIPCHK(gemm_raw<R>(opa, opb, (int)M, (int)N, (int)K, ar, ai, lda, br, bi, ldb, cr, ci, ldc, st->stream));
+    }
+    t.done();
+}
+
+// Split-precision (BF16 x 3) complex GEMM, C = A B^T with both operands k-contiguous.
+void gemm_split(mps_state* st, int cls, int64_t M, int64_t N, int64_t K, const float* ar, const float* ai,
+                int64_t lda, const float* br, const float* bi, int64_t ldb, float* cr, float* ci, int64_t ldc) {
+    if (M > 0x7fffffff || N > 0x7fffffff || K > 0x7fffffff) fail(MPS_ERR_ARG, "GEMM dimension too large");
+    const double fl = 8.0 * (double)M * (double)N * (double)K;
+    const double by = 8.0 * ((double)M * K + (double)K * N + (double)M * N);
+    Timer t(st, cls, fl, by);
+    const int ks = splitk_chunks((int)K, splitk_for(M, N, K), 16);
+    if (ks > 1) {
+        st->splitws.ensure(M * N * ks, st->stream);
+        HIPCHK(cgemm_bf16x3_nt_splitk((int)M, (int)N, (int)K, {ar, ai, lda}, {br, bi, ldb}, st->splitws.re(),
+                                      st->splitws.im(), splitk_for(M, N, K), st->stream));
+        HIPCHK(splitk_reduce(st->splitws.re(), st->splitws.im(), ks, M, N, cr, ci, ldc, st->stream));
+    } else {
+        HIPCHK(cgemm_bf16x3_nt((int)M, (int)N, (int)K, {ar, ai, lda}, {br, bi, ldb}, {cr, ci, ldc}, st->stream));
+    }
     t.done();
 }
 
@@ -456,7 +499,8 @@ struct Engine {
     std::vector<Planar<R>> env;       // per bond
     std::vector<Planar<R>> psi[2];    // per view-site, view layout
     std::vector<Planar<double>> phi;  // per site, layout of the pass that wrote it
-    Planar<R> X, T2, T4, TH, UR;
+    Planar<R> X, T2, T4, TH, UR, T2T;
+    bool split = false;   // BF16 x 3 contractions (R = float only): operands kept k-contiguous
     Planar<double> TH64, GR, U64, V64, M64;
     Raw<double> Z, evals, evwork, svec;
     Raw<int> info;
@@ -468,7 +512,7 @@ struct Engine {
         for (auto& e : env) e.release(s);
         for (int o = 0; o < 2; ++o)
             for (auto& e : psi[o]) e.release(s);
-        X.release(s); T2.release(s); T4.release(s); TH.release(s); UR.release(s);
+        X.release(s); T2.release(s); T4.release(s); TH.release(s); UR.release(s); T2T.release(s);
         TH64.release(s); GR.release(s); U64.release(s); V64.release(s); M64.release(s);
         Z.release(s); evals.release(s); evwork.release(s); svec.release(s); info.release(s);
         for (auto& p : phi) p.release(s);
@@ -628,8 +672,15 @@ struct Engine {
                 const int Dl = st->orient == 0 ? st->bond[k] : st->bond[k + 1];
                 const int Dr = st->orient == 0 ? st->bond[k + 1] : st->bond[k];
                 Timer t(st, MPS_KCLASS_OTHER, 0, (8.0 + sizeof(R) * 2) * sz);
-                HIPCHK(site_to_view<R>(st->ten[k].re(), st->ten[k].im(), Dl, Dr, st->orient != o ? 1 : 0,
-                                       psi[o][j].re(), psi[o][j].im(), s));
+                if (split) {
+                    // k-major copy: (2 D_right) x D_left with the view's legs
+                    const int Dlv = st->orient != o ? Dr : Dl, Drv = st->orient != o ? Dl : Dr;
+                    HIPCHK(site_to_kmajor(st->ten[k].re(), st->ten[k].im(), Dlv, Drv, st->orient != o ? 1 : 0,
+                                          (float*)psi[o][j].re(), (float*)psi[o][j].im(), s));
+                } else {
+                    HIPCHK(site_to_view<R>(st->ten[k].re(), st->ten[k].im(), Dl, Dr, st->orient != o ? 1 : 0,
+                                           psi[o][j].re(), psi[o][j].im(), s));
+                }
                 t.done();
             }
         }
@@ -644,8 +695,13 @@ struct Engine {
         const int64_t DL = st->bond[bL], DM = st->bond[bM];
         X.ensure(cL * wL * 2 * DM, s);
         T2.ensure(cL * 2 * wM * DM, s);
-        gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_N, cL * wL, 2 * DM, DL, env[bL].re(), env[bL].im(), DL,
-                psi[o][j].re(), psi[o][j].im(), 2 * DM, X.re(), X.im(), 2 * DM);
+        if (split)
+            gemm_split(st, MPS_KCLASS_CONTRACT, cL * wL, 2 * DM, DL, (const float*)env[bL].re(),
+                       (const float*)env[bL].im(), DL, (const float*)psi[o][j].re(), (const float*)psi[o][j].im(), DL,
+                       (float*)X.re(), (float*)X.im(), 2 * DM);
+        else
+            gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_N, cL * wL, 2 * DM, DL, env[bL].re(), env[bL].im(), DL,
+                    psi[o][j].re(), psi[o][j].im(), 2 * DM, X.re(), X.im(), 2 * DM);
         const MpoSiteOp& op = mpo.view[o][j];
         Timer t(st, MPS_KCLASS_MPO, 0, 2.0 * sizeof(R) * (cL * wL * 2 * DM + cL * 2 * wM * DM));
         HIPCHK(mpo_apply<R>(op, cL, DM, X.re(), X.im(), T2.re(), T2.im(), s));
@@ -665,6 +721,21 @@ struct Engine {
         if (!update_env) return;
         env[bM].ensure(tr.k * wM * DM, s);
         UR.ensure(rows * tr.k, s);
+        if (split) {
+            // env = U^H T2 as (U^H) (T2^T)^T: both operands k-contiguous
+            T2T.ensure(rows * wM * DM, s);
+            {
+                Timer t(st, MPS_KCLASS_OTHER, 0, 16.0 * rows * wM * DM);
+                HIPCHK(transpose_planar((const float*)T2.re(), (const float*)T2.im(), rows, wM * DM, (float*)T2T.re(),
+                                        (float*)T2T.im(), s));
+                t.done();
+            }
+            HIPCHK(adjoint_to_f32(U64.re(), U64.im(), rows, tr.k, (float*)UR.re(), (float*)UR.im(), s));
+            gemm_split(st, MPS_KCLASS_CONTRACT, tr.k, wM * DM, rows, (const float*)UR.re(), (const float*)UR.im(),
+                       rows, (const float*)T2T.re(), (const float*)T2T.im(), rows, (float*)env[bM].re(),
+                       (float*)env[bM].im(), wM * DM);
+            return;
+        }
         HIPCHK((convert_planar<double, R>(U64.re(), U64.im(), rows * tr.k, UR.re(), UR.im(), s)));
         gemm<R>(st, MPS_KCLASS_CONTRACT, OP_C, OP_N, tr.k, wM * DM, rows, UR.re(), UR.im(), tr.k, T2.re(), T2.im(),
                 wM * DM, env[bM].re(), env[bM].im(), wM * DM);
@@ -710,16 +781,26 @@ struct Engine {
             TH.ensure(4 * cL * cR, s);
             TH64.ensure(4 * cL * cR, s);
             // T2 . A_{j+1}
-            gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_N, cL * 2 * wM, 2 * DR, DM, T2.re(), T2.im(), DM,
-                    psi[o][j + 1].re(), psi[o][j + 1].im(), 2 * DR, X.re(), X.im(), 2 * DR);
+            if (split)
+                gemm_split(st, MPS_KCLASS_CONTRACT, cL * 2 * wM, 2 * DR, DM, (const float*)T2.re(),
+                           (const float*)T2.im(), DM, (const float*)psi[o][j + 1].re(),
+                           (const float*)psi[o][j + 1].im(), DM, (float*)X.re(), (float*)X.im(), 2 * DR);
+            else
+                gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_N, cL * 2 * wM, 2 * DR, DM, T2.re(), T2.im(), DM,
+                        psi[o][j + 1].re(), psi[o][j + 1].im(), 2 * DR, X.re(), X.im(), 2 * DR);
             {
                 Timer t(st, MPS_KCLASS_MPO, 0, 2.0 * sizeof(R) * (cL * 2 * wM * 2 * DR + cL * 4 * wR * DR));
                 HIPCHK(mpo_apply<R>(mpo.view[o][j + 1], 2 * cL, DR, X.re(), X.im(), T4.re(), T4.im(), s));
                 t.done();
             }
             // Theta = T4 . R^T
-            gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_T, 4 * cL, cR, wR * DR, T4.re(), T4.im(), wR * DR,
-                    env[bR].re(), env[bR].im(), wR * DR, TH.re(), TH.im(), cR);
+            if (split)
+                gemm_split(st, MPS_KCLASS_CONTRACT, 4 * cL, cR, wR * DR, (const float*)T4.re(), (const float*)T4.im(),
+                           wR * DR, (const float*)env[bR].re(), (const float*)env[bR].im(), wR * DR,
+                           (float*)TH.re(), (float*)TH.im(), cR);
+            else
+                gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_T, 4 * cL, cR, wR * DR, T4.re(), T4.im(), wR * DR,
+                        env[bR].re(), env[bR].im(), wR * DR, TH.re(), TH.im(), cR);
             const int64_t rows = 2 * cL, cols = 2 * cR;
             HIPCHK((convert_planar<R, double>(TH.re(), TH.im(), rows * cols, TH64.re(), TH64.im(), s)));
             Trunc tr = truncate(TH.re(), TH.im(), rows, cols, last, TH64.re(), TH64.im());
@@ -821,8 +902,9 @@ void apply_layer_impl(mps_state* st, const mps_gate* gates, int n_gates, int chi
     const size_t log_mark = st->log_step_f.size();
     double f = 0;
     try {
-        if (st->prec == MPS_FP32) {
+        if (st->prec == MPS_FP32 || st->prec == MPS_BF16X3) {
             Engine<float> e(st, chi);
+            e.split = st->prec == MPS_BF16X3;
             f = e.run(gates, n_gates, n_sweeps);
         } else {
             Engine<double> e(st, chi);
@@ -858,7 +940,8 @@ mps_status mps_create(int n_sites, const uint8_t* init_bits, int max_chi, int pr
         *out = nullptr;
         if (n_sites < 1 || n_sites > 4096) fail(MPS_ERR_ARG, "n_sites must be in [1, 4096]");
         if (max_chi < 1) fail(MPS_ERR_ARG, "max_chi must be >= 1");
-        if (precision != MPS_FP64 && precision != MPS_FP32) fail(MPS_ERR_ARG, "unknown precision");
+        if (precision != MPS_FP64 && precision != MPS_FP32 && precision != MPS_BF16X3)
+            fail(MPS_ERR_ARG, "unknown precision");
         if (init_bits)
             for (int k = 0; k < n_sites; ++k)
                 if (init_bits[k] > 1) fail(MPS_ERR_ARG, "init_bits must be 0 or 1");
@@ -876,14 +959,12 @@ mps_status mps_create(int n_sites, const uint8_t* init_bits, int max_chi, int pr
             st->partial.ensure(1024, st->stream);
             st->bond.assign(n_sites + 1, 1);
             st->ten.resize(n_sites);
-            std::vector<double> host(4);
             for (int k = 0; k < n_sites; ++k) {
                 st->ten[k].ensure(2, st->stream);
                 const int b = init_bits ? init_bits[k] : 0;
-                host[0] = b == 0 ? 1.0 : 0.0;
-                host[1] = b == 1 ? 1.0 : 0.0;
-                host[2] = host[3] = 0.0;
-                HIPCHK(hipMemcpyAsync(st->ten[k].p, host.data(), sizeof(double) * 4, hipMemcpyHostToDevice, st->stream));
+                const double re[2] = {b == 0 ? 1.0 : 0.0, b == 1 ? 1.0 : 0.0}, im[2] = {0.0, 0.0};
+                HIPCHK(hipMemcpyAsync(st->ten[k].re(), re, sizeof(re), hipMemcpyHostToDevice, st->stream));
+                HIPCHK(hipMemcpyAsync(st->ten[k].im(), im, sizeof(im), hipMemcpyHostToDevice, st->stream));
                 HIPCHK(hipStreamSynchronize(st->stream));
             }
         } catch (...) {
@@ -900,6 +981,7 @@ mps_status mps_destroy(mps_state* st) {
     for (auto& t : st->ten) t.release(st->stream);
     st->dscal.release(st->stream);
     st->partial.release(st->stream);
+    st->splitws.release(st->stream);
     for (auto& p : st->pending) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
@@ -1093,7 +1175,7 @@ mps_status mps_amplitude(const mps_state* st_c, int n_strings, const uint8_t* bi
 namespace {
 
 template <typename R>
-void sample_impl(mps_state* st, int64_t n_samples, uint64_t seed, uint64_t* out) {
+void sample_impl(mps_state* st, int64_t n_samples, uint64_t seed, uint64_t* out, bool split = false) {
     const int n = st->n;
     const hipStream_t s = st->stream;
     const int words = (n + 63) / 64;
@@ -1109,8 +1191,14 @@ void sample_impl(mps_state* st, int64_t n_samples, uint64_t seed, uint64_t* out)
         views[j].ensure((int64_t)st->bond[k] * 2 * st->bond[k + 1], s);
         const int Dl = st->orient == 0 ? st->bond[k] : st->bond[k + 1];
         const int Dr = st->orient == 0 ? st->bond[k + 1] : st->bond[k];
-        HIPCHK(site_to_view<R>(st->ten[k].re(), st->ten[k].im(), Dl, Dr, st->orient != oc ? 1 : 0,
-                               views[j].re(), views[j].im(), s));
+        if (split) {
+            const int Dlv = st->orient != oc ? Dr : Dl, Drv = st->orient != oc ? Dl : Dr;
+            HIPCHK(site_to_kmajor(st->ten[k].re(), st->ten[k].im(), Dlv, Drv, st->orient != oc ? 1 : 0,
+                                  (float*)views[j].re(), (float*)views[j].im(), s));
+        } else {
+            HIPCHK(site_to_view<R>(st->ten[k].re(), st->ten[k].im(), Dl, Dr, st->orient != oc ? 1 : 0,
+                                   views[j].re(), views[j].im(), s));
+        }
     }
     Planar<R> v, u;
     v.ensure(chunk * maxD, s);
@@ -1125,8 +1213,13 @@ void sample_impl(mps_state* st, int64_t n_samples, uint64_t seed, uint64_t* out)
             const int k = oc == 0 ? j : n - 1 - j;
             const int64_t Dv = oc == 0 ? st->bond[k] : st->bond[k + 1];
             const int64_t Dn = oc == 0 ? st->bond[k + 1] : st->bond[k];
-            gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_N, S, 2 * Dn, Dv, v.re(), v.im(), Dv, views[j].re(),
-                    views[j].im(), 2 * Dn, u.re(), u.im(), 2 * Dn);
+            if (split)
+                gemm_split(st, MPS_KCLASS_CONTRACT, S, 2 * Dn, Dv, (const float*)v.re(), (const float*)v.im(), Dv,
+                           (const float*)views[j].re(), (const float*)views[j].im(), Dv, (float*)u.re(),
+                           (float*)u.im(), 2 * Dn);
+            else
+                gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_N, S, 2 * Dn, Dv, v.re(), v.im(), Dv, views[j].re(),
+                        views[j].im(), 2 * Dn, u.re(), u.im(), 2 * Dn);
             Timer t(st, MPS_KCLASS_OTHER, 0, 3.0 * sizeof(R) * S * 2 * Dn);
             HIPCHK(select_rows<R>(u.re(), u.im(), S, (int)Dn, 1, nullptr, seed, s0, k, v.re(), v.im(),
                                   bdev.p + (int64_t)k * S, s));
@@ -1153,6 +1246,7 @@ mps_status sample(mps_state* st, int64_t n_samples, uint64_t seed, uint64_t* bit
         if (n_samples < 0 || (n_samples > 0 && !bits)) fail(MPS_ERR_ARG, "bad sample arguments");
         if (n_samples == 0) return;
         if (st->prec == MPS_FP32) sample_impl<float>(st, n_samples, seed, bits);
+        else if (st->prec == MPS_BF16X3) sample_impl<float>(st, n_samples, seed, bits, true);
         else sample_impl<double>(st, n_samples, seed, bits);
     });
 }
@@ -1220,7 +1314,8 @@ mps_status mps_kernel_stats(const mps_state* st, int cls, int64_t* launches, dou
 
 namespace {
 template <typename R>
-void selftest_cgemm_impl(int opa, int opb, int M, int N, int K, const double* a, const double* b, double* c) {
+void selftest_cgemm_impl(int opa, int opb, int M, int N, int K, const double* a, const double* b, double* c,
+                         bool split = false) {
     hipStream_t s = nullptr;
     const int64_t na = (int64_t)M * K, nb = (int64_t)K * N, nc = (int64_t)M * N;
     std::vector<R> ha(2 * na), hb(2 * nb), hc(2 * nc);
@@ -1233,7 +1328,26 @@ void selftest_cgemm_impl(int opa, int opb, int M, int N, int K, const double* a,
     HIPCHK(hipMemcpyAsync(db, hb.data(), sizeof(R) * 2 * nb, hipMemcpyHostToDevice, s));
     const int64_t lda = (opa == OP_N) ? K : M;
     const int64_t ldb = (opb == OP_N) ? N : K;
-    HIPCHK(gemm_raw<R>(opa, opb, M, N, K, da, da + na, lda, db, db + nb, ldb, dc, dc + nc, N, s));
+    // the same split-K policy as the compression step (FP32 and split-precision kernels)
+    const int ks = sizeof(R) == 4 ? splitk_chunks(K, splitk_for(M, N, K), 16) : 1;
+    float* ws = nullptr;
+    if (ks > 1) ws = (float*)dalloc(sizeof(float) * 2 * (size_t)nc * ks, s);
+    if (split && ks > 1)
+        HIPCHK(cgemm_bf16x3_nt_splitk(M, N, K, {(const float*)da, (const float*)(da + na), lda},
+                                      {(const float*)db, (const float*)(db + nb), ldb}, ws, ws + nc * ks,
+                                      splitk_for(M, N, K), s));
+    else if (split)
+        HIPCHK(cgemm_bf16x3_nt(M, N, K, {(const float*)da, (const float*)(da + na), lda},
+                               {(const float*)db, (const float*)(db + nb), ldb}, {(float*)dc, (float*)(dc + nc), N}, s));
+    else if (ks > 1)
+        HIPCHK(cgemm_f32_splitk(opa, opb, M, N, K, {(const float*)da, (const float*)(da + na), lda},
+                                {(const float*)db, (const float*)(db + nb), ldb}, ws, ws + nc * ks, splitk_for(M, N, K), s));
+    else
+        HIPCHK(gemm_raw<R>(opa, opb, M, N, K, da, da + na, lda, db, db + nb, ldb, dc, dc + nc, N, s));
+    if (ks > 1) {
+        HIPCHK(splitk_reduce(ws, ws + nc * ks, ks, M, N, (float*)dc, (float*)(dc + nc), N, s));
+        dfree(ws, s);
+    }
     HIPCHK(hipMemcpyAsync(hc.data(), dc, sizeof(R) * 2 * nc, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     dfree(da, s); dfree(db, s); dfree(dc, s);
@@ -1250,7 +1364,10 @@ extern "C" mps_status mps_kernel_selftest_cgemm(int precision, int opa, int opb,
         if (opb != OP_N && opb != OP_T && opb != OP_C) fail(MPS_ERR_ARG, "opb must be 0, 1 or 2");
         if ((int64_t)M * K > (1 << 28) || (int64_t)K * N > (1 << 28) || (int64_t)M * N > (1 << 28))
             fail(MPS_ERR_ARG, "self-test operands too large");
-        if (precision == MPS_FP32) selftest_cgemm_impl<float>(opa, opb, M, N, K, a, b, c);
+        if (precision == MPS_BF16X3) {
+            if (opa != OP_N || opb != OP_T) fail(MPS_ERR_ARG, "the split-precision kernel takes opa = 0, opb = 1");
+            selftest_cgemm_impl<float>(opa, opb, M, N, K, a, b, c, true);
+        } else if (precision == MPS_FP32) selftest_cgemm_impl<float>(opa, opb, M, N, K, a, b, c);
         else if (precision == MPS_FP64) selftest_cgemm_impl<double>(opa, opb, M, N, K, a, b, c);
         else fail(MPS_ERR_ARG, "unknown precision");
     });

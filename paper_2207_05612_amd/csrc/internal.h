@@ -40,6 +40,24 @@ hipError_t cgemm_f64(int opa, int opb, int M, int N, int K, CView<double> A, CVi
 hipError_t cgemm_f32in_f64(int opa, int opb, int M, int N, int K, CView<float> A,
                            CView<float> B, CViewMut<double> C, hipStream_t stream, int lower_only = 0);
 
+// Split-K FP32 complex GEMM: the K range is cut into chunks of whole k-tiles;
+// chunk y writes its partial product to ws + y M N (ld N).  splitk_chunks()
+// gives the number of chunks a request for ksplit produces; splitk_reduce()
+// sums them in FP64 in chunk order into C.
+int splitk_chunks(int K, int ksplit, int bk);
+hipError_t cgemm_f32_splitk(int opa, int opb, int M, int N, int K, CView<float> A, CView<float> B,
+                            float* ws_re, float* ws_im, int ksplit, hipStream_t stream);
+hipError_t splitk_reduce(const float* ws_re, const float* ws_im, int nsplit, int64_t M, int64_t N, float* c_re,
+                         float* c_im, int64_t ldc, hipStream_t stream);
+hipError_t cgemm_bf16x3_nt_splitk(int M, int N, int K, CView<float> A, CView<float> B, float* ws_re,
+                                  float* ws_im, int ksplit, hipStream_t stream);
+
+// Split-precision complex GEMM: C (M x N) = A (M x K) B^T with B stored N x K,
+// FP32 operands split into three BF16 terms, six BF16 MFMA products per real
+// product, FP32 accumulation (about FP32 accuracy).
+hipError_t cgemm_bf16x3_nt(int M, int N, int K, CView<float> A, CView<float> B, CViewMut<float> C,
+                           hipStream_t stream);
+
 // Structured MPO application on one site.
 //   in  [P][w_in][2 (t)][Q],  out [P][2 (s)][w_out][Q]
 //   w_in = H * r_in * lo, w_out = H * r_out * lo; one of r_in, r_out is 1.
@@ -58,6 +76,19 @@ hipError_t mpo_apply(const MpoSiteOp& op, int64_t P, int64_t Q, const T* in_re, 
 template <typename T>
 hipError_t site_to_view(const double* re, const double* im, int Dl, int Dr, int swap_legs,
                         T* out_re, T* out_im, hipStream_t stream);
+
+// View tensor V[a][s][x] (dims Dl_v, 2, Dr_v) as the k-major (2 Dr_v) x Dl_v
+// FP32 matrix O[(s Dr_v + x) Dl_v + a]; stored layout as in site_to_view.
+hipError_t site_to_kmajor(const double* re, const double* im, int Dlv, int Drv, int swap_legs, float* ore,
+                          float* oim, hipStream_t stream);
+
+// out (C x R) = in^T of a row-major R x C planar FP32 matrix (LDS-tiled).
+hipError_t transpose_planar(const float* ire, const float* iim, int64_t R, int64_t C, float* ore, float* oim,
+                            hipStream_t stream);
+
+// out (k x m, FP32) = in^H of a row-major m x k FP64 planar matrix.
+hipError_t adjoint_to_f32(const double* re, const double* im, int64_t m, int64_t k, float* ore, float* oim,
+                          hipStream_t stream);
 
 // Element-wise conversion of a planar array of n complex numbers.
 template <typename TI, typename TO>

@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpsdmrg.so")
 
 MPS_OK, MPS_ERR_ARG, MPS_ERR_OOM, MPS_ERR_DEVICE, MPS_ERR_NUMERIC, MPS_ERR_STATE = 0, -1, -2, -3, -4, -5
-MPS_FP64, MPS_FP32 = 0, 1
+MPS_FP64, MPS_FP32, MPS_BF16X3 = 0, 1, 3
 KCLASS = {"contract": 0, "mpo": 1, "gram": 2, "eigh": 3, "other": 4}
 
 # every symbol declared in include/mps_dmrg.h

@@ -30,7 +30,7 @@ from oracle import dmrg
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-FP64, FP32 = mps.MPS_FP64, mps.MPS_FP32
+FP64, FP32, BF16X3 = mps.MPS_FP64, mps.MPS_FP32, mps.MPS_BF16X3
 
 
 def golden_cases():
@@ -49,7 +49,7 @@ def bitstrings(n, count=64, seed=12345):
     return rng.integers(0, 2, size=(count, n)).astype(np.uint8)
 
 
-@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("prec", [FP64, FP32, BF16X3])
 @pytest.mark.parametrize("name", golden_cases())
 def test_golden_parity(name, prec):
     rec = json.load(open(os.path.join(GOLDEN, name + ".json")))
