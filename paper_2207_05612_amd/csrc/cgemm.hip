@@ -330,4 +330,46 @@ hipError_t cgemm_f32in_f64(int opa, int opb, int M, int N, int K, CView<float> A
     return launch<float, double, 128, 64, 8>(opa, opb, M, N, K, A, B, C, stream, lower_only);
 }
 
+hipError_t cgemm_f32in_f64_splitk(int opa, int opb, int M, int N, int K, CView<float> A, CView<float> B,
+                                  double* ws_re, double* ws_im, int ksplit, int lower_only, hipStream_t stream) {
+    return launch<float, double, 128, 64, 8>(opa, opb, M, N, K, A, B, {ws_re, ws_im, N}, stream, lower_only, ksplit,
+                                             (int64_t)M * N);
+}
+
+hipError_t cgemm_f64_splitk(int opa, int opb, int M, int N, int K, CView<double> A, CView<double> B,
+                            double* ws_re, double* ws_im, int ksplit, int lower_only, hipStream_t stream) {
+    return launch<double, double, 128, 64, 8>(opa, opb, M, N, K, A, B, {ws_re, ws_im, N}, stream, lower_only, ksplit,
+                                              (int64_t)M * N);
+}
+
+// C[r][c] = sum_y ws[y][r][c] in split order (FP64 partials)
+__global__ __launch_bounds__(256) void splitk_reduce64_kernel(const double* __restrict__ wre,
+                                                              const double* __restrict__ wim, int nsplit,
+                                                              int64_t M, int64_t N, double* __restrict__ cre,
+                                                              double* __restrict__ cim, int64_t ldc) {
+    const int64_t total = M * N;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        double sr = 0, si = 0;
+        for (int y = 0; y < nsplit; ++y) {
+            sr += wre[y * total + idx];
+            si += wim[y * total + idx];
+        }
+        const int64_t r = idx / N, c = idx % N;
+        cre[r * ldc + c] = sr;
+        cim[r * ldc + c] = si;
+    }
+}
+
+hipError_t splitk_reduce64(const double* ws_re, const double* ws_im, int nsplit, int64_t M, int64_t N, double* c_re,
+                           double* c_im, int64_t ldc, hipStream_t stream) {
+    const int64_t total = M * N;
+    if (total <= 0) return hipSuccess;
+    int64_t g = (total + 255) / 256;
+    if (g > 1048576) g = 1048576;
+    hipLaunchKernelGGL(splitk_reduce64_kernel, dim3((unsigned)g), dim3(256), 0, stream, ws_re, ws_im, nsplit, M, N,
+                       c_re, c_im, ldc);
+    return hipGetLastError();
+}
+
 }  // namespace mpsk

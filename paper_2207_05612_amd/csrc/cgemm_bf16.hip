@@ -8,14 +8,16 @@
 // dropped terms are below 2^-24 of the product, so the result carries about
 // FP32 accuracy; a complex product is four such real products.
 //
-// Tiling: 256 threads = 4 wavefronts (2 x 2), wave tile 64 x 64 complex
-// (2 x 2 MFMA tiles of 32 x 32), block tile 128 x 128, BK = 16 (one MFMA k
-// step).  The split happens when a k-tile is staged from registers into LDS;
+// Tiling: 512 threads = 8 wavefronts (4 x 2), wave tile 64 x 64 complex
+// (2 x 2 MFMA tiles of 32 x 32), block tile 256 x 128, BK = 16 (one MFMA k
+// step), two wavefronts per SIMD so that one wave's MFMAs cover the other's
+// waits.  The split happens when a k-tile is staged from registers into LDS;
 // LDS holds [split][re|im][k/8][row][8] so that the 8 consecutive k of one
 // MFMA lane are one 16-byte read and the 32 lanes of a row group read
-// consecutive 16-byte words.  Two LDS buffers (96 KiB) overlap the next
-// tile's global loads with the current tile's 96 MFMAs per wave.  Block ids
-// map to tiles XCD-first, then in groups of 8 tile rows.
+// consecutive 16-byte words.  Two LDS buffers (144 KiB) overlap the next
+// tile's float4 global loads with the current tile's 96 MFMAs per wave;
+// fragments are read per split pair to keep each wave under 256 registers.
+// Block ids map to tiles XCD-first, then in groups of 8 tile rows.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -57,12 +59,14 @@ __device__ inline void split3(float x, unsigned short& h, unsigned short& m, uns
     l = bf16_bits(r2);
 }
 
-constexpr int SBM = 128, SBN = 128, SBK = 16;
-// LDS element offset of (split s, part p, chunk c, row r, element e) in a [3][2][2][128][8] tile
-__device__ inline int lds_off(int s, int p, int c, int r) { return ((((s * 2 + p) * 2 + c) * 128) + r) * 8; }
+constexpr int SBM = 256, SBN = 128, SBK = 16;
+constexpr int NT = 512;   // threads per block: 8 wavefronts, 4 (m) x 2 (n)
+// LDS element offset of (split s, part p, chunk c, row r) in a [3][2][2][rows][8] tile
+template <int ROWS>
+__device__ inline int lds_off(int s, int p, int c, int r) { return ((((s * 2 + p) * 2 + c) * ROWS) + r) * 8; }
 
 template <bool VEC>
-__global__ __launch_bounds__(256) void cgemm_bf16x3_nt_kernel(SplitArgs g) {
+__global__ __launch_bounds__(NT, 1) void cgemm_bf16x3_nt_kernel(SplitArgs g) {
     __shared__ __attribute__((aligned(16))) unsigned short As[2][3 * 2 * 2 * SBM * 8];
     __shared__ __attribute__((aligned(16))) unsigned short Bs[2][3 * 2 * 2 * SBN * 8];
 
@@ -88,47 +92,36 @@ __global__ __launch_bounds__(256) void cgemm_bf16x3_nt_kernel(SplitArgs g) {
     float* const c_re = g.c_re + blockIdx.y * g.split_stride;
     float* const c_im = g.c_im + blockIdx.y * g.split_stride;
 
-    // staging: each tile plane is 128 rows x 16 k = 512 groups of 4 consecutive k;
-    // thread t stages groups t and t + 256 (row = group / 4, k = 4 (group % 4) .. +3),
-    // so four neighbouring lanes read one 64-byte row segment
-    float4 ar[2], ai[2], br[2], bi[2];
+    // staging: a tile plane is rows x 16 k in groups of 4 consecutive k (4 groups per row);
+    // A has 1024 groups per plane (threads take groups tid, tid + 512), B has 512 (group tid)
+    float4 ar[2], ai[2], br, bi;
 
+    auto ld4 = [&](const float* base, int64_t ld, int row, int rows_valid, int k, bool full_k) -> float4 {
+        if (full_k) {
+            if (row < rows_valid) return *(const float4*)(base + (int64_t)row * ld + k);
+            return make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        float t[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            t[e] = (row < rows_valid && k + e < K) ? base[(int64_t)row * ld + k + e] : 0.f;
+        return make_float4(t[0], t[1], t[2], t[3]);
+    };
     auto load = [&](int k0) {
         const bool full_k = VEC && (k0 + SBK <= K);
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int grp = tid + 256 * u;
-            const int row = grp >> 2, kq = (grp & 3) * 4;
-            const int gr = m0 + row, gc = n0 + row;
-            const int k = k0 + kq;
-            if (full_k) {
-                const int64_t oa = (int64_t)gr * g.lda + k, ob = (int64_t)gc * g.ldb + k;
-                const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-                ar[u] = gr < M ? *(const float4*)(g.a_re + oa) : z;
-                ai[u] = gr < M ? *(const float4*)(g.a_im + oa) : z;
-                br[u] = gc < N ? *(const float4*)(g.b_re + ob) : z;
-                bi[u] = gc < N ? *(const float4*)(g.b_im + ob) : z;
-            } else {
-                float t[4][4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const bool ka = (gr < M) && (k + e < K);
-                    const bool kb = (gc < N) && (k + e < K);
-                    const int64_t oa = (int64_t)gr * g.lda + k + e, ob = (int64_t)gc * g.ldb + k + e;
-                    t[0][e] = ka ? g.a_re[oa] : 0.f;
-                    t[1][e] = ka ? g.a_im[oa] : 0.f;
-                    t[2][e] = kb ? g.b_re[ob] : 0.f;
-                    t[3][e] = kb ? g.b_im[ob] : 0.f;
-                }
-                ar[u] = make_float4(t[0][0], t[0][1], t[0][2], t[0][3]);
-                ai[u] = make_float4(t[1][0], t[1][1], t[1][2], t[1][3]);
-                br[u] = make_float4(t[2][0], t[2][1], t[2][2], t[2][3]);
-                bi[u] = make_float4(t[3][0], t[3][1], t[3][2], t[3][3]);
-            }
+            const int grp = tid + NT * u;
+            const int row = grp >> 2, k = k0 + (grp & 3) * 4;
+            ar[u] = ld4(g.a_re, g.lda, m0 + row, M, k, full_k);
+            ai[u] = ld4(g.a_im, g.lda, m0 + row, M, k, full_k);
         }
+        const int row = tid >> 2, k = k0 + (tid & 3) * 4;
+        br = ld4(g.b_re, g.ldb, n0 + row, N, k, full_k);
+        bi = ld4(g.b_im, g.ldb, n0 + row, N, k, full_k);
     };
     typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
-    auto put = [&](unsigned short* base, int p, int row, int kq, float4 v) {
+    auto put = [&](unsigned short* base, int rows, int p, int row, int kq, float4 v) {
         const float x[4] = {v.x, v.y, v.z, v.w};
         u16x4 h, m, l;
 #pragma unroll
@@ -138,20 +131,23 @@ __global__ __launch_bounds__(256) void cgemm_bf16x3_nt_kernel(SplitArgs g) {
             h[e] = a; m[e] = b; l[e] = c;
         }
         const int chunk = kq >> 3, sub = kq & 7;
-        *(u16x4*)&base[lds_off(0, p, chunk, row) + sub] = h;
-        *(u16x4*)&base[lds_off(1, p, chunk, row) + sub] = m;
-        *(u16x4*)&base[lds_off(2, p, chunk, row) + sub] = l;
+        const int plane = 2 * rows * 8;   // elements per (split, part) for both chunks
+        const int off = ((p * 2 + chunk) * rows + row) * 8 + sub;
+        *(u16x4*)&base[off] = h;
+        *(u16x4*)&base[off + 2 * plane] = m;
+        *(u16x4*)&base[off + 4 * plane] = l;
     };
     auto store = [&](int buf) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int grp = tid + 256 * u;
+            const int grp = tid + NT * u;
             const int row = grp >> 2, kq = (grp & 3) * 4;
-            put(As[buf], 0, row, kq, ar[u]);
-            put(As[buf], 1, row, kq, ai[u]);
-            put(Bs[buf], 0, row, kq, br[u]);
-            put(Bs[buf], 1, row, kq, bi[u]);
+            put(As[buf], SBM, 0, row, kq, ar[u]);
+            put(As[buf], SBM, 1, row, kq, ai[u]);
         }
+        const int row = tid >> 2, kq = (tid & 3) * 4;
+        put(Bs[buf], SBN, 0, row, kq, br);
+        put(Bs[buf], SBN, 1, row, kq, bi);
     };
 
     f32x16 acc_re[2][2], acc_im[2][2];
@@ -169,41 +165,36 @@ __global__ __launch_bounds__(256) void cgemm_bf16x3_nt_kernel(SplitArgs g) {
 
     const int lrow = lane & 31;
     const int lchunk = lane >> 5;
-    // the six kept split pairs (x split, y split)
-    constexpr int PA[6] = {0, 0, 1, 1, 0, 2};
-    constexpr int PB[6] = {0, 1, 0, 1, 2, 0};
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
         if (kt + 1 < nk) load(kbeg + (kt + 1) * SBK);
-        bf16x8 fa[2][2][3], fb[2][2][3], fbn[2][3];   // [tile][re|im][split]; fbn = -B_im
+        // kept split pairs: (0,0) (0,1) (0,2) (1,0) (1,1) (2,0), grouped by the A split
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
-#pragma unroll
-                for (int s = 0; s < 3; ++s) {
-                    fa[i][p][s] = *(const bf16x8*)&As[buf][lds_off(s, p, lchunk, wm0 + i * 32 + lrow)];
-                    fb[i][p][s] = *(const bf16x8*)&Bs[buf][lds_off(s, p, lchunk, wn0 + i * 32 + lrow)];
-                }
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int s = 0; s < 3; ++s) {
-                u16x8 t = __builtin_bit_cast(u16x8, fb[j][1][s]);
-                t ^= (unsigned short)0x8000;
-                fbn[j][s] = __builtin_bit_cast(bf16x8, t);
-            }
-#pragma unroll
-        for (int q = 0; q < 6; ++q)
+        for (int sa = 0; sa < 3; ++sa) {
+            bf16x8 fa[2][2];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
+                for (int p = 0; p < 2; ++p)
+                    fa[i][p] = *(const bf16x8*)&As[buf][lds_off<SBM>(sa, p, lchunk, wm0 + i * 32 + lrow)];
+            for (int sb = 0; sb < 3 - sa; ++sb) {
+#pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][0][PA[q]], fb[j][0][PB[q]], acc_re[i][j], 0, 0, 0);
-                    acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][0][PA[q]], fb[j][1][PB[q]], acc_im[i][j], 0, 0, 0);
-                    acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][1][PA[q]], fbn[j][PB[q]], acc_re[i][j], 0, 0, 0);
-                    acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][1][PA[q]], fb[j][0][PB[q]], acc_im[i][j], 0, 0, 0);
+                    const bf16x8 fbr = *(const bf16x8*)&Bs[buf][lds_off<SBN>(sb, 0, lchunk, wn0 + j * 32 + lrow)];
+                    const bf16x8 fbi = *(const bf16x8*)&Bs[buf][lds_off<SBN>(sb, 1, lchunk, wn0 + j * 32 + lrow)];
+                    u16x8 t = __builtin_bit_cast(u16x8, fbi);
+                    t ^= (unsigned short)0x8000;
+                    const bf16x8 fbn = __builtin_bit_cast(bf16x8, t);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][0], fbr, acc_re[i][j], 0, 0, 0);
+                        acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][0], fbi, acc_im[i][j], 0, 0, 0);
+                        acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][1], fbn, acc_re[i][j], 0, 0, 0);
+                        acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][1], fbr, acc_im[i][j], 0, 0, 0);
+                    }
                 }
+            }
+        }
         if (kt + 1 < nk) store(buf ^ 1);
         __syncthreads();
     }
@@ -247,9 +238,9 @@ static hipError_t launch_split(int M, int N, int K, CView<float> A, CView<float>
                      ((((uintptr_t)A.re) | ((uintptr_t)A.im) | ((uintptr_t)B.re) | ((uintptr_t)B.im)) & 15) == 0;
     const dim3 grid((unsigned)nblocks, (unsigned)ksplit);
     if (vec)
-        hipLaunchKernelGGL(cgemm_bf16x3_nt_kernel<true>, grid, dim3(256), 0, stream, g);
+        hipLaunchKernelGGL(cgemm_bf16x3_nt_kernel<true>, grid, dim3(NT), 0, stream, g);
     else
-        hipLaunchKernelGGL(cgemm_bf16x3_nt_kernel<false>, grid, dim3(256), 0, stream, g);
+        hipLaunchKernelGGL(cgemm_bf16x3_nt_kernel<false>, grid, dim3(NT), 0, stream, g);
     return hipGetLastError();
 }
 

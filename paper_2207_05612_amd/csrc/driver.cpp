@@ -363,6 +363,7 @@ struct mps_state {
     rocblas_handle blas = nullptr;
     // scratch
     Planar<float> splitws;         // partial sums of split-K FP32 / split-precision GEMMs
+    Planar<double> splitws64;      // partial sums of split-K FP64 Gram matrices
     Raw<double> dscal;             // small device scalars
     Raw<double> partial;           // reduction partials
     bool prof = false;
@@ -488,6 +489,36 @@ void gemm_split(mps_state* st, int cls, int64_t M, int64_t N, int64_t K, const f
     t.done();
 }
 
+// Hermitian Gram product (lower tiles only) with FP64 accumulation; long k
+// ranges are split so that enough tiles run and partial sums add in FP64.
+template <typename TIn>
+void gram_product(mps_state* st, int opa, int opb, int dim, int64_t K, const TIn* re, const TIn* im, int64_t ld,
+                  double* out_re, double* out_im) {
+    const int64_t tiles = (int64_t)((dim + 127) / 128) * ((dim + 63) / 64) / 2 + 1;   // lower half
+    int ks = 1;
+    if (K >= 4096) ks = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)32, K / 2048, (1024 + tiles - 1) / tiles}));
+    const int chunks = splitk_chunks((int)K, ks, 8);
+    if (chunks > 1) {
+        st->splitws64.ensure((int64_t)dim * dim * chunks, st->stream);
+        if (sizeof(TIn) == 4)
+            HIPCHK(cgemm_f32in_f64_splitk(opa, opb, dim, dim, (int)K, {(const float*)re, (const float*)im, ld},
+                                          {(const float*)re, (const float*)im, ld}, st->splitws64.re(),
+                                          st->splitws64.im(), ks, 1, st->stream));
+        else
+            HIPCHK(cgemm_f64_splitk(opa, opb, dim, dim, (int)K, {(const double*)re, (const double*)im, ld},
+                                    {(const double*)re, (const double*)im, ld}, st->splitws64.re(),
+                                    st->splitws64.im(), ks, 1, st->stream));
+        HIPCHK(splitk_reduce64(st->splitws64.re(), st->splitws64.im(), chunks, dim, dim, out_re, out_im, dim,
+                               st->stream));
+    } else if (sizeof(TIn) == 4) {
+        HIPCHK(cgemm_f32in_f64(opa, opb, dim, dim, (int)K, {(const float*)re, (const float*)im, ld},
+                               {(const float*)re, (const float*)im, ld}, {out_re, out_im, dim}, st->stream, 1));
+    } else {
+        HIPCHK(cgemm_f64(opa, opb, dim, dim, (int)K, {(const double*)re, (const double*)im, ld},
+                         {(const double*)re, (const double*)im, ld}, {out_re, out_im, dim}, st->stream, 1));
+    }
+}
+
 // =========================================================== the engine ====
 template <typename R>
 struct Engine {
@@ -577,12 +608,10 @@ struct Engine {
             {
                 // Hermitian product: rows (rows + 1) / 2 distinct entries of cols MACs each
                 Timer t(st, MPS_KCLASS_GRAM, 4.0 * rows * (rows + 1) * cols, 2.0 * sizeof(R) * rows * cols + 8.0 * rows * (rows + 1));
-                if (m64_re) {
-                    HIPCHK(cgemm_f64(OP_N, OP_C, dim, dim, (int)cols, {m64_re, m64_im, cols}, {m64_re, m64_im, cols},
-                                     {GR.re(), GR.im(), dim}, s, 1));
-                } else {
-                    gram_from_working(m_re, m_im, dim, cols);
-                }
+                if (m64_re)
+                    gram_product<double>(st, OP_N, OP_C, dim, cols, m64_re, m64_im, cols, GR.re(), GR.im());
+                else
+                    gram_product<R>(st, OP_N, OP_C, dim, cols, m_re, m_im, cols, GR.re(), GR.im());
                 t.done();
             }
             eigh(dim);
@@ -611,8 +640,7 @@ struct Engine {
         GR.ensure((int64_t)dim * dim, s);
         {
             Timer t(st, MPS_KCLASS_GRAM, 4.0 * cols * (cols + 1) * rows, 16.0 * rows * cols + 8.0 * cols * (cols + 1));
-            HIPCHK(cgemm_f64(OP_C, OP_N, dim, dim, (int)rows, {m64_re, m64_im, cols}, {m64_re, m64_im, cols},
-                             {GR.re(), GR.im(), dim}, s, 1));
+            gram_product<double>(st, OP_C, OP_N, dim, rows, m64_re, m64_im, cols, GR.re(), GR.im());
             t.done();
         }
         eigh(dim);
@@ -644,8 +672,6 @@ struct Engine {
         tr.caseA = false;
         return tr;
     }
-
-    void gram_from_working(const R* m_re, const R* m_im, int dim, int64_t cols);
 
     void set_scalar(int idx, double v) {
         HIPCHK(hipMemcpyAsync(st->dscal.p + idx, &v, sizeof(double), hipMemcpyHostToDevice, s));
@@ -851,17 +877,6 @@ struct Engine {
     }
 };
 
-template <>
-void Engine<float>::gram_from_working(const float* m_re, const float* m_im, int dim, int64_t cols) {
-    HIPCHK(cgemm_f32in_f64(OP_N, OP_C, dim, dim, (int)cols, {m_re, m_im, cols}, {m_re, m_im, cols},
-                           {GR.re(), GR.im(), dim}, s, 1));
-}
-template <>
-void Engine<double>::gram_from_working(const double* m_re, const double* m_im, int dim, int64_t cols) {
-    HIPCHK(cgemm_f64(OP_N, OP_C, dim, dim, (int)cols, {m_re, m_im, cols}, {m_re, m_im, cols},
-                     {GR.re(), GR.im(), dim}, s, 1));
-}
-
 // Forward-layout FP64 copy of site k into dst ([D_k][2][D_k+1]).
 void forward_tensor(const mps_state* st, int k, Planar<double>& dst) {
     const int64_t sz = (int64_t)st->bond[k] * 2 * st->bond[k + 1];
@@ -982,6 +997,7 @@ mps_status mps_destroy(mps_state* st) {
     st->dscal.release(st->stream);
     st->partial.release(st->stream);
     st->splitws.release(st->stream);
+    st->splitws64.release(st->stream);
     for (auto& p : st->pending) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);

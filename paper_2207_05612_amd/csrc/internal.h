@@ -51,6 +51,13 @@ hipError_t splitk_reduce(const float* ws_re, const float* ws_im, int nsplit, int
                          float* c_im, int64_t ldc, hipStream_t stream);
 hipError_t cgemm_bf16x3_nt_splitk(int M, int N, int K, CView<float> A, CView<float> B, float* ws_re,
                                   float* ws_im, int ksplit, hipStream_t stream);
+// FP64-accumulating split-K variants (BK = 8), used by the Gram matrices of the truncation
+hipError_t cgemm_f32in_f64_splitk(int opa, int opb, int M, int N, int K, CView<float> A, CView<float> B,
+                                  double* ws_re, double* ws_im, int ksplit, int lower_only, hipStream_t stream);
+hipError_t cgemm_f64_splitk(int opa, int opb, int M, int N, int K, CView<double> A, CView<double> B,
+                            double* ws_re, double* ws_im, int ksplit, int lower_only, hipStream_t stream);
+hipError_t splitk_reduce64(const double* ws_re, const double* ws_im, int nsplit, int64_t M, int64_t N, double* c_re,
+                           double* c_im, int64_t ldc, hipStream_t stream);
 
 // Split-precision complex GEMM: C (M x N) = A (M x K) B^T with B stored N x K,
 // FP32 operands split into three BF16 terms, six BF16 MFMA products per real
