@@ -214,6 +214,23 @@ mps_status mps_kernel_stats(const mps_state* state, int kernel_class, int64_t* l
 mps_status mps_kernel_selftest_cgemm(int precision, int opa, int opb, int M, int N, int K,
                                      const double* a, const double* b, double* c);
 
+/* Run the FP64 Hermitian eigensolver of the truncation (Sec. VI.A: the kept
+ * singular values are the largest eigenvalues of the Gram matrix of the
+ * local tensor) once on host data.  a: n x n Hermitian, HOST, interleaved
+ * complex128, row-major (only the lower triangle, row >= column, is read).
+ * method 0: rocSOLVER's dense solver; method 1: the persistent tridiagonal
+ * reduction kernel (n <= 2048, else method 0 is used) followed by
+ * rocSOLVER's tridiagonal divide and conquer and back-transformation.
+ * Outputs (HOST): w[n] eigenvalues in ascending order; z[n * n] interleaved
+ * complex128, column j at z[2 (i + j n)] is the eigenvector of w[j];
+ * *used (may be NULL) the method that actually ran (method 1 falls back to
+ * method 0 when the cooperative launch is refused or gives up waiting).
+ * MPS_ERR_NUMERIC when the solver does not converge.  For kernel-level
+ * parity tests; the compression step calls the same routine on the device
+ * Gram matrix (choose the method with the environment variable
+ * MPS_EIGENSOLVER = rocsolver | persistent, default persistent). */
+mps_status mps_kernel_selftest_eigh(int n, const double* a, int method, double* w, double* z, int* used);
+
 #ifdef __cplusplus
 }
 #endif

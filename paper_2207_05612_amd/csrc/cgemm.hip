@@ -63,6 +63,8 @@ struct GemmArgs {
     int lower_only;   // skip tiles that hold no element with column <= row
     int kchunk;       // k range of split blockIdx.y: [y kchunk, (y+1) kchunk)
     int64_t split_stride;   // C offset of split y (partial sums); 0 without split
+    int sub;          // C -= A B instead of C = A B
+    int64_t sa, sb, sc;     // batch strides (elements) of A, B, C: batch z = blockIdx.z
 };
 
 template <typename TIn, typename TAcc, int OPA, int OPB, int BM, int BN, int BK>
@@ -102,8 +104,13 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
     // split-K: this block sums k in [kbeg, K) of its own chunk
     const int kbeg = blockIdx.y * g.kchunk;
     const int K = min(g.K, kbeg + g.kchunk);
-    TAcc* const c_re = g.c_re + blockIdx.y * g.split_stride;
-    TAcc* const c_im = g.c_im + blockIdx.y * g.split_stride;
+    const int64_t bz = blockIdx.z;
+    TAcc* const c_re = g.c_re + blockIdx.y * g.split_stride + bz * g.sc;
+    TAcc* const c_im = g.c_im + blockIdx.y * g.split_stride + bz * g.sc;
+    const TIn* const a_re = g.a_re + bz * g.sa;
+    const TIn* const a_im = g.a_im + bz * g.sa;
+    const TIn* const b_re = g.b_re + bz * g.sb;
+    const TIn* const b_im = g.b_im + bz * g.sb;
 
     TIn ra_re[EA], ra_im[EA], rb_re[EB], rb_im[EB];
 
@@ -118,8 +125,8 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
             TIn vr = 0, vi = 0;
             if (gm_ < M && gk < K) {
                 const int64_t off = (OPA == OP_N) ? (int64_t)gm_ * g.lda + gk : (int64_t)gk * g.lda + gm_;
-                vr = g.a_re[off];
-                vi = g.a_im[off];
+                vr = a_re[off];
+                vi = a_im[off];
                 if (OPA == OP_C) vi = -vi;
             }
             ra_re[i] = vr;
@@ -135,8 +142,8 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
             TIn vr = 0, vi = 0;
             if (gn_ < N && gk < K) {
                 const int64_t off = (OPB == OP_N) ? (int64_t)gk * g.ldb + gn_ : (int64_t)gn_ * g.ldb + gk;
-                vr = g.b_re[off];
-                vi = g.b_im[off];
+                vr = b_re[off];
+                vi = b_im[off];
                 if (OPB == OP_C) vi = -vi;
             }
             rb_re[i] = vr;
@@ -228,8 +235,13 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
                 const int c = n0 + wn0 + j * MT + lrow;
                 if (r < M && c < N) {
                     const int64_t off = (int64_t)r * g.ldc + c;
-                    c_re[off] = acc_re[i][j][v];
-                    c_im[off] = acc_im[i][j][v];
+                    if (g.sub) {
+                        c_re[off] -= acc_re[i][j][v];
+                        c_im[off] -= acc_im[i][j][v];
+                    } else {
+                        c_re[off] = acc_re[i][j][v];
+                        c_im[off] = acc_im[i][j][v];
+                    }
                 }
             }
 }
@@ -237,7 +249,8 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
 template <typename TIn, typename TAcc, int BM, int BN, int BK>
 static hipError_t launch(int opa, int opb, int M, int N, int K, CView<TIn> A, CView<TIn> B,
                          CViewMut<TAcc> C, hipStream_t stream, int lower_only = 0, int ksplit = 1,
-                         int64_t split_stride = 0) {
+                         int64_t split_stride = 0, int sub = 0, int batch = 1, int64_t sa = 0, int64_t sb = 0,
+                         int64_t sc = 0) {
     if (M <= 0 || N <= 0) return hipSuccess;
     GemmArgs<TIn, TAcc> g;
     g.a_re = A.re; g.a_im = A.im; g.lda = A.ld;
@@ -247,6 +260,11 @@ static hipError_t launch(int opa, int opb, int M, int N, int K, CView<TIn> A, CV
     g.gm = (M + BM - 1) / BM;
     g.gn = (N + BN - 1) / BN;
     g.lower_only = lower_only;
+    g.sub = sub;
+    g.sa = sa;
+    g.sb = sb;
+    g.sc = sc;
+    if (batch < 1 || batch > 65535) return hipErrorInvalidValue;
     if (ksplit < 1) ksplit = 1;
     g.kchunk = (((K + ksplit - 1) / ksplit) + BK - 1) / BK * BK;
     if (g.kchunk < BK) g.kchunk = BK;
@@ -255,7 +273,7 @@ static hipError_t launch(int opa, int opb, int M, int N, int K, CView<TIn> A, CV
     g.split_stride = ksplit > 1 ? split_stride : 0;
     const int64_t nblocks = (int64_t)g.gm * g.gn;
     if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
-    dim3 grid((unsigned)nblocks, (unsigned)ksplit), block(256);
+    dim3 grid((unsigned)nblocks, (unsigned)ksplit, (unsigned)batch), block(256);
 #define MPS_GEMM_CASE(OA, OB)                                                                     \
     if (opa == OA && opb == OB) {                                                                 \
         hipLaunchKernelGGL((cgemm_kernel<TIn, TAcc, OA, OB, BM, BN, BK>), grid, block, 0, stream, g); \
@@ -323,6 +341,24 @@ hipError_t splitk_reduce(const float* ws_re, const float* ws_im, int nsplit, int
 hipError_t cgemm_f64(int opa, int opb, int M, int N, int K, CView<double> A, CView<double> B,
                      CViewMut<double> C, hipStream_t stream, int lower_only) {
     return launch<double, double, 128, 64, 8>(opa, opb, M, N, K, A, B, C, stream, lower_only);
+}
+
+hipError_t cgemm_f64_sub(int opa, int opb, int M, int N, int K, CView<double> A, CView<double> B, CViewMut<double> C,
+                         hipStream_t stream) {
+    return launch<double, double, 128, 64, 8>(opa, opb, M, N, K, A, B, C, stream, 0, 1, 0, 1);
+}
+
+hipError_t cgemm_f64_batched(int opa, int opb, int M, int N, int K, CView<double> A, int64_t sa, CView<double> B,
+                             int64_t sb, CViewMut<double> C, int64_t sc, int batch, hipStream_t stream) {
+    return launch<double, double, 128, 64, 8>(opa, opb, M, N, K, A, B, C, stream, 0, 1, 0, 0, batch, sa, sb, sc);
+}
+
+hipError_t cgemm_f64_batched_splitk(int opa, int opb, int M, int N, int K, CView<double> A, int64_t sa,
+                                    CView<double> B, int64_t sb, double* ws_re, double* ws_im, int ksplit, int batch,
+                                    hipStream_t stream) {
+    // partial sums of split y, batch z at ws + (y batch + z) M N: reduce as (batch M) x N
+    return launch<double, double, 128, 64, 8>(opa, opb, M, N, K, A, B, {ws_re, ws_im, N}, stream, 0, ksplit,
+                                              (int64_t)batch * M * N, 0, batch, sa, sb, (int64_t)M * N);
 }
 
 hipError_t cgemm_f32in_f64(int opa, int opb, int M, int N, int K, CView<float> A,

@@ -32,6 +32,7 @@
 #include <functional>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -364,6 +365,13 @@ struct mps_state {
     // scratch
     Planar<float> splitws;         // partial sums of split-K FP32 / split-precision GEMMs
     Planar<double> splitws64;      // partial sums of split-K FP64 Gram matrices
+    // second stream: the right block of the next two-site step runs on it
+    // while the current step's truncation runs on the state's stream
+    hipStream_t stream2 = nullptr;
+    Planar<float> splitws2;
+    hipEvent_t ev_order[4] = {nullptr, nullptr, nullptr, nullptr};
+    int eigh_method = 1;           // EIGH_PERSISTENT, or EIGH_ROCSOLVER
+    bool overlap_right = true;     // right blocks on the second stream
     Raw<double> dscal;             // small device scalars
     Raw<double> partial;           // reduction partials
     bool prof = false;
@@ -389,17 +397,19 @@ struct Timer {
     mps_state* st;
     int cls;
     double flops, bytes;
+    hipStream_t strm;
     hipEvent_t a = nullptr;
-    Timer(mps_state* s, int c, double f, double b) : st(s), cls(c), flops(f), bytes(b) {
+    Timer(mps_state* s, int c, double f, double b, hipStream_t on = nullptr)
+        : st(s), cls(c), flops(f), bytes(b), strm(on ? on : s->stream) {
         if (st->prof) {
             a = get_event(st);
-            HIPCHK(hipEventRecord(a, st->stream));
+            HIPCHK(hipEventRecord(a, strm));
         }
     }
     void done() {
         if (!st->prof) return;
         hipEvent_t b = get_event(st);
-        HIPCHK(hipEventRecord(b, st->stream));
+        HIPCHK(hipEventRecord(b, strm));
         st->pending.push_back({cls, a, b, flops, bytes});
     }
 };
@@ -407,6 +417,7 @@ struct Timer {
 void flush_timings(mps_state* st) {
     if (st->pending.empty()) return;
     HIPCHK(hipStreamSynchronize(st->stream));
+    if (st->stream2) HIPCHK(hipStreamSynchronize(st->stream2));
     for (auto& p : st->pending) {
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
@@ -422,6 +433,13 @@ void flush_timings(mps_state* st) {
 }
 
 // ---------------------------------------------------------- GEMM helpers ---
+// A stream and the split-K workspace that only work on that stream may use.
+struct Lane {
+    hipStream_t s;
+    Planar<float>* ws;
+};
+Lane main_lane(mps_state* st) { return Lane{st->stream, &st->splitws}; }
+
 template <typename R>
 hipError_t gemm_raw(int opa, int opb, int M, int N, int K, const R* ar, const R* ai, int64_t lda,
                     const R* br, const R* bi, int64_t ldb, R* cr, R* ci, int64_t ldc, hipStream_t s);
@@ -452,39 +470,43 @@ int splitk_for(int64_t M, int64_t N, int64_t K) {
 
 template <typename R>
 void gemm(mps_state* st, int cls, int opa, int opb, int64_t M, int64_t N, int64_t K, const R* ar,
-          const R* ai, int64_t lda, const R* br, const R* bi, int64_t ldb, R* cr, R* ci, int64_t ldc) {
+          const R* ai, int64_t lda, const R* br, const R* bi, int64_t ldb, R* cr, R* ci, int64_t ldc,
+          const Lane* lane = nullptr) {
     if (M > 0x7fffffff || N > 0x7fffffff || K > 0x7fffffff) fail(MPS_ERR_ARG, "GEMM dimension too large");
+    const Lane ln = lane ? *lane : main_lane(st);
     const double fl = 8.0 * (double)M * (double)N * (double)K;
     const double by = 2.0 * sizeof(R) * ((double)M * K + (double)K * N + (double)M * N);
-    Timer t(st, cls, fl, by);
+    Timer t(st, cls, fl, by, ln.s);
     const int ks = sizeof(R) == 4 ? splitk_chunks((int)K, splitk_for(M, N, K), 16) : 1;
     if (ks > 1) {
-        st->splitws.ensure(M * N * ks, st->stream);
+        ln.ws->ensure(M * N * ks, ln.s);
         HIPCHK(cgemm_f32_splitk(opa, opb, (int)M, (int)N, (int)K, {(const float*)ar, (const float*)ai, lda},
-                                {(const float*)br, (const float*)bi, ldb}, st->splitws.re(), st->splitws.im(),
-                                splitk_for(M, N, K), st->stream));
-        HIPCHK(splitk_reduce(st->splitws.re(), st->splitws.im(), ks, M, N, (float*)cr, (float*)ci, ldc, st->stream));
+                                {(const float*)br, (const float*)bi, ldb}, ln.ws->re(), ln.ws->im(),
+                                splitk_for(M, N, K), ln.s));
+        HIPCHK(splitk_reduce(ln.ws->re(), ln.ws->im(), ks, M, N, (float*)cr, (float*)ci, ldc, ln.s));
     } else {
-        HIPCHK(gemm_raw<R>(opa, opb, (int)M, (int)N, (int)K, ar, ai, lda, br, bi, ldb, cr, ci, ldc, st->stream));
+        HIPCHK(gemm_raw<R>(opa, opb, (int)M, (int)N, (int)K, ar, ai, lda, br, bi, ldb, cr, ci, ldc, ln.s));
     }
     t.done();
 }
 
 // Split-precision (BF16 x 3) complex GEMM, C = A B^T with both operands k-contiguous.
 void gemm_split(mps_state* st, int cls, int64_t M, int64_t N, int64_t K, const float* ar, const float* ai,
-                int64_t lda, const float* br, const float* bi, int64_t ldb, float* cr, float* ci, int64_t ldc) {
+                int64_t lda, const float* br, const float* bi, int64_t ldb, float* cr, float* ci, int64_t ldc,
+                const Lane* lane = nullptr) {
     if (M > 0x7fffffff || N > 0x7fffffff || K > 0x7fffffff) fail(MPS_ERR_ARG, "GEMM dimension too large");
+    const Lane ln = lane ? *lane : main_lane(st);
     const double fl = 8.0 * (double)M * (double)N * (double)K;
     const double by = 8.0 * ((double)M * K + (double)K * N + (double)M * N);
-    Timer t(st, cls, fl, by);
+    Timer t(st, cls, fl, by, ln.s);
     const int ks = splitk_chunks((int)K, splitk_for(M, N, K), 16);
     if (ks > 1) {
-        st->splitws.ensure(M * N * ks, st->stream);
-        HIPCHK(cgemm_bf16x3_nt_splitk((int)M, (int)N, (int)K, {ar, ai, lda}, {br, bi, ldb}, st->splitws.re(),
-                                      st->splitws.im(), splitk_for(M, N, K), st->stream));
-        HIPCHK(splitk_reduce(st->splitws.re(), st->splitws.im(), ks, M, N, cr, ci, ldc, st->stream));
+        ln.ws->ensure(M * N * ks, ln.s);
+        HIPCHK(cgemm_bf16x3_nt_splitk((int)M, (int)N, (int)K, {ar, ai, lda}, {br, bi, ldb}, ln.ws->re(),
+                                      ln.ws->im(), splitk_for(M, N, K), ln.s));
+        HIPCHK(splitk_reduce(ln.ws->re(), ln.ws->im(), ks, M, N, cr, ci, ldc, ln.s));
     } else {
-        HIPCHK(cgemm_bf16x3_nt((int)M, (int)N, (int)K, {ar, ai, lda}, {br, bi, ldb}, {cr, ci, ldc}, st->stream));
+        HIPCHK(cgemm_bf16x3_nt((int)M, (int)N, (int)K, {ar, ai, lda}, {br, bi, ldb}, {cr, ci, ldc}, ln.s));
     }
     t.done();
 }
@@ -519,6 +541,153 @@ void gram_product(mps_state* st, int opa, int opb, int dim, int64_t K, const TIn
     }
 }
 
+// ================================================== FP64 eigensolver ====
+enum { EIGH_ROCSOLVER = 0, EIGH_PERSISTENT = 1 };
+
+struct EighWork {
+    Raw<double> Z, evals, evwork, tau;   // Z: eigenvectors (complex for the library solver, real of T otherwise)
+    Planar<double> vh, S, T, Y, W, ws;   // reflectors (conjugated rows) and back-transformation scratch
+    Raw<char> trws;
+    Raw<int> info;
+    int method_used = EIGH_ROCSOLVER;
+    void release(hipStream_t s) {
+        Z.release(s); evals.release(s); evwork.release(s); tau.release(s);
+        vh.release(s); S.release(s); T.release(s); Y.release(s); W.release(s); ws.release(s);
+        trws.release(s); info.release(s);
+    }
+};
+
+// C = op(A) op(B) in FP64 with the k range split for short, wide products.
+void gemm64_long_k(mps_state* st, EighWork& wk, int opa, int opb, int M, int N, int K, CView<double> A,
+                   CView<double> B, CViewMut<double> C) {
+    const int64_t tiles = (int64_t)((M + 127) / 128) * ((N + 63) / 64);
+    int ks = 1;
+    if (K >= 128 && tiles < 256) ks = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)32, K / 64, (512 + tiles - 1) / tiles}));
+    const int chunks = splitk_chunks(K, ks, 8);
+    if (chunks > 1) {
+        wk.ws.ensure((int64_t)M * N * chunks, st->stream);
+        HIPCHK(cgemm_f64_splitk(opa, opb, M, N, K, A, B, wk.ws.re(), wk.ws.im(), ks, 0, st->stream));
+        HIPCHK(splitk_reduce64(wk.ws.re(), wk.ws.im(), chunks, M, N, C.re, C.im, C.ld, st->stream));
+    } else {
+        HIPCHK(cgemm_f64(opa, opb, M, N, K, A, B, C, st->stream));
+    }
+}
+
+// Eigen-decomposition of the Hermitian dim x dim matrix given by the lower
+// triangle (row >= column) of the row-major planar array (re, im).  On
+// return wk.evals holds the eigenvalues in ascending order; top_eigvecs()
+// then forms the eigenvectors of the largest ones.
+// EIGH_PERSISTENT: tridiagonal reduction by the persistent kernel, rocSOLVER's
+// divide and conquer on the real tridiagonal matrix, and (in top_eigvecs) the
+// blocked back-transformation by the reflectors on the kept columns only.
+// It falls back to rocSOLVER's dense solver when the cooperative launch is
+// refused or gives up waiting.
+// after_reduce (may be null) is called once the reduction no longer needs
+// the whole device: work that the caller queues on other streams from it
+// does not compete with the cooperative launch.
+void eigh_gram(mps_state* st, EighWork& wk, const double* re, const double* im, int dim, int method,
+               const std::function<void()>* after_reduce = nullptr) {
+    const hipStream_t s = st->stream;
+    wk.evals.ensure(dim, s);
+    wk.evwork.ensure(dim, s);
+    wk.info.ensure(1, s);
+    if (method == EIGH_PERSISTENT && dim >= 2 && dim <= hetrd_max_n()) {
+        wk.Z.ensure(2 * (int64_t)dim * dim, s);      // full matrix first, real eigenvectors after
+        // reflectors padded to whole blocks of the back-transformation with zero rows (tau = 0)
+        const int nb = wy_block(), nblk = (dim - 1 + nb - 1) / nb, npad = nblk * nb - (dim - 1);
+        wk.tau.ensure(2 * (int64_t)nblk * nb, s);
+        wk.vh.ensure((int64_t)nblk * nb * dim, s);
+        if (npad > 0) {
+            HIPCHK(hipMemsetAsync(wk.tau.p + 2 * (int64_t)(dim - 1), 0, sizeof(double) * 2 * npad, s));
+            HIPCHK(hipMemsetAsync(wk.vh.re() + (int64_t)(dim - 1) * dim, 0, sizeof(double) * npad * dim, s));
+            HIPCHK(hipMemsetAsync(wk.vh.im() + (int64_t)(dim - 1) * dim, 0, sizeof(double) * npad * dim, s));
+        }
+        const size_t wsb = hetrd_workspace_bytes(dim);
+        wk.trws.ensure((int64_t)wsb, s);
+        {
+            Timer t(st, MPS_KCLASS_OTHER, 0, 32.0 * dim * dim);
+            HIPCHK(hermitian_full_colmajor(re, im, dim, wk.Z.p, s));
+            t.done();
+        }
+        Timer t(st, MPS_KCLASS_EIGH, 0, 0);
+        int* abort_dev = nullptr;
+        int aborted = 1;
+        if (hetrd_persistent(wk.Z.p, dim, wk.evals.p, wk.evwork.p, wk.tau.p, wk.vh.re(), wk.vh.im(), wk.trws.p, wsb,
+                             &abort_dev, s) == hipSuccess) {
+            HIPCHK(hipMemcpyAsync(&aborted, abort_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        } else {
+            (void)hipGetLastError();
+        }
+        if (!aborted) {
+            if (after_reduce) (*after_reduce)();
+            rocblas_status rs = rocsolver_dstedc(st->blas, rocblas_evect_tridiagonal, dim, wk.evals.p, wk.evwork.p,
+                                                 wk.Z.p, dim, wk.info.p);
+            t.done();
+            if (rs != rocblas_status_success) fail(MPS_ERR_DEVICE, "rocsolver_dstedc failed: status " + std::to_string((int)rs));
+            wk.method_used = EIGH_PERSISTENT;
+            return;
+        }
+        t.done();
+    }
+    wk.Z.ensure(2 * (int64_t)dim * dim, s);
+    {
+        Timer t(st, MPS_KCLASS_OTHER, 0, 32.0 * dim * dim);
+        HIPCHK(pack_hermitian(re, im, dim, wk.Z.p, s));
+        t.done();
+    }
+    Timer t(st, MPS_KCLASS_EIGH, 0, 0);
+    rocblas_status rs = rocsolver_zheevd(st->blas, rocblas_evect_original, rocblas_fill_upper, dim,
+                                         (rocblas_double_complex*)wk.Z.p, dim, wk.evals.p, wk.evwork.p, wk.info.p);
+    t.done();
+    if (rs != rocblas_status_success) fail(MPS_ERR_DEVICE, "rocsolver_zheevd failed: status " + std::to_string((int)rs));
+    wk.method_used = EIGH_ROCSOLVER;
+    if (after_reduce) (*after_reduce)();
+}
+
+// Eigenvectors of the k largest eigenvalues after eigh_gram(), as planar
+// row-major dim x k (largest first).  For the persistent path this applies
+// Q = H_0 H_1 ... H_{dim-2} to the eigenvectors of T in blocks b of nb
+// reflectors, Q_b = I - V_b T_b V_b^H, last block first.  The factors of all
+// blocks are formed up front (S_b = V_b^H V_b, T_b, Y_b = T_b V_b^H, three
+// batched launches); each block then costs two products on the rows below it:
+//   W = Y_b U,  U -= V_b W.
+void top_eigvecs(mps_state* st, EighWork& wk, int dim, int k, double* out_re, double* out_im) {
+    const hipStream_t s = st->stream;
+    if (wk.method_used == EIGH_ROCSOLVER) {
+        HIPCHK(take_top_eigvecs(wk.Z.p, dim, k, nullptr, out_re, out_im, s));
+        return;
+    }
+    HIPCHK(take_top_real_eigvecs(wk.Z.p, dim, k, out_re, out_im, s));
+    Timer t(st, MPS_KCLASS_EIGH, 0, 0);
+    const int nb = wy_block(), nblk = (dim - 1 + nb - 1) / nb;
+    const int64_t nbb = (int64_t)nb * nb, nbd = (int64_t)nb * dim;
+    wk.S.ensure(nblk * nbb, s);
+    wk.T.ensure(nblk * nbb, s);
+    wk.Y.ensure(nblk * nbd, s);
+    wk.W.ensure((int64_t)nb * k, s);
+    const int ks = std::max(1, std::min(32, dim / 64));
+    const int chunks = splitk_chunks(dim, ks, 8);
+    wk.ws.ensure(chunks * nblk * nbb, s);
+    HIPCHK(cgemm_f64_batched_splitk(OP_N, OP_C, nb, nb, dim, {wk.vh.re(), wk.vh.im(), dim}, nbd,
+                                    {wk.vh.re(), wk.vh.im(), dim}, nbd, wk.ws.re(), wk.ws.im(), ks, nblk, s));
+    HIPCHK(splitk_reduce64(wk.ws.re(), wk.ws.im(), chunks, (int64_t)nblk * nb, nb, wk.S.re(), wk.S.im(), nb, s));
+    HIPCHK(wy_t_factors(wk.S.re(), wk.S.im(), nblk, wk.tau.p, wk.T.re(), wk.T.im(), s));
+    HIPCHK(cgemm_f64_batched(OP_N, OP_N, nb, dim, nb, {wk.T.re(), wk.T.im(), nb}, nbb, {wk.vh.re(), wk.vh.im(), dim},
+                             nbd, {wk.Y.re(), wk.Y.im(), dim}, nbd, nblk, s));
+    for (int b = nblk - 1; b >= 0; --b) {
+        const int r0 = b * nb + 1, rows = dim - r0;          // v_j[r] = 0 for r <= j
+        if (rows <= 0) continue;
+        const CView<double> Yb{wk.Y.re() + b * nbd + r0, wk.Y.im() + b * nbd + r0, dim};
+        const CView<double> Vb{wk.vh.re() + b * nbd + r0, wk.vh.im() + b * nbd + r0, dim};
+        gemm64_long_k(st, wk, OP_N, OP_N, nb, k, rows, Yb, {out_re + (int64_t)r0 * k, out_im + (int64_t)r0 * k, k},
+                      {wk.W.re(), wk.W.im(), k});
+        HIPCHK(cgemm_f64_sub(OP_C, OP_N, rows, k, nb, Vb, {wk.W.re(), wk.W.im(), k},
+                             {out_re + (int64_t)r0 * k, out_im + (int64_t)r0 * k, k}, s));
+    }
+    t.done();
+}
+
 // =========================================================== the engine ====
 template <typename R>
 struct Engine {
@@ -530,22 +699,25 @@ struct Engine {
     std::vector<Planar<R>> env;       // per bond
     std::vector<Planar<R>> psi[2];    // per view-site, view layout
     std::vector<Planar<double>> phi;  // per site, layout of the pass that wrote it
-    Planar<R> X, T2, T4, TH, UR, T2T;
+    Planar<R> X, T2, TH, UR, T2T;
+    Planar<R> XR, T2R[2];             // right blocks, written on the second stream
     bool split = false;   // BF16 x 3 contractions (R = float only): operands kept k-contiguous
     Planar<double> TH64, GR, U64, V64, M64;
-    Raw<double> Z, evals, evwork, svec;
-    Raw<int> info;
+    EighWork ew;
+    Raw<double> svec;
     std::vector<double> hvals;
 
     Engine(mps_state* state, int chi_) : st(state), s(state->stream), n(state->n), chi(chi_) {}
 
     ~Engine() {
+        if (st->stream2) (void)hipStreamSynchronize(st->stream2);   // right blocks in flight
+        XR.release(s); T2R[0].release(s); T2R[1].release(s);
         for (auto& e : env) e.release(s);
         for (int o = 0; o < 2; ++o)
             for (auto& e : psi[o]) e.release(s);
-        X.release(s); T2.release(s); T4.release(s); TH.release(s); UR.release(s); T2T.release(s);
+        X.release(s); T2.release(s); TH.release(s); UR.release(s); T2T.release(s);
         TH64.release(s); GR.release(s); U64.release(s); V64.release(s); M64.release(s);
-        Z.release(s); evals.release(s); evwork.release(s); svec.release(s); info.release(s);
+        ew.release(s); svec.release(s);
         for (auto& p : phi) p.release(s);
     }
 
@@ -559,30 +731,16 @@ struct Engine {
         bool caseA;
     };
 
-    // FP64 eigen-decomposition of the Hermitian n x n Gram matrix in GR.
-    void eigh(int dim) {
-        Z.ensure(2 * (int64_t)dim * dim, s);
-        evals.ensure(dim, s);
-        evwork.ensure(dim, s);
-        info.ensure(1, s);
-        {
-            Timer t(st, MPS_KCLASS_OTHER, 0, 32.0 * dim * dim);
-            HIPCHK(pack_hermitian(GR.re(), GR.im(), dim, Z.p, s));
-            t.done();
-        }
-        Timer t(st, MPS_KCLASS_EIGH, 0, 0);
-        rocblas_status rs = rocsolver_zheevd(st->blas, rocblas_evect_original, rocblas_fill_upper, dim,
-                                             (rocblas_double_complex*)Z.p, dim, evals.p, evwork.p, info.p);
-        t.done();
-        if (rs != rocblas_status_success) fail(MPS_ERR_DEVICE, "rocsolver_zheevd failed: status " + std::to_string((int)rs));
-    }
+    // FP64 eigen-decomposition of the Hermitian dim x dim Gram matrix in GR.
+    const std::function<void()>* after_reduce = nullptr;
+    void eigh(int dim) { eigh_gram(st, ew, GR.re(), GR.im(), dim, st->eigh_method, after_reduce); }
 
     // Kept count and weights from the eigenvalues of the Gram matrix.
     Trunc select(int dim, int chi_) {
         hvals.resize(dim);
         int hinfo = 0;
-        HIPCHK(hipMemcpyAsync(hvals.data(), evals.p, sizeof(double) * dim, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hvals.data(), ew.evals.p, sizeof(double) * dim, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&hinfo, ew.info.p, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (hinfo != 0) fail(MPS_ERR_NUMERIC, "eigensolver did not converge (info " + std::to_string(hinfo) + ")");
         double total = 0;
@@ -617,7 +775,7 @@ struct Engine {
             eigh(dim);
             Trunc tr = select(dim, chi);
             U64.ensure(rows * tr.k, s);
-            HIPCHK(take_top_eigvecs(Z.p, dim, tr.k, nullptr, U64.re(), U64.im(), s));
+            top_eigvecs(st, ew, dim, tr.k, U64.re(), U64.im());
             if (want_right) {
                 if (!m64_re) fail(MPS_ERR_ARG, "internal: right factor needs FP64 input");
                 V64.ensure((int64_t)tr.k * cols, s);
@@ -646,7 +804,7 @@ struct Engine {
         eigh(dim);
         Trunc tr = select(dim, chi);
         V64.ensure((int64_t)dim * tr.k, s);
-        HIPCHK(take_top_eigvecs(Z.p, dim, tr.k, nullptr, V64.re(), V64.im(), s));
+        top_eigvecs(st, ew, dim, tr.k, V64.re(), V64.im());
         std::vector<double> inv_s(tr.k), s_over(tr.k);
         for (int i = 0; i < tr.k; ++i) {
             const double sv = std::sqrt(std::max(hvals[dim - 1 - i], 0.0));
@@ -714,25 +872,29 @@ struct Engine {
         cb.assign(n + 1, 1);
     }
 
-    // L_j A_j W_j for view o, view-site j, into T2 ([cL][2][wM][DM]).
-    void left_block(int o, int j) {
+    // L_j A_j W_j for view o, view-site j, into out ([cL][2][wM][DM]); xb holds
+    // the intermediate L_j A_j.  Applied in the mirrored view this is the right
+    // block A W R of a pair, with the pair's right site as view-site j.
+    void block(int o, int j, Planar<R>& xb, Planar<R>& out, const Lane& ln) {
         const int bL = bnd(o, j), bM = bnd(o, j + 1);
         const int64_t cL = cb[bL], wL = mpo.w[bL], wM = mpo.w[bM];
         const int64_t DL = st->bond[bL], DM = st->bond[bM];
-        X.ensure(cL * wL * 2 * DM, s);
-        T2.ensure(cL * 2 * wM * DM, s);
+        xb.ensure(cL * wL * 2 * DM, ln.s);
+        out.ensure(cL * 2 * wM * DM, ln.s);
         if (split)
             gemm_split(st, MPS_KCLASS_CONTRACT, cL * wL, 2 * DM, DL, (const float*)env[bL].re(),
                        (const float*)env[bL].im(), DL, (const float*)psi[o][j].re(), (const float*)psi[o][j].im(), DL,
-                       (float*)X.re(), (float*)X.im(), 2 * DM);
+                       (float*)xb.re(), (float*)xb.im(), 2 * DM, &ln);
         else
             gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_N, cL * wL, 2 * DM, DL, env[bL].re(), env[bL].im(), DL,
-                    psi[o][j].re(), psi[o][j].im(), 2 * DM, X.re(), X.im(), 2 * DM);
+                    psi[o][j].re(), psi[o][j].im(), 2 * DM, xb.re(), xb.im(), 2 * DM, &ln);
         const MpoSiteOp& op = mpo.view[o][j];
-        Timer t(st, MPS_KCLASS_MPO, 0, 2.0 * sizeof(R) * (cL * wL * 2 * DM + cL * 2 * wM * DM));
-        HIPCHK(mpo_apply<R>(op, cL, DM, X.re(), X.im(), T2.re(), T2.im(), s));
+        Timer t(st, MPS_KCLASS_MPO, 0, 2.0 * sizeof(R) * (cL * wL * 2 * DM + cL * 2 * wM * DM), ln.s);
+        HIPCHK(mpo_apply<R>(op, cL, DM, xb.re(), xb.im(), out.re(), out.im(), ln.s));
         t.done();
     }
+
+    void left_block(int o, int j) { block(o, j, X, T2, main_lane(st)); }
 
     // Store U64 (rows x k) as the phi tensor of site k0 and update the left
     // environment of bond bM from T2: env = U^H T2 (k x (wM DM)).
@@ -794,46 +956,70 @@ struct Engine {
         return f0;
     }
 
+    void ensure_stream2() {
+        if (st->stream2) return;
+        HIPCHK(hipStreamCreateWithFlags(&st->stream2, hipStreamNonBlocking));
+        for (auto& e : st->ev_order) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+
+    // One directional pass in view o.  The local tensor of the pair (j, j+1)
+    // is met in the middle: Theta = (L_j A_j W_j) . (A_{j+1} W_{j+1} R_{j+2})^T
+    // contracted over the MPO bond and the psi bond between the pair
+    // (rows (cL, s1), columns (cR, s2)).  The right block depends only on psi
+    // and on right environments that this pass has not yet overwritten, so
+    // the block of the next pair is built on the second stream while the
+    // current pair is truncated.
     double sweep(int o) {
+        if (n < 2) return 0;
+        ensure_stream2();
+        const Lane l2 = st->overlap_right ? Lane{st->stream2, &st->splitws2} : main_lane(st);
+        hipEvent_t ev_start = st->ev_order[0], ev_used = st->ev_order[1];
+        hipEvent_t ev_right[2] = {st->ev_order[2], st->ev_order[3]};
+        HIPCHK(hipEventRecord(ev_start, s));
+        HIPCHK(hipStreamWaitEvent(st->stream2, ev_start, 0));
+        block(1 - o, n - 2, XR, T2R[0], l2);
+        HIPCHK(hipEventRecord(ev_right[0], st->stream2));
         double f = 0;
         for (int j = 0; j + 1 < n; ++j) {
             const bool last = (j + 2 == n);
             left_block(o, j);
             const int bL = bnd(o, j), bM = bnd(o, j + 1), bR = bnd(o, j + 2);
-            const int64_t cL = cb[bL], cR = cb[bR], wM = mpo.w[bM], wR = mpo.w[bR];
-            const int64_t DM = st->bond[bM], DR = st->bond[bR];
-            X.ensure(cL * 2 * wM * 2 * DR, s);
-            T4.ensure(cL * 4 * wR * DR, s);
-            TH.ensure(4 * cL * cR, s);
-            TH64.ensure(4 * cL * cR, s);
-            // T2 . A_{j+1}
+            const int64_t cL = cb[bL], cR = cb[bR], wM = mpo.w[bM];
+            const int64_t DM = st->bond[bM];
+            const int64_t rows = 2 * cL, cols = 2 * cR, K = wM * DM;
+            TH.ensure(rows * cols, s);
+            TH64.ensure(rows * cols, s);
+            const Planar<R>& rb = T2R[j & 1];
+            HIPCHK(hipStreamWaitEvent(s, ev_right[j & 1], 0));
             if (split)
-                gemm_split(st, MPS_KCLASS_CONTRACT, cL * 2 * wM, 2 * DR, DM, (const float*)T2.re(),
-                           (const float*)T2.im(), DM, (const float*)psi[o][j + 1].re(),
-                           (const float*)psi[o][j + 1].im(), DM, (float*)X.re(), (float*)X.im(), 2 * DR);
+                gemm_split(st, MPS_KCLASS_CONTRACT, rows, cols, K, (const float*)T2.re(), (const float*)T2.im(), K,
+                           (const float*)rb.re(), (const float*)rb.im(), K, (float*)TH.re(), (float*)TH.im(), cols);
             else
-                gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_N, cL * 2 * wM, 2 * DR, DM, T2.re(), T2.im(), DM,
-                        psi[o][j + 1].re(), psi[o][j + 1].im(), 2 * DR, X.re(), X.im(), 2 * DR);
-            {
-                Timer t(st, MPS_KCLASS_MPO, 0, 2.0 * sizeof(R) * (cL * 2 * wM * 2 * DR + cL * 4 * wR * DR));
-                HIPCHK(mpo_apply<R>(mpo.view[o][j + 1], 2 * cL, DR, X.re(), X.im(), T4.re(), T4.im(), s));
-                t.done();
-            }
-            // Theta = T4 . R^T
-            if (split)
-                gemm_split(st, MPS_KCLASS_CONTRACT, 4 * cL, cR, wR * DR, (const float*)T4.re(), (const float*)T4.im(),
-                           wR * DR, (const float*)env[bR].re(), (const float*)env[bR].im(), wR * DR,
-                           (float*)TH.re(), (float*)TH.im(), cR);
-            else
-                gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_T, 4 * cL, cR, wR * DR, T4.re(), T4.im(), wR * DR,
-                        env[bR].re(), env[bR].im(), wR * DR, TH.re(), TH.im(), cR);
-            const int64_t rows = 2 * cL, cols = 2 * cR;
+                gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_T, rows, cols, K, T2.re(), T2.im(), K, rb.re(), rb.im(), K,
+                        TH.re(), TH.im(), cols);
+            // The right block of the next pair is queued on the second stream once
+            // this pair's tridiagonal reduction (a whole-device cooperative launch)
+            // has finished, so it overlaps the rest of the truncation.
+            bool queued = last;
+            const std::function<void()> queue_right = [&, j]() {
+                if (queued) return;
+                queued = true;
+                // buffer (j+1)&1 was last read by the previous pair's product
+                HIPCHK(hipEventRecord(ev_used, s));
+                HIPCHK(hipStreamWaitEvent(st->stream2, ev_used, 0));
+                block(1 - o, n - 3 - j, XR, T2R[(j + 1) & 1], l2);
+                HIPCHK(hipEventRecord(ev_right[(j + 1) & 1], st->stream2));
+            };
+            after_reduce = &queue_right;
             HIPCHK((convert_planar<R, double>(TH.re(), TH.im(), rows * cols, TH64.re(), TH64.im(), s)));
             Trunc tr = truncate(TH.re(), TH.im(), rows, cols, last, TH64.re(), TH64.im());
+            after_reduce = nullptr;
+            queue_right();          // no-op when the truncation already queued it
             f = tr.f;
             if (f > 1.0 + 1e-3) fail(MPS_ERR_NUMERIC, "partial fidelity above 1: " + std::to_string(f));
             finish_left(o, j, tr, !last);
             if (last) {
+                // cR = 1 at the end of the chain: the column order (cR, s2) is the site layout [k][s2]
                 const int k1 = site(o, j + 1);
                 phi[k1].ensure((int64_t)tr.k * cols, s);
                 HIPCHK((convert_planar<double, double>(V64.re(), V64.im(), (int64_t)tr.k * cols, phi[k1].re(),
@@ -967,6 +1153,9 @@ mps_status mps_create(int n_sites, const uint8_t* init_bits, int max_chi, int pr
         st->max_chi = max_chi;
         st->prec = precision;
         st->stream = (hipStream_t)hip_stream;
+        if (const char* em = std::getenv("MPS_EIGENSOLVER"))
+            st->eigh_method = std::strcmp(em, "rocsolver") == 0 ? EIGH_ROCSOLVER : EIGH_PERSISTENT;
+        if (const char* ov = std::getenv("MPS_OVERLAP")) st->overlap_right = std::strcmp(ov, "0") != 0;
         try {
             if (rocblas_create_handle(&st->blas) != rocblas_status_success) fail(MPS_ERR_DEVICE, "rocblas_create_handle failed");
             rocblas_set_stream(st->blas, st->stream);
@@ -998,6 +1187,14 @@ mps_status mps_destroy(mps_state* st) {
     st->partial.release(st->stream);
     st->splitws.release(st->stream);
     st->splitws64.release(st->stream);
+    if (st->stream2) {
+        (void)hipStreamSynchronize(st->stream2);
+        st->splitws2.release(st->stream2);
+        (void)hipStreamSynchronize(st->stream2);
+        (void)hipStreamDestroy(st->stream2);
+    }
+    for (auto e : st->ev_order)
+        if (e) (void)hipEventDestroy(e);
     for (auto& p : st->pending) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
@@ -1371,6 +1568,62 @@ void selftest_cgemm_impl(int opa, int opb, int M, int N, int K, const double* a,
     for (int64_t i = 0; i < nc; ++i) { c[2 * i] = hc[i]; c[2 * i + 1] = hc[nc + i]; }
 }
 }  // namespace
+
+namespace {
+void selftest_eigh_impl(int n, const double* a, int method, double* w, double* z, int* used) {
+    mps_state tmp;
+    tmp.stream = nullptr;
+    if (rocblas_create_handle(&tmp.blas) != rocblas_status_success) fail(MPS_ERR_DEVICE, "rocblas_create_handle failed");
+    EighWork wk;
+    Planar<double> g;
+    try {
+        const int64_t nn = (int64_t)n * n;
+        std::vector<double> h(2 * nn);
+        for (int64_t i = 0; i < nn; ++i) { h[i] = a[2 * i]; h[nn + i] = a[2 * i + 1]; }
+        g.ensure(nn, nullptr);
+        HIPCHK(hipMemcpyAsync(g.re(), h.data(), sizeof(double) * nn, hipMemcpyHostToDevice, nullptr));
+        HIPCHK(hipMemcpyAsync(g.im(), h.data() + nn, sizeof(double) * nn, hipMemcpyHostToDevice, nullptr));
+        eigh_gram(&tmp, wk, g.re(), g.im(), n, method);
+        Planar<double> u;
+        u.ensure(nn, nullptr);
+        top_eigvecs(&tmp, wk, n, n, u.re(), u.im());      // row-major n x n, largest first
+        int info = 0;
+        std::vector<double> hu(2 * nn);
+        HIPCHK(hipMemcpyAsync(w, wk.evals.p, sizeof(double) * n, hipMemcpyDeviceToHost, nullptr));
+        HIPCHK(hipMemcpyAsync(hu.data(), u.re(), sizeof(double) * nn, hipMemcpyDeviceToHost, nullptr));
+        HIPCHK(hipMemcpyAsync(hu.data() + nn, u.im(), sizeof(double) * nn, hipMemcpyDeviceToHost, nullptr));
+        HIPCHK(hipMemcpyAsync(&info, wk.info.p, sizeof(int), hipMemcpyDeviceToHost, nullptr));
+        HIPCHK(hipStreamSynchronize(nullptr));
+        u.release(nullptr);
+        // eigenvector j (ascending order) is column n - 1 - j of u
+        for (int64_t r = 0; r < n; ++r)
+            for (int64_t j = 0; j < n; ++j) {
+                z[2 * (r + j * n)] = hu[r * n + (n - 1 - j)];
+                z[2 * (r + j * n) + 1] = hu[nn + r * n + (n - 1 - j)];
+            }
+        if (info != 0) fail(MPS_ERR_NUMERIC, "eigensolver did not converge (info " + std::to_string(info) + ")");
+        if (used) *used = wk.method_used;
+    } catch (...) {
+        (void)hipStreamSynchronize(nullptr);
+        wk.release(nullptr);
+        g.release(nullptr);
+        rocblas_destroy_handle(tmp.blas);
+        throw;
+    }
+    wk.release(nullptr);
+    g.release(nullptr);
+    HIPCHK(hipStreamSynchronize(nullptr));
+    rocblas_destroy_handle(tmp.blas);
+}
+}  // namespace
+
+extern "C" mps_status mps_kernel_selftest_eigh(int n, const double* a, int method, double* w, double* z, int* used) {
+    return run_guarded([&] {
+        if (n < 1 || n > 8192 || !a || !w || !z) fail(MPS_ERR_ARG, "bad eigensolver self-test arguments");
+        if (method != EIGH_ROCSOLVER && method != EIGH_PERSISTENT) fail(MPS_ERR_ARG, "method must be 0 or 1");
+        selftest_eigh_impl(n, a, method, w, z, used);
+    });
+}
 
 extern "C" mps_status mps_kernel_selftest_cgemm(int precision, int opa, int opb, int M, int N, int K,
                                                 const double* a, const double* b, double* c) {

@@ -1,0 +1,554 @@
+// Householder reduction of a Hermitian matrix to real symmetric tridiagonal
+// form, T = Q^H A Q with Q = H_0 H_1 ... H_{n-2}, as one persistent kernel.
+//
+// The FP64 truncation of a two-site step (Sec. VI.A: keep the chi largest
+// singular values) diagonalises a Gram matrix of order 2 chi.  Its
+// tridiagonal reduction is a chain of n - 1 dependent Householder steps, each
+// a matrix-vector product with the trailing block; issued as a few kernels
+// per step it is launch-latency bound.  Here one cooperative launch does all
+// steps:
+//   * workgroup g owns the columns g, g + P, g + 2P, ... (at most 8 of them),
+//     four in registers and four in LDS, for the whole reduction, so the
+//     trailing block is never re-read from memory;
+//   * every workgroup holds column i (as updated by steps 0 .. i-1) in its
+//     registers and forms the reflector (v, tau) from it redundantly;
+//   * it computes y = A v for its own columns (the matrix is Hermitian, so
+//     y_c is the dot product of column c with v), publishes y_c and its share
+//     of y^H v, and waits for all workgroups (one flag each, the only wait of
+//     the step);
+//   * it applies the rank-2 update A -= v w^H + w v^H,
+//     w = tau y - (|tau|^2 y^H v / 2) v, to its columns, and rebuilds column
+//     i+1 for the next step from the copy of it that the column's owner
+//     published one step earlier plus this step's update (look-ahead), so no
+//     second wait is needed;
+//   * the owner of column i+2 publishes it after this step's update.
+// Reflector convention: H = I - tau v v^H with v_i[0..i] = 0, v_i[i+1] = 1,
+// H^H x = (beta, 0, ...) for the column x below the diagonal, beta real.
+// The reflectors are written conjugated, one per row, as the planar
+// row-major (n - 1) x n matrix V^H, which is the operand layout of the
+// blocked back-transformation by GEMMs.
+//
+// Every wait is bounded: a workgroup that waits too long raises the abort
+// flag, every other wait sees it, and all workgroups exit; the host then
+// falls back to another eigensolver.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace mpsk {
+namespace {
+
+constexpr int TT = 512;            // threads per workgroup
+constexpr int TQ = 4;              // rows per thread: row = tid + TT * q
+constexpr int TC = 8;              // columns per workgroup
+constexpr int TCR = 4;             // columns kept in registers (the rest in LDS)
+constexpr int TMAXN = TT * TQ;     // 2048
+constexpr int NWAVE = TT / 64;
+constexpr int SPIN_LIMIT = 1 << 21;
+
+struct TrArgs {
+    const double2* a;    // n x n column-major, full Hermitian (not modified)
+    double* vh_re;       // (n - 1) x n row-major planar: row i = conj(v_i)
+    double* vh_im;
+    int n, lda, P;
+    double* d;           // n
+    double* e;           // n - 1
+    double2* tau;        // n - 1
+    double2* colbuf;     // 2 x n: published column
+    double2* ybuf;       // 2 x n: published y
+    double2* pdot;       // 2 x P: per-workgroup partial y^H v
+    int* col_flag;       // number of published columns
+    int* wg_flag;        // P: steps completed by each workgroup
+    int* abort_flag;
+};
+
+__device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+// conj(a) * b
+__device__ inline double2 cjmul(double2 a, double2 b) { return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); }
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+__device__ inline double2 ld_coh(const double2* p) {
+    const unsigned long long* q = (const unsigned long long*)p;
+    const unsigned long long x = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long y = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_double2(__builtin_bit_cast(double, x), __builtin_bit_cast(double, y));
+}
+__device__ inline void st_coh(double2* p, double2 v) {
+    unsigned long long* q = (unsigned long long*)p;
+    __hip_atomic_store(q, __builtin_bit_cast(unsigned long long, v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(q + 1, __builtin_bit_cast(unsigned long long, v.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Cross-workgroup protocol.  Every value another workgroup reads is written
+// with a device-coherent store (st_coh) and read with a device-coherent load
+// (ld_coh), so no cache write-back or invalidation is needed: a producer
+// waits until its coherent stores are acknowledged (s_waitcnt), joins its
+// workgroup barrier and then sets the flag; a consumer polls the flag with
+// coherent loads and issues its data loads only after the poll returned.
+
+// One thread waits until *flag >= target.  False on abort or time-out.
+__device__ bool wait_geq(int* flag, int target, int* abort_flag) {
+    int spins = 0;
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+        if (++spins > SPIN_LIMIT) {
+            __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    return true;
+}
+
+// After this workgroup's coherent stores are acknowledged, set *flag = val.
+__device__ void publish(int* flag, int val) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flag, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Sums of 16 values over the 64 lanes of a wave by reduce-scatter: at the
+// exchange with lane ^ 32, ^ 16, ^ 8, ^ 4 each lane keeps half of its values
+// and adds the partner's copy of that half (8 + 4 + 2 + 1 shuffles), then two
+// plain steps finish.  On return every lane holds the total of value
+// index (lane >> 2) & 15 in bit-reversed order; see sum16_index().
+__device__ inline double wave_sum16(double (&v)[16], int lane) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const bool hi = lane & 32;
+        const double keep = hi ? v[8 + k] : v[k], give = hi ? v[k] : v[8 + k];
+        v[k] = keep + __shfl_xor(give, 32);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool hi = lane & 16;
+        const double keep = hi ? v[4 + k] : v[k], give = hi ? v[k] : v[4 + k];
+        v[k] = keep + __shfl_xor(give, 16);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const bool hi = lane & 8;
+        const double keep = hi ? v[2 + k] : v[k], give = hi ? v[k] : v[2 + k];
+        v[k] = keep + __shfl_xor(give, 8);
+    }
+    {
+        const bool hi = lane & 4;
+        const double keep = hi ? v[1] : v[0], give = hi ? v[0] : v[1];
+        v[0] = keep + __shfl_xor(give, 4);
+    }
+    double r = v[0];
+    r += __shfl_xor(r, 2);
+    r += __shfl_xor(r, 1);
+    return r;
+}
+// Index (0..15) of the value whose total wave_sum16 leaves in this lane.
+__device__ inline int sum16_index(int lane) {
+    return ((lane & 32) ? 8 : 0) + ((lane & 16) ? 4 : 0) + ((lane & 8) ? 2 : 0) + ((lane & 4) ? 1 : 0);
+}
+
+// Owned column j (a compile-time constant after unrolling), thread row slot q, row r.
+#define A_GET(j, q, r) ((j) < TCR ? areg[(j) < TCR ? (j) : 0][q] : alds[(j) < TCR ? 0 : (j) - TCR][r])
+#define A_SUB(j, q, r, dx, dy)                                \
+    do {                                                      \
+        if ((j) < TCR) {                                      \
+            areg[(j) < TCR ? (j) : 0][q].x -= (dx);           \
+            areg[(j) < TCR ? (j) : 0][q].y -= (dy);           \
+        } else {                                              \
+            alds[(j) < TCR ? 0 : (j) - TCR][r].x -= (dx);     \
+            alds[(j) < TCR ? 0 : (j) - TCR][r].y -= (dy);     \
+        }                                                     \
+    } while (0)
+// A[r, c_j] -= v[r] conj(w_cj) + w[r] conj(v_cj) over the trailing rows
+#define UPDATE_COL(j)                                                  \
+    do {                                                               \
+        const double2 wc_ = wcol[j], vc_ = vcol[j];                    \
+        _Pragma("unroll") for (int q = 0; q < TQ; ++q) {               \
+            const int r = tid + TT * q;                                \
+            if (r < i + 1 || r >= n) continue;                         \
+            const double2 t1 = cjmul(wc_, v[q]);                       \
+            const double2 t2 = cjmul(vc_, w[q]);                       \
+            A_SUB(j, q, r, t1.x + t2.x, t1.y + t2.y);                  \
+        }                                                              \
+    } while (0)
+
+__global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrArgs g) {
+    __shared__ double2 alds[TC - TCR][TMAXN];
+    __shared__ double red[NWAVE][2 * TC + 1];
+    __shared__ double bc[2 * TC + 1];
+    __shared__ double2 vcol[TC], wcol[TC], ycol[TC], xcol[TC], a1col[TC];
+    __shared__ double2 alpha_s;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wg = blockIdx.x, P = g.P, n = g.n;
+    const int64_t lda = g.lda;
+    double2 areg[TCR][TQ];
+    double2 x[TQ];          // column i at this thread's rows
+
+    // load the owned columns and column 0
+#pragma unroll
+    for (int j = 0; j < TC; ++j) {
+        const int c = wg + P * j;
+#pragma unroll
+        for (int q = 0; q < TQ; ++q) {
+            const int r = tid + TT * q;
+            double2 val = make_double2(0.0, 0.0);
+            if (c < n && r < n) val = g.a[r + c * lda];
+            if (j < TCR)
+                areg[j < TCR ? j : 0][q] = val;
+            else
+                alds[j < TCR ? 0 : j - TCR][r] = val;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < TQ; ++q) {
+        const int r = tid + TT * q;
+        x[q] = r < n ? g.a[r] : make_double2(0.0, 0.0);
+    }
+    if (tid < TC) {
+        xcol[tid] = make_double2(0.0, 0.0);
+        a1col[tid] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+
+    for (int i = 0; i + 1 < n; ++i) {
+        const int buf = i & 1;
+        // ---- broadcasts from row i+1 and from the rows of the owned columns
+#pragma unroll
+        for (int q = 0; q < TQ; ++q) {
+            const int r = tid + TT * q;
+            if (r == i + 1) {
+                alpha_s = x[q];
+#pragma unroll
+                for (int j = 0; j < TC; ++j) a1col[j] = A_GET(j, q, r);
+            }
+            if (r < n && r >= wg && (r - wg) % P == 0) xcol[(r - wg) / P] = x[q];
+        }
+        // ---- one reduction: |x[i+2:]|^2 and z_c = sum_{r >= i+2} conj(A[r, c]) x[r]
+        double part = 0.0;
+        double zp[2 * TC];
+#pragma unroll
+        for (int q = 0; q < TQ; ++q) {
+            const int r = tid + TT * q;
+            if (r >= i + 2 && r < n) part += x[q].x * x[q].x + x[q].y * x[q].y;
+        }
+#pragma unroll
+        for (int j = 0; j < TC; ++j) {
+            double2 sacc = make_double2(0.0, 0.0);
+            const int c = wg + P * j;
+            if (c >= i + 1 && c < n) {
+#pragma unroll
+                for (int q = 0; q < TQ; ++q) {
+                    const int r = tid + TT * q;
+                    if (r >= i + 2) sacc = cadd(sacc, cjmul(A_GET(j, q, r), x[q]));
+                }
+            }
+            zp[2 * j] = sacc.x;
+            zp[2 * j + 1] = sacc.y;
+        }
+        {
+            const double zs = wave_sum16(zp, lane);
+            if ((lane & 3) == 0) red[wave][sum16_index(lane)] = zs;
+        }
+        part = wave_sum(part);
+        if (lane == 0) red[wave][2 * TC] = part;
+        __syncthreads();
+        if (tid <= 2 * TC) {
+            double sum = 0.0;
+            for (int w = 0; w < NWAVE; ++w) sum += red[w][tid];
+            bc[tid] = sum;
+        }
+        __syncthreads();
+        // ---- reflector: H^H x = (beta, 0, ...), v = (1, x[i+2:] / (alpha - beta))
+        const double xnorm2 = bc[2 * TC];
+        const double2 alpha = alpha_s;
+        const double anorm2 = alpha.x * alpha.x + alpha.y * alpha.y + xnorm2;
+        // tau = 0 (H = I) when x is already (real alpha, 0, ...) or negligible
+        const bool reflect = !(xnorm2 == 0.0 && alpha.y == 0.0) && anorm2 > 1e-300;
+        double2 tau = make_double2(0.0, 0.0);
+        double beta = alpha.x;
+        double2 scale = make_double2(0.0, 0.0);
+        if (reflect) {
+            beta = -copysign(sqrt(anorm2), alpha.x);
+            tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+            const double2 am = make_double2(alpha.x - beta, alpha.y);     // scale = 1 / (alpha - beta)
+            const double den = am.x * am.x + am.y * am.y;
+            scale = make_double2(am.x / den, -am.y / den);
+        }
+        double2 v[TQ];
+#pragma unroll
+        for (int q = 0; q < TQ; ++q) {
+            const int r = tid + TT * q;
+            v[q] = make_double2(0.0, 0.0);
+            if (r == i + 1)
+                v[q] = make_double2(1.0, 0.0);
+            else if (r >= i + 2 && r < n)
+                v[q] = cmul(x[q], scale);
+        }
+        if (tid < TC) {
+            const int c = wg + P * tid;
+            double2 vc = make_double2(0.0, 0.0), yc = make_double2(0.0, 0.0);
+            if (c >= i + 1 && c < n) {
+                vc = c == i + 1 ? make_double2(1.0, 0.0) : cmul(xcol[tid], scale);
+                // y_c = conj(A[i+1, c]) + scale z_c
+                const double2 a1 = a1col[tid];
+                yc = cadd(make_double2(a1.x, -a1.y), cmul(scale, make_double2(bc[2 * tid], bc[2 * tid + 1])));
+                st_coh(&g.ybuf[(int64_t)buf * n + c], yc);
+            }
+            vcol[tid] = vc;
+            ycol[tid] = yc;
+        }
+        // the owner of column i records d_i, e_i, tau_i and the reflector
+        if (wg == i % P) {
+#pragma unroll
+            for (int q = 0; q < TQ; ++q) {
+                const int r = tid + TT * q;
+                if (r < n) {
+                    g.vh_re[(int64_t)i * n + r] = v[q].x;
+                    g.vh_im[(int64_t)i * n + r] = -v[q].y;
+                }
+                if (r == i) g.d[i] = x[q].x;
+            }
+            if (tid == 0) {
+                g.e[i] = beta;
+                g.tau[i] = tau;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double2 pd = make_double2(0.0, 0.0);
+            for (int j = 0; j < TC; ++j) pd = cadd(pd, cjmul(ycol[j], vcol[j]));
+            st_coh(&g.pdot[(int64_t)buf * P + wg], pd);
+        }
+        publish(g.wg_flag + wg, i + 1);
+        // ---- wait for every workgroup's y entries and partial y^H v (and the
+        //      column published one step earlier)
+        bool ok = true;
+        if (tid < P) ok = wait_geq(g.wg_flag + tid, i + 1, g.abort_flag);
+        if (__syncthreads_or(!ok)) return;
+        double pdr = tid < P ? ld_coh(&g.pdot[(int64_t)buf * P + tid]).x : 0.0;
+        pdr = wave_sum(pdr);
+        if (lane == 0) red[wave][0] = pdr;
+        __syncthreads();
+        if (tid == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < NWAVE; ++w) sum += red[w][0];
+            bc[0] = sum;
+        }
+        __syncthreads();
+        // w = tau y + alpha_w v, alpha_w = -|tau|^2 (y^H v) / 2
+        const double alw = -0.5 * (tau.x * tau.x + tau.y * tau.y) * bc[0];
+        double2 w[TQ];
+#pragma unroll
+        for (int q = 0; q < TQ; ++q) {
+            const int r = tid + TT * q;
+            w[q] = make_double2(0.0, 0.0);
+            if (r >= i + 1 && r < n) {
+                const double2 ty = cmul(tau, ld_coh(&g.ybuf[(int64_t)buf * n + r]));
+                w[q] = make_double2(ty.x + alw * v[q].x, ty.y + alw * v[q].y);
+            }
+        }
+        if (tid < TC) {
+            const double2 ty = cmul(tau, ycol[tid]);
+            wcol[tid] = make_double2(ty.x + alw * vcol[tid].x, ty.y + alw * vcol[tid].y);
+        }
+        // w at row i+1 (v there is 1): the scalar of the next column's update
+        const double2 ty1 = cmul(tau, ld_coh(&g.ybuf[(int64_t)buf * n + i + 1]));
+        const double2 w1 = make_double2(ty1.x + alw, ty1.y);
+        __syncthreads();   // wcol visible to every wave before the update
+        // ---- rank-2 update of the owned columns; column i+2 first, then published
+        const int j2 = (i + 2 < n && wg == (i + 2) % P) ? (i + 2) / P : -1;
+        if (j2 >= 0) {
+#pragma unroll
+            for (int j = 0; j < TC; ++j) {
+                if (j != j2) continue;
+                UPDATE_COL(j);
+#pragma unroll
+                for (int q = 0; q < TQ; ++q) {
+                    const int r = tid + TT * q;
+                    // slot (i+2) & 1 == buf: read after the next step's wait
+                    if (r >= i + 1 && r < n) st_coh(&g.colbuf[(int64_t)buf * n + r], A_GET(j, q, r));
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < TC; ++j) {
+            const int c = wg + P * j;
+            if (j == j2 || c < i + 1 || c >= n) continue;
+            UPDATE_COL(j);
+        }
+        // ---- next column: x_{i+1} = A[:, i+1] (after step i-1) - v conj(w_{i+1}) - w
+        {
+            const double2* src = g.colbuf + (int64_t)((i + 1) & 1) * n;
+#pragma unroll
+            for (int q = 0; q < TQ; ++q) {
+                const int r = tid + TT * q;
+                double2 cv = make_double2(0.0, 0.0);
+                if (r >= i + 1 && r < n) cv = (i == 0) ? g.a[r + lda] : ld_coh(&src[r]);
+                const double2 t1 = cjmul(w1, v[q]);
+                x[q] = make_double2(cv.x - t1.x - w[q].x, cv.y - t1.y - w[q].y);
+            }
+        }
+        __syncthreads();
+    }
+    // last diagonal entry: column n-1 after step n-2
+    if (wg == 0) {
+#pragma unroll
+        for (int q = 0; q < TQ; ++q)
+            if (tid + TT * q == n - 1) g.d[n - 1] = x[q].x;
+    }
+}
+#undef UPDATE_COL
+#undef A_SUB
+#undef A_GET
+
+// Full Hermitian matrix, column-major interleaved, from the row-major planar
+// Gram matrix whose lower triangle (row >= column) is valid.
+__global__ __launch_bounds__(256) void herm_full_kernel(const double* __restrict__ re, const double* __restrict__ im,
+                                                       int n, double2* __restrict__ out) {
+    __shared__ double2 lo[64][65];   // lo[a][b] = rho[bi + a][bj + b]  (valid for row >= col)
+    __shared__ double2 up[64][65];   // up[a][b] = rho[bj + a][bi + b]
+    const int bi = blockIdx.x * 64, bj = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int a = ty; a < 64; a += 4) {
+        const int r1 = bi + a, c1 = bj + tx;
+        if (r1 < n && c1 < n && r1 >= c1) lo[a][tx] = make_double2(re[(int64_t)r1 * n + c1], im[(int64_t)r1 * n + c1]);
+        const int r2 = bj + a, c2 = bi + tx;
+        if (r2 < n && c2 < n && r2 >= c2) up[a][tx] = make_double2(re[(int64_t)r2 * n + c2], im[(int64_t)r2 * n + c2]);
+    }
+    __syncthreads();
+    // out(i, j) at i + j n: i = bi + x (fastest), j = bj + y
+    for (int y = ty; y < 64; y += 4) {
+        const int i = bi + tx, j = bj + y;
+        if (i >= n || j >= n) continue;
+        double2 v;
+        if (i >= j) {
+            v = lo[tx][y];                  // rho[i][j]
+        } else {
+            const double2 u = up[y][tx];    // rho[j][i]
+            v = make_double2(u.x, -u.y);
+        }
+        out[i + (int64_t)j * n] = v;
+    }
+}
+
+// T of the compact WY form H_0 H_1 ... H_{m-1} = I - V T V^H (T upper
+// triangular): T[i][i] = tau_i, T[i][j] = -tau_j sum_{l=i}^{j-1} T[i][l] S[l][j]
+// for i < j, with S = V^H V.  Row i depends only on itself: one wave per row,
+// lane l holding T[i][l]; one workgroup per block of reflectors.
+constexpr int WY_MAX = 64;
+constexpr int WY_THREADS = 1024;
+__global__ __launch_bounds__(WY_THREADS) void wy_t_kernel(const double* __restrict__ s_re, const double* __restrict__ s_im,
+                                                        const double2* __restrict__ tau, double* __restrict__ t_re,
+                                                        double* __restrict__ t_im) {
+    __shared__ double2 S[WY_MAX][WY_MAX + 1];
+    const int64_t b = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double* sr = s_re + b * WY_MAX * WY_MAX;
+    const double* si = s_im + b * WY_MAX * WY_MAX;
+    for (int idx = threadIdx.x; idx < WY_MAX * WY_MAX; idx += WY_THREADS)
+        S[idx / WY_MAX][idx % WY_MAX] = make_double2(sr[idx], si[idx]);
+    __syncthreads();
+    const double2* tb = tau + b * WY_MAX;
+    for (int i = wave; i < WY_MAX; i += WY_THREADS / 64) {
+        double2 t = make_double2(0.0, 0.0);        // T[i][lane]
+        if (lane == i) t = tb[i];
+        for (int j = i + 1; j < WY_MAX; ++j) {
+            double2 p = make_double2(0.0, 0.0);
+            if (lane >= i && lane < j) p = cmul(t, S[lane][j]);
+            const double sx = wave_sum(p.x), sy = wave_sum(p.y);
+            if (lane == j) {
+                const double2 tt = cmul(tb[j], make_double2(sx, sy));
+                t = make_double2(-tt.x, -tt.y);
+            }
+        }
+        t_re[b * WY_MAX * WY_MAX + (int64_t)i * WY_MAX + lane] = t.x;
+        t_im[b * WY_MAX * WY_MAX + (int64_t)i * WY_MAX + lane] = t.y;
+    }
+}
+
+// The k eigenvectors of the largest eigenvalues (ascending order input, real
+// n x n column-major) as planar complex row-major n x k, largest first.
+__global__ __launch_bounds__(256) void top_real_kernel(const double* __restrict__ ev, int n, int k,
+                                                      double* __restrict__ ore, double* __restrict__ oim) {
+    const int64_t total = (int64_t)n * k;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = idx % k, r = idx / k;
+        ore[idx] = ev[r + (int64_t)(n - 1 - c) * n];
+        oim[idx] = 0.0;
+    }
+}
+
+}  // namespace
+
+int wy_block() { return WY_MAX; }
+
+hipError_t wy_t_factors(const double* s_re, const double* s_im, int nblk, const double* tau_z, double* t_re,
+                        double* t_im, hipStream_t stream) {
+    if (nblk < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(WY_THREADS), 0, stream, s_re, s_im, (const double2*)tau_z, t_re,
+                       t_im);
+    return hipGetLastError();
+}
+
+hipError_t take_top_real_eigvecs(const double* evec, int n, int k, double* out_re, double* out_im, hipStream_t stream) {
+    const int64_t total = (int64_t)n * k;
+    if (total <= 0) return hipSuccess;
+    int64_t g = (total + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(top_real_kernel, dim3((unsigned)g), dim3(256), 0, stream, evec, n, k, out_re, out_im);
+    return hipGetLastError();
+}
+
+int hetrd_max_n() { return TMAXN; }
+
+size_t hetrd_workspace_bytes(int n) {
+    const int P = (n + TC - 1) / TC;
+    return sizeof(double2) * (4 * (size_t)n + 2 * (size_t)P) + sizeof(int) * (size_t)(P + 2) + 256;
+}
+
+hipError_t hermitian_full_colmajor(const double* re, const double* im, int n, double* out_z, hipStream_t stream) {
+    const dim3 grid((n + 63) / 64, (n + 63) / 64);
+    hipLaunchKernelGGL(herm_full_kernel, grid, dim3(256), 0, stream, re, im, n, (double2*)out_z);
+    return hipGetLastError();
+}
+
+hipError_t hetrd_persistent(const double* a_z, int n, double* d, double* e, double* tau_z, double* vh_re,
+                            double* vh_im, void* ws, size_t ws_bytes, int** abort_flag, hipStream_t stream) {
+    if (n < 2 || n > TMAXN) return hipErrorInvalidValue;
+    if (ws_bytes < hetrd_workspace_bytes(n)) return hipErrorInvalidValue;
+    TrArgs g;
+    g.a = (const double2*)a_z;
+    g.vh_re = vh_re;
+    g.vh_im = vh_im;
+    g.n = n;
+    g.lda = n;
+    g.P = (n + TC - 1) / TC;
+    g.d = d;
+    g.e = e;
+    g.tau = (double2*)tau_z;
+    char* p = (char*)ws;
+    g.colbuf = (double2*)p;
+    g.ybuf = g.colbuf + 2 * (size_t)n;
+    g.pdot = g.ybuf + 2 * (size_t)n;
+    int* flags = (int*)(g.pdot + 2 * (size_t)g.P);
+    g.col_flag = flags;
+    g.abort_flag = flags + 1;
+    g.wg_flag = flags + 2;
+    *abort_flag = g.abort_flag;
+    hipError_t err = hipMemsetAsync(flags, 0, sizeof(int) * (size_t)(g.P + 2), stream);
+    if (err != hipSuccess) return err;
+    void* args[] = {&g};
+    return hipLaunchCooperativeKernel((const void*)hetrd_kernel, dim3(g.P), dim3(TT), args, 0, stream);
+}
+
+}  // namespace mpsk

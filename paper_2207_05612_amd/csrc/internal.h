@@ -152,4 +152,39 @@ hipError_t select_rows(const T* u_re, const T* u_im, int64_t S, int D, int sampl
 hipError_t apply_z_phys(const double* re, const double* im, int Dl, int Dr, double* out_re,
                         double* out_im, hipStream_t stream);
 
+// ---------------------------------------------------------------- hetrd.hip
+// Persistent-kernel Householder tridiagonalisation (n <= hetrd_max_n()).
+int hetrd_max_n();
+size_t hetrd_workspace_bytes(int n);
+// Full Hermitian matrix (column-major, interleaved complex) from the lower
+// triangle of a row-major planar matrix.
+hipError_t hermitian_full_colmajor(const double* re, const double* im, int n, double* out_z, hipStream_t stream);
+// a_z: full Hermitian matrix (column-major interleaved, lda = n, read only);
+// d (n), e (n - 1) real; tau_z (n - 1 complex); vh: planar row-major
+// (n - 1) x n, row i = conj(v_i).  *abort_flag points at a device int that
+// is non-zero when the kernel gave up waiting (results then invalid).
+hipError_t hetrd_persistent(const double* a_z, int n, double* d, double* e, double* tau_z, double* vh_re,
+                            double* vh_im, void* ws, size_t ws_bytes, int** abort_flag, hipStream_t stream);
+// T factors (wy_block() x wy_block(), planar row-major, block b at
+// b wy_block()^2) of the compact WY forms of nblk blocks of wy_block()
+// reflectors, from S_b = V_b^H V_b (same layout) and tau (interleaved,
+// nblk wy_block() entries; tau = 0 marks an identity reflector).
+int wy_block();
+hipError_t wy_t_factors(const double* s_re, const double* s_im, int nblk, const double* tau_z, double* t_re,
+                        double* t_im, hipStream_t stream);
+// Top-k eigenvectors of a real column-major eigenvector matrix (ascending
+// eigenvalues) as planar complex row-major n x k, largest first.
+hipError_t take_top_real_eigvecs(const double* evec, int n, int k, double* out_re, double* out_im, hipStream_t stream);
+// Batched FP64 GEMMs: batch z uses A + z sa, B + z sb, C + z sc (elements).
+// The split-K form writes the partial sums of split y, batch z to
+// ws + (y batch + z) M N; splitk_reduce64 over (batch M) x N sums them.
+hipError_t cgemm_f64_batched(int opa, int opb, int M, int N, int K, CView<double> A, int64_t sa, CView<double> B,
+                             int64_t sb, CViewMut<double> C, int64_t sc, int batch, hipStream_t stream);
+hipError_t cgemm_f64_batched_splitk(int opa, int opb, int M, int N, int K, CView<double> A, int64_t sa,
+                                    CView<double> B, int64_t sb, double* ws_re, double* ws_im, int ksplit, int batch,
+                                    hipStream_t stream);
+// C -= op(A) op(B) (FP64 complex, same operand conventions as cgemm_f64).
+hipError_t cgemm_f64_sub(int opa, int opb, int M, int N, int K, CView<double> A, CView<double> B, CViewMut<double> C,
+                         hipStream_t stream);
+
 }  // namespace mpsk

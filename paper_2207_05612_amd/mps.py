@@ -28,7 +28,8 @@ KCLASS = {"contract": 0, "mpo": 1, "gram": 2, "eigh": 3, "other": 4}
 EXPORTS = ("mps_create", "mps_destroy", "apply_layer_dmrg", "apply_layer_dmrg_batched", "fidelity", "sample",
            "mps_last_error",
            "mps_amplitude", "mps_to_statevector", "mps_bond_dims", "mps_get_tensor", "mps_step_log",
-           "mps_expect_zz", "mps_set_profiling", "mps_kernel_stats", "mps_kernel_selftest_cgemm")
+           "mps_expect_zz", "mps_set_profiling", "mps_kernel_stats", "mps_kernel_selftest_cgemm",
+           "mps_kernel_selftest_eigh")
 
 _lib = None
 
@@ -73,6 +74,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mps_set_profiling": (i32, [P, i32]),
         "mps_kernel_stats": (i32, [P, i32, ctypes.POINTER(i64), dp, dp, dp]),
         "mps_kernel_selftest_cgemm": (i32, [i32, i32, i32, i32, i32, i32, dp, dp, dp]),
+        "mps_kernel_selftest_eigh": (i32, [i32, dp, i32, dp, dp, ip]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -215,6 +217,23 @@ def selftest_cgemm(precision: int, opa: int, opb: int, a: np.ndarray, b: np.ndar
     _check(lib.mps_kernel_selftest_cgemm(precision, opa, opb, M, N, K, _dptr(a.view(np.float64)),
                                          _dptr(b.view(np.float64)), _dptr(c.view(np.float64))))
     return c
+
+
+EIGH_ROCSOLVER, EIGH_PERSISTENT = 0, 1
+
+
+def selftest_eigh(a: np.ndarray, method: int = EIGH_PERSISTENT):
+    """Eigenvalues (ascending), eigenvectors (columns) and the method that ran, through the
+    library's FP64 eigensolver (see mps_kernel_selftest_eigh).  Only the lower triangle of a is read."""
+    lib = load_library()
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    n = a.shape[0]
+    w = np.zeros(n)
+    z = np.zeros((n, n), dtype=np.complex128)      # filled column-major: z.T[j] is eigenvector j
+    used = ctypes.c_int(-1)
+    _check(lib.mps_kernel_selftest_eigh(n, _dptr(a.view(np.float64)), method, _dptr(w),
+                                        _dptr(z.view(np.float64)), ctypes.byref(used)))
+    return w, np.ascontiguousarray(z.T), used.value
 
 
 # free functions with the ABI's names
