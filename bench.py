@@ -12,10 +12,14 @@ synchronisations.  All inputs are resident on the GPU when timing starts (the
 gate list of a layer is a few KiB and is copied inside the call).
 
 Prints one JSON line.  ``roofline`` describes the complex-GEMM contraction
-kernels (the dominant kernels of this library): algorithmic flops (8 per
-complex multiply-add) over the summed launch durations measured with HIP
-events on the library's stream.  ``cpu_baseline`` times the FP64 oracle on a
-bounded sample (see ``cpu_baseline()``).
+kernels: algorithmic flops (8 per complex multiply-add) over the summed launch
+durations measured with HIP events on the stream each launch runs on.
+``roofline_tridiag`` does the same for the persistent tridiagonal reduction of
+the FP64 eigensolver ((16/3) n^3 flops per order-n matrix), the kernel with the
+largest total time; it is latency-bound, so it is reported against the FP64
+vector peak.  ``sampling`` times bitstring sampling from the final MPS.
+``cpu_baseline`` times the FP64 oracle on a bounded sample (see
+``cpu_baseline()``).
 """
 from __future__ import annotations
 
@@ -44,11 +48,13 @@ def parse():
     p.add_argument("--warmup", type=int, default=4)
     p.add_argument("--chi", type=int, default=1024)
     p.add_argument("--sweeps", type=int, default=2)
-    p.add_argument("--precision", choices=("fp32", "bf16x3", "fp64"), default="fp32")
+    p.add_argument("--precision", choices=("fp32", "bf16x3", "fp64"), default="bf16x3")
     p.add_argument("--seed", type=int, default=0)
     p.add_argument("--compare-fp64", type=int, default=1,
                    help="also time the same layers with FP64 contractions (1 = yes)")
     p.add_argument("--cpu-baseline", type=int, default=1)
+    p.add_argument("--samples", type=int, default=65536,
+                   help="bitstrings sampled from the final MPS of the timed run (0 = skip)")
     p.add_argument("--progress", action="store_true", help="print one line per layer to stderr")
     p.add_argument("--calibrate-copy-mib", type=int, default=0,
                    help="launch a plain device copy of this many MiB (HBM counter calibration)")
@@ -63,7 +69,7 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def run_layers(mps, circuit, precision, chi, sweeps, warmup, steps, torch, progress=False):
+def run_layers(mps, circuit, precision, chi, sweeps, warmup, steps, torch, progress=False, samples=0):
     st = mps.MPS(circuit.n, None, max_chi=chi, precision=precision)
     for d in range(warmup):
         f = st.apply_layer_dmrg(circuit.layers[d], chi, sweeps)
@@ -80,11 +86,25 @@ def run_layers(mps, circuit, precision, chi, sweeps, warmup, steps, torch, progr
             print("timed layer %d f=%.6f" % (d, fs[-1]), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    stats = {k: st.kernel_stats(k) for k in ("contract", "mpo", "gram", "eigh", "other")}
+    stats = {k: st.kernel_stats(k) for k in ("contract", "mpo", "gram", "tridiag", "eigh", "other")}
     bonds = st.bond_dims()
     fid = st.fidelity()
+    sampling = None
+    if samples > 0:
+        st.sample(min(samples, 4096), seed=1)           # warm-up (buffers, kernels)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.sample(samples, seed=2)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        # per sample and site: (1 x D_k) (D_k x 2 D_k+1) complex MACs
+        flops = 16.0 * samples * sum(bonds[k] * bonds[k + 1] for k in range(len(bonds) - 1))
+        sampling = {"samples": samples, "seconds": ts, "samples_per_s": samples / ts,
+                    "algorithmic_tflops": flops / ts / 1e12, "max_bond": max(bonds)}
+        if progress:
+            print("sampled %d bitstrings in %.2f s" % (samples, ts), file=sys.stderr, flush=True)
     st.close()
-    return dt, fs, stats, bonds, fid
+    return dt, fs, stats, bonds, fid, sampling
 
 
 def cpu_baseline(chi: int, sweeps: int, stats_per_layer_flops: float, n_steps_per_layer: int):
@@ -159,8 +179,8 @@ def main():
     if args.warmup + args.steps > len(c.layers):
         raise SystemExit("warmup + steps must not exceed the circuit depth (20)")
     prec = {"fp32": mps.MPS_FP32, "bf16x3": mps.MPS_BF16X3, "fp64": mps.MPS_FP64}[args.precision]
-    dt, fs, stats, bonds, fid = run_layers(mps, c, prec, args.chi, args.sweeps, args.warmup, args.steps, torch,
-                                           args.progress)
+    dt, fs, stats, bonds, fid, sampling = run_layers(mps, c, prec, args.chi, args.sweeps, args.warmup, args.steps,
+                                                     torch, args.progress, args.samples)
     value = args.steps / dt
     con = stats["contract"]
     achieved = con["flops"] / (con["ms"] * 1e-3) / 1e12 if con["ms"] > 0 else 0.0
@@ -200,9 +220,19 @@ def main():
                                   "cgemm_kernel<%s>" % args.precision, con["launches"], con["ms"])},
         "contraction_frac_of_fp32_mfma_peak": achieved / PEAK["fp32"],
     }
+    tri = stats["tridiag"]
+    if tri["ms"] > 0:
+        tri_tf = tri["flops"] / (tri["ms"] * 1e-3) / 1e12
+        out["roofline_tridiag"] = {"bound": "alu", "achieved": tri_tf, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                                   "frac": tri_tf / PEAK["fp64"], "traffic": None,
+                                   "kernel": "hetrd_kernel (persistent tridiagonal reduction, %d launches, "
+                                             "%.1f ms; latency-bound: one cross-workgroup wait per column)"
+                                             % (tri["launches"], tri["ms"])}
+    if sampling:
+        out["sampling"] = sampling
     if args.compare_fp64 and args.precision != "fp64":
-        dt64, fs64, stats64, _, _ = run_layers(mps, c, mps.MPS_FP64, args.chi, args.sweeps, args.warmup,
-                                               args.steps, torch, args.progress)
+        dt64, fs64, stats64, _, _, _ = run_layers(mps, c, mps.MPS_FP64, args.chi, args.sweeps, args.warmup,
+                                                  args.steps, torch, args.progress)
         c64 = stats64["contract"]
         out["fp64_path"] = {"value": args.steps / dt64, "unit": "gate-layers/s",
                             "contraction_tflops": c64["flops"] / (c64["ms"] * 1e-3) / 1e12,

@@ -181,9 +181,13 @@ typedef enum {
     MPS_KCLASS_CONTRACT = 0,  /* complex GEMMs of the environment / local tensor */
     MPS_KCLASS_MPO = 1,       /* structured MPO application                      */
     MPS_KCLASS_GRAM = 2,      /* FP64 Gram matrices of the truncation            */
-    MPS_KCLASS_EIGH = 3,      /* FP64 Hermitian eigensolver                      */
+    MPS_KCLASS_EIGH = 3,      /* FP64 Hermitian eigensolver (tridiagonal divide
+                                 and conquer, back-transformation, or the dense
+                                 library solver)                                 */
     MPS_KCLASS_OTHER = 4,     /* conversions, reductions, small FP64 GEMMs       */
-    MPS_KCLASS_COUNT = 5
+    MPS_KCLASS_TRIDIAG = 5,   /* FP64 tridiagonal reduction of the eigensolver;
+                                 flops = (16/3) n^3 per order-n matrix           */
+    MPS_KCLASS_COUNT = 6
 } mps_kernel_class;
 
 /* Turn per-launch timing on (1) or off (0) and reset the counters. */

@@ -63,11 +63,11 @@ struct GemmArgs {
     int lower_only;   // skip tiles that hold no element with column <= row
     int kchunk;       // k range of split blockIdx.y: [y kchunk, (y+1) kchunk)
     int64_t split_stride;   // C offset of split y (partial sums); 0 without split
-    int sub;          // C -= A B instead of C = A B
     int64_t sa, sb, sc;     // batch strides (elements) of A, B, C: batch z = blockIdx.z
 };
 
-template <typename TIn, typename TAcc, int OPA, int OPB, int BM, int BN, int BK>
+// SUB: C -= A B instead of C = A B.
+template <typename TIn, typename TAcc, int OPA, int OPB, int BM, int BN, int BK, bool SUB = false>
 __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
     using MF = Mfma<TAcc>;
     constexpr int MT = MF::MT;
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
                 const int c = n0 + wn0 + j * MT + lrow;
                 if (r < M && c < N) {
                     const int64_t off = (int64_t)r * g.ldc + c;
-                    if (g.sub) {
+                    if (SUB) {
                         c_re[off] -= acc_re[i][j][v];
                         c_im[off] -= acc_im[i][j][v];
                     } else {
@@ -260,7 +260,6 @@ static hipError_t launch(int opa, int opb, int M, int N, int K, CView<TIn> A, CV
     g.gm = (M + BM - 1) / BM;
     g.gn = (N + BN - 1) / BN;
     g.lower_only = lower_only;
-    g.sub = sub;
     g.sa = sa;
     g.sb = sb;
     g.sc = sc;
@@ -278,6 +277,12 @@ static hipError_t launch(int opa, int opb, int M, int N, int K, CView<TIn> A, CV
     if (opa == OA && opb == OB) {                                                                 \
         hipLaunchKernelGGL((cgemm_kernel<TIn, TAcc, OA, OB, BM, BN, BK>), grid, block, 0, stream, g); \
         return hipGetLastError();                                                                 \
+    }
+    if (sub) {
+        // the subtracting form exists for the FP64 back-transformation only (opa = C, opb = N)
+        if (sizeof(TAcc) != 8 || opa != OP_C || opb != OP_N) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((cgemm_kernel<TIn, TAcc, OP_C, OP_N, BM, BN, BK, true>), grid, block, 0, stream, g);
+        return hipGetLastError();
     }
     MPS_GEMM_CASE(OP_N, OP_N)
     MPS_GEMM_CASE(OP_N, OP_T)

@@ -609,16 +609,21 @@ void eigh_gram(mps_state* st, EighWork& wk, const double* re, const double* im, 
             HIPCHK(hermitian_full_colmajor(re, im, dim, wk.Z.p, s));
             t.done();
         }
-        Timer t(st, MPS_KCLASS_EIGH, 0, 0);
         int* abort_dev = nullptr;
         int aborted = 1;
-        if (hetrd_persistent(wk.Z.p, dim, wk.evals.p, wk.evwork.p, wk.tau.p, wk.vh.re(), wk.vh.im(), wk.trws.p, wsb,
-                             &abort_dev, s) == hipSuccess) {
-            HIPCHK(hipMemcpyAsync(&aborted, abort_dev, sizeof(int), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-        } else {
-            (void)hipGetLastError();
+        {
+            Timer tr(st, MPS_KCLASS_TRIDIAG, 16.0 / 3.0 * dim * (double)dim * dim, 16.0 * dim * (double)dim);
+            const hipError_t le = hetrd_persistent(wk.Z.p, dim, wk.evals.p, wk.evwork.p, wk.tau.p, wk.vh.re(),
+                                                   wk.vh.im(), wk.trws.p, wsb, &abort_dev, s);
+            tr.done();
+            if (le == hipSuccess) {
+                HIPCHK(hipMemcpyAsync(&aborted, abort_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+            } else {
+                (void)hipGetLastError();
+            }
         }
+        Timer t(st, MPS_KCLASS_EIGH, 0, 0);
         if (!aborted) {
             if (after_reduce) (*after_reduce)();
             rocblas_status rs = rocsolver_dstedc(st->blas, rocblas_evect_tridiagonal, dim, wk.evals.p, wk.evwork.p,

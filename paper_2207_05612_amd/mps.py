@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libmpsdmrg.so")
 
 MPS_OK, MPS_ERR_ARG, MPS_ERR_OOM, MPS_ERR_DEVICE, MPS_ERR_NUMERIC, MPS_ERR_STATE = 0, -1, -2, -3, -4, -5
 MPS_FP64, MPS_FP32, MPS_BF16X3 = 0, 1, 3
-KCLASS = {"contract": 0, "mpo": 1, "gram": 2, "eigh": 3, "other": 4}
+KCLASS = {"contract": 0, "mpo": 1, "gram": 2, "eigh": 3, "other": 4, "tridiag": 5}
 
 # every symbol declared in include/mps_dmrg.h
 EXPORTS = ("mps_create", "mps_destroy", "apply_layer_dmrg", "apply_layer_dmrg_batched", "fidelity", "sample",
