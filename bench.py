@@ -57,7 +57,7 @@ def parse():
                    help="bitstrings sampled from the final MPS of the timed run (0 = skip)")
     p.add_argument("--progress", action="store_true", help="print one line per layer to stderr")
     p.add_argument("--calibrate-copy-mib", type=int, default=0,
-                   help="launch a plain device copy of this many MiB (HBM counter calibration)")
+                   help="fill, then sum, a device buffer of this many MiB (HBM counter calibration)")
     return p.parse_args()
 
 
@@ -69,6 +69,11 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def mark(torch):
+    """A short spin kernel on the current stream: delimits the timed region in profiler traces."""
+    torch.cuda._sleep(1000)
+
+
 def run_layers(mps, circuit, precision, chi, sweeps, warmup, steps, torch, progress=False, samples=0):
     st = mps.MPS(circuit.n, None, max_chi=chi, precision=precision)
     for d in range(warmup):
@@ -78,6 +83,7 @@ def run_layers(mps, circuit, precision, chi, sweeps, warmup, steps, torch, progr
     torch.cuda.synchronize()
     st.set_profiling(True)
     fs = []
+    mark(torch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for d in range(warmup, warmup + steps):
@@ -86,6 +92,7 @@ def run_layers(mps, circuit, precision, chi, sweeps, warmup, steps, torch, progr
             print("timed layer %d f=%.6f" % (d, fs[-1]), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    mark(torch)
     stats = {k: st.kernel_stats(k) for k in ("contract", "mpo", "gram", "tridiag", "eigh", "other")}
     bonds = st.bond_dims()
     fid = st.fidelity()
@@ -168,12 +175,13 @@ def main():
     mps.load_library()
 
     if args.calibrate_copy_mib:
+        # known HBM traffic for the counter calibration: a fill writes the buffer once,
+        # a sum reads it once
         n = args.calibrate_copy_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
+        total = src.sum()
         torch.cuda.synchronize()
+        del src, total
 
     c = circuits.sycamore_like_54_workload(args.seed, depth=20)
     if args.warmup + args.steps > len(c.layers):
@@ -187,8 +195,11 @@ def main():
     peak = PEAK[args.precision]
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
+        # HBM bytes per launch of the same kernel over the same timed launches, from the
+        # FETCH_SIZE / WRITE_SIZE passes; only valid for unchanged kernel sources and launch schedule
         rec = json.load(open(TRAFFIC_FILE))
-        if rec.get("source_hash") == source_hash() and rec.get("precision") == args.precision:
+        if (rec.get("source_hash") == source_hash() and rec.get("precision") == args.precision
+                and rec.get("timed_region_dispatches") == con["launches"]):
             traffic = rec.get("bytes_per_launch")
     total_flops = sum(v["flops"] for v in stats.values())
 
@@ -215,6 +226,7 @@ def main():
         "f_delta": fs,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": con["bytes"] / max(con["launches"], 1),
                      "kernel": "%s (complex planar GEMM, %d launches, %.1f ms)"
                                % ("cgemm_bf16x3_nt_kernel" if args.precision == "bf16x3" else
                                   "cgemm_kernel<%s>" % args.precision, con["launches"], con["ms"])},

@@ -468,6 +468,7 @@ int splitk_for(int64_t M, int64_t N, int64_t K) {
     return (int)std::max<int64_t>(1, ks);
 }
 
+// Each launch is timed on its own; the split-K reduction counts as OTHER.
 template <typename R>
 void gemm(mps_state* st, int cls, int opa, int opb, int64_t M, int64_t N, int64_t K, const R* ar,
           const R* ai, int64_t lda, const R* br, const R* bi, int64_t ldb, R* cr, R* ci, int64_t ldc,
@@ -476,18 +477,24 @@ void gemm(mps_state* st, int cls, int opa, int opb, int64_t M, int64_t N, int64_
     const Lane ln = lane ? *lane : main_lane(st);
     const double fl = 8.0 * (double)M * (double)N * (double)K;
     const double by = 2.0 * sizeof(R) * ((double)M * K + (double)K * N + (double)M * N);
-    Timer t(st, cls, fl, by, ln.s);
     const int ks = sizeof(R) == 4 ? splitk_chunks((int)K, splitk_for(M, N, K), 16) : 1;
     if (ks > 1) {
         ln.ws->ensure(M * N * ks, ln.s);
-        HIPCHK(cgemm_f32_splitk(opa, opb, (int)M, (int)N, (int)K, {(const float*)ar, (const float*)ai, lda},
-                                {(const float*)br, (const float*)bi, ldb}, ln.ws->re(), ln.ws->im(),
-                                splitk_for(M, N, K), ln.s));
+        {
+            Timer t(st, cls, fl, by, ln.s);
+            HIPCHK(cgemm_f32_splitk(opa, opb, (int)M, (int)N, (int)K, {(const float*)ar, (const float*)ai, lda},
+                                    {(const float*)br, (const float*)bi, ldb}, ln.ws->re(), ln.ws->im(),
+                                    splitk_for(M, N, K), ln.s));
+            t.done();
+        }
+        Timer t(st, MPS_KCLASS_OTHER, 0, 8.0 * (double)M * N * (ks + 1), ln.s);
         HIPCHK(splitk_reduce(ln.ws->re(), ln.ws->im(), ks, M, N, (float*)cr, (float*)ci, ldc, ln.s));
+        t.done();
     } else {
+        Timer t(st, cls, fl, by, ln.s);
         HIPCHK(gemm_raw<R>(opa, opb, (int)M, (int)N, (int)K, ar, ai, lda, br, bi, ldb, cr, ci, ldc, ln.s));
+        t.done();
     }
-    t.done();
 }
 
 // Split-precision (BF16 x 3) complex GEMM, C = A B^T with both operands k-contiguous.
@@ -498,17 +505,23 @@ void gemm_split(mps_state* st, int cls, int64_t M, int64_t N, int64_t K, const f
     const Lane ln = lane ? *lane : main_lane(st);
     const double fl = 8.0 * (double)M * (double)N * (double)K;
     const double by = 8.0 * ((double)M * K + (double)K * N + (double)M * N);
-    Timer t(st, cls, fl, by, ln.s);
     const int ks = splitk_chunks((int)K, splitk_for(M, N, K), 16);
     if (ks > 1) {
         ln.ws->ensure(M * N * ks, ln.s);
-        HIPCHK(cgemm_bf16x3_nt_splitk((int)M, (int)N, (int)K, {ar, ai, lda}, {br, bi, ldb}, ln.ws->re(),
-                                      ln.ws->im(), splitk_for(M, N, K), ln.s));
+        {
+            Timer t(st, cls, fl, by, ln.s);
+            HIPCHK(cgemm_bf16x3_nt_splitk((int)M, (int)N, (int)K, {ar, ai, lda}, {br, bi, ldb}, ln.ws->re(),
+                                          ln.ws->im(), splitk_for(M, N, K), ln.s));
+            t.done();
+        }
+        Timer t(st, MPS_KCLASS_OTHER, 0, 8.0 * (double)M * N * (ks + 1), ln.s);
         HIPCHK(splitk_reduce(ln.ws->re(), ln.ws->im(), ks, M, N, cr, ci, ldc, ln.s));
+        t.done();
     } else {
+        Timer t(st, cls, fl, by, ln.s);
         HIPCHK(cgemm_bf16x3_nt((int)M, (int)N, (int)K, {ar, ai, lda}, {br, bi, ldb}, {cr, ci, ldc}, ln.s));
+        t.done();
     }
-    t.done();
 }
 
 // Hermitian Gram product (lower tiles only) with FP64 accumulation; long k
