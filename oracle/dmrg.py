@@ -31,8 +31,16 @@ Readings where the paper is silent (each one is listed in the design notes):
   * composite MPO bonds order the open gates by their left chain site, the
     leftmost gate being the most significant digit.
 
+Single-site variant (the paper's production rule, Sec. IV.B, eq:optimization
+with one free tensor): the same zip-up, then sweeps that optimise one tensor
+at a time, F = L A W R, M = F / sqrt(f) with f = |F|^2, and move the
+orthogonality centre by a QR (left-to-right) or LQ (right-to-left) of M.  The
+bond dimensions are those of the zip-up (they can only shrink, when the QR of
+a site has fewer rows than columns).  Readings: one single-site sweep visits
+all n sites; f_delta is the f of the last site of the last sweep.
+
 Everything here is plain and slow on purpose: dense MPO tensors, einsum, and
-LAPACK's SVD.
+LAPACK's SVD and QR.
 """
 from __future__ import annotations
 
@@ -310,11 +318,69 @@ def sweep_right_to_left(a, w, b, chi, envs, log):
     return f
 
 
+# ------------------------------------------------ single-site sweeps ------
+def single_site_tensor(lenv, a, w, renv):
+    """Local tensor of one site, F[p, s, q] = sum L[p,b,x] A[x,t,y] W[b,s,t,c] R[q,c,y]
+    (eq:scalarproduct with one free tensor)."""
+    x = _ein("pbx,xty->pbty", lenv, a)
+    x = _ein("pbty,bstc->pscy", x, w)
+    return _ein("pscy,qcy->psq", x, renv)
+
+
+def sweep_single_left_to_right(a, w, b, envs, log):
+    n = len(a)
+    envs[0] = np.ones((1, 1, 1), dtype=np.complex128)
+    f = None
+    for k in range(n):
+        m = single_site_tensor(envs[k], a[k], w[k], envs[k + 1])
+        f = float(np.sum(np.abs(m) ** 2))
+        if not f > 0.0:
+            raise FloatingPointError("local tensor has zero norm")
+        cl, _, cr = m.shape
+        if k == n - 1:
+            b[k] = m / math.sqrt(f)
+            log.append(StepRecord("l2r1", k + 1, f, f, cr))
+            break
+        q, _ = np.linalg.qr(m.reshape(cl * 2, cr))          # M = Q R, Q left-isometric
+        b[k] = q.reshape(cl, 2, q.shape[1])
+        envs[k + 1] = env_left_step(envs[k], a[k], w[k], b[k])
+        log.append(StepRecord("l2r1", k + 1, f, f, q.shape[1]))
+    return f
+
+
+def sweep_single_right_to_left(a, w, b, envs, log):
+    n = len(a)
+    envs[n] = np.ones((1, 1, 1), dtype=np.complex128)
+    f = None
+    for k in range(n - 1, -1, -1):
+        m = single_site_tensor(envs[k], a[k], w[k], envs[k + 1])
+        f = float(np.sum(np.abs(m) ** 2))
+        if not f > 0.0:
+            raise FloatingPointError("local tensor has zero norm")
+        cl, _, cr = m.shape
+        if k == 0:
+            b[k] = m / math.sqrt(f)
+            log.append(StepRecord("r2l1", k, f, f, cl))
+            break
+        # M = L Q with Q right-isometric: QR of M^H
+        q, _ = np.linalg.qr(m.reshape(cl, 2 * cr).conj().T)
+        b[k] = q.conj().T.reshape(q.shape[1], 2, cr)
+        envs[k] = env_right_step(envs[k + 1], a[k], w[k], b[k])
+        log.append(StepRecord("r2l1", k, f, f, q.shape[1]))
+    return f
+
+
 # ------------------------------------------------------ compression step ---
-def apply_layer(state: OracleMPS, layer, chi: int, n_sweeps: int) -> float:
-    """One compression step (K = 1): fit a bond-chi MPS to W|psi>, return f_delta."""
+def apply_layer(state: OracleMPS, layer, chi: int, n_sweeps: int, update: str = "two-site") -> float:
+    """One compression step (K = 1): fit a bond-chi MPS to W|psi>, return f_delta.
+
+    update = "two-site" (SVD split of each pair, bond dimensions up to chi) or
+    "single-site" (bond dimensions of the zip-up, QR moves of the centre)."""
     if chi < 1 or n_sweeps < 0:
         raise ValueError("chi >= 1 and n_sweeps >= 0 required")
+    if update not in ("two-site", "single-site"):
+        raise ValueError("update must be 'two-site' or 'single-site'")
+    single = update == "single-site"
     n = state.n
     w, _ = layer_mpo(n, layer)
     a = state.tensors
@@ -331,10 +397,12 @@ def apply_layer(state: OracleMPS, layer, chi: int, n_sweeps: int) -> float:
     if n >= 2:
         for _ in range(n_sweeps):
             if direction == "r2l":
-                f = sweep_right_to_left(a, w, b, chi, envs, log)
+                f = (sweep_single_right_to_left(a, w, b, envs, log) if single
+                     else sweep_right_to_left(a, w, b, chi, envs, log))
                 center, direction = 0, "l2r"
             else:
-                f = sweep_left_to_right(a, w, b, chi, envs, log)
+                f = (sweep_single_left_to_right(a, w, b, envs, log) if single
+                     else sweep_left_to_right(a, w, b, chi, envs, log))
                 center, direction = n - 1, "r2l"
     state.tensors = b
     state.center = center

@@ -310,3 +310,74 @@ def test_qaoa_swap_network_equals_direct_circuit():
         bits = [(x >> (n - 1 - k)) & 1 for k in range(n)]
         c_sv += probs[x] * sum(bits[u] != bits[v] for u, v in edges)
     assert abs(c_mps - c_sv) < 1e-10
+
+
+# ------------------------------------------------- single-site update ------
+def test_single_site_exact_regime_matches_statevector():
+    """P1 for the single-site update: chi >= 2^(n/2) keeps the state exact and F~ = 1."""
+    c = circuits.plain_fp64_workload(0)
+    st = dmrg.product_state(c.n)
+    for layer in c.layers:
+        dmrg.apply_layer(st, layer, chi=64, n_sweeps=2, update="single-site")
+    psi = sv.run(c)
+    phi = dmrg.to_statevector(st)
+    assert np.linalg.norm(phi - psi) / np.linalg.norm(psi) < 1e-12
+    assert abs(math.exp(st.log_f) - 1.0) < 1e-12
+    assert st.n_2q == c.n_2q
+
+
+@pytest.mark.parametrize("chi", [3, 6])
+def test_single_site_invariants_and_overlap(chi):
+    """P4 for the single-site update: ||phi|| = 1, every non-centre tensor an isometry, f
+    non-decreasing from the zip-up over all steps of the layer, and f_delta equal to the exact
+    overlap |<phi|U|psi>|^2 computed by statevector simulation of the layer."""
+    c = circuits.plain_fp64_workload(3)
+    st = dmrg.product_state(c.n)
+    for layer in c.layers:
+        before = len(st.step_log)
+        prev_vec = dmrg.to_statevector(st)
+        dims_before = st.bond_dims()
+        f = dmrg.apply_layer(st, layer, chi=chi, n_sweeps=3, update="single-site")
+        phi = dmrg.to_statevector(st)
+        assert abs(np.linalg.norm(phi) - 1.0) < 1e-12
+        assert 0.0 < f <= 1.0 + 1e-12
+        fs = [r.f for r in st.step_log[before:]]
+        assert all(b >= a - 1e-12 for a, b in zip(fs, fs[1:])), fs
+        target = sv.apply_layer(prev_vec, c.n, layer)
+        assert abs(abs(np.vdot(phi, target)) ** 2 - f) < 1e-11
+        assert max(st.bond_dims()) <= chi
+        # odd number of sweeps: the centre ends where the zip-up started
+        ctr = st.center
+        for k, a in enumerate(st.tensors):
+            if k == ctr:
+                continue
+            if k < ctr:
+                m = a.reshape(-1, a.shape[2])
+                assert np.allclose(m.conj().T @ m, np.eye(m.shape[1]), atol=1e-12)
+            else:
+                m = a.reshape(a.shape[0], -1)
+                assert np.allclose(m @ m.conj().T, np.eye(m.shape[0]), atol=1e-12)
+        assert st.bond_dims()[0] == st.bond_dims()[-1] == 1
+        del dims_before
+
+
+def test_single_site_update_is_the_local_optimum():
+    """eq:optimization with one free tensor: with every other tensor fixed, M = F/|F| maximises
+    |<phi(M)|U|psi>|^2 and the maximum is |F|^2 (brute force over random perturbations)."""
+    rng = np.random.default_rng(5)
+    c = circuits.random_brickwork(6, 3, seed=11)
+    st = dmrg.run_circuit(c, chi=3, n_sweeps=1, depth=2)
+    prev_vec = dmrg.to_statevector(st)
+    layer = c.layers[2]
+    dmrg.apply_layer(st, layer, chi=3, n_sweeps=1, update="single-site")
+    target = sv.apply_layer(prev_vec, c.n, layer)
+    f_best = st.layer_f[-1]
+    ctr = st.center
+    base = st.tensors[ctr].copy()
+    for _ in range(20):
+        pert = base + 0.05 * (rng.standard_normal(base.shape) + 1j * rng.standard_normal(base.shape))
+        st.tensors[ctr] = pert / np.linalg.norm(pert)
+        val = abs(np.vdot(dmrg.to_statevector(st), target)) ** 2
+        assert val <= f_best + 1e-12
+    st.tensors[ctr] = base
+    assert abs(abs(np.vdot(dmrg.to_statevector(st), target)) ** 2 - f_best) < 1e-12
