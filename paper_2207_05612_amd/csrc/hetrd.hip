@@ -306,7 +306,20 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrArgs g) {
             vcol[tid] = vc;
             ycol[tid] = yc;
         }
-        // the owner of column i records d_i, e_i, tau_i and the reflector
+        // d_i before x is reused
+        double d_i = 0.0;
+#pragma unroll
+        for (int q = 0; q < TQ; ++q)
+            if (tid + TT * q == i) d_i = x[q].x;
+        __syncthreads();
+        if (tid == 0) {
+            double2 pd = make_double2(0.0, 0.0);
+            for (int j = 0; j < TC; ++j) pd = cadd(pd, cjmul(ycol[j], vcol[j]));
+            st_coh(&g.pdot[(int64_t)buf * P + wg], pd);
+        }
+        publish(g.wg_flag + wg, i + 1);
+        // the owner of column i records d_i, e_i, tau_i and the reflector; issued after
+        // the flag so that the publication does not wait for these stores
         if (wg == i % P) {
 #pragma unroll
             for (int q = 0; q < TQ; ++q) {
@@ -315,20 +328,13 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrArgs g) {
                     g.vh_re[(int64_t)i * n + r] = v[q].x;
                     g.vh_im[(int64_t)i * n + r] = -v[q].y;
                 }
-                if (r == i) g.d[i] = x[q].x;
+                if (r == i) g.d[i] = d_i;
             }
             if (tid == 0) {
                 g.e[i] = beta;
                 g.tau[i] = tau;
             }
         }
-        __syncthreads();
-        if (tid == 0) {
-            double2 pd = make_double2(0.0, 0.0);
-            for (int j = 0; j < TC; ++j) pd = cadd(pd, cjmul(ycol[j], vcol[j]));
-            st_coh(&g.pdot[(int64_t)buf * P + wg], pd);
-        }
-        publish(g.wg_flag + wg, i + 1);
         // ---- wait for every workgroup's y entries and partial y^H v (and the
         //      column published one step earlier)
         bool ok = true;
