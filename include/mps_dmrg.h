@@ -108,6 +108,18 @@ mps_status mps_destroy(mps_state* state);
 mps_status apply_layer_dmrg(mps_state* state, const mps_gate* gates, int n_gates,
                             int chi, int n_sweeps, double* f_layer);
 
+/* The compression step with single-site sweeps (the update rule of Sec. IV.B
+ * with one free tensor, eq:optimization): the same zip-up as
+ * apply_layer_dmrg (which fixes the bond dimensions, at most chi), then
+ * n_sweeps passes in alternating directions over all n sites.  At site j
+ * the local tensor F_j = L_{j-1} A_j W_j R_{j+1} is computed, f = |F_j|^2,
+ * M = F_j / sqrt(f), and the orthogonality centre moves on by an FP64 QR of
+ * M (its column space is kept: bond dimensions only shrink where a site has
+ * fewer rows than columns).  f_layer receives the f of the last site of the
+ * last pass.  Arguments, ownership and errors as for apply_layer_dmrg. */
+mps_status apply_layer_dmrg_single_site(mps_state* state, const mps_gate* gates, int n_gates,
+                                        int chi, int n_sweeps, double* f_layer);
+
 /* Apply one layer to each of `batch` independent states (the compression
  * step above, per instance), concurrently: instances are driven by up to 8
  * host threads and run on their own streams, so give every state its own

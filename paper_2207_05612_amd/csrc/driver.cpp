@@ -722,7 +722,8 @@ struct Engine {
     bool split = false;   // BF16 x 3 contractions (R = float only): operands kept k-contiguous
     Planar<double> TH64, GR, U64, V64, M64;
     EighWork ew;
-    Raw<double> svec;
+    Raw<double> svec, QZ, QG, QT;
+    Raw<int> QI;
     std::vector<double> hvals;
 
     Engine(mps_state* state, int chi_) : st(state), s(state->stream), n(state->n), chi(chi_) {}
@@ -735,7 +736,7 @@ struct Engine {
             for (auto& e : psi[o]) e.release(s);
         X.release(s); T2.release(s); TH.release(s); UR.release(s); T2T.release(s);
         TH64.release(s); GR.release(s); U64.release(s); V64.release(s); M64.release(s);
-        ew.release(s); svec.release(s);
+        ew.release(s); svec.release(s); QZ.release(s); QG.release(s); QT.release(s); QI.release(s);
         for (auto& p : phi) p.release(s);
     }
 
@@ -847,6 +848,60 @@ struct Engine {
         HIPCHK(hipStreamSynchronize(s));  // host vectors above must outlive their copies
         tr.caseA = false;
         return tr;
+    }
+
+    // FP64 QR of the planar row-major rows x cols matrix (re, im): U64 <- Q
+    // (rows x k, k = min(rows, cols)), an orthonormal basis of its column space
+    // with the order of the columns kept (M = Q R, R upper triangular).
+    // Cholesky QR twice when rows >= cols: each pass G = X^H X (rocBLAS herk),
+    // R = chol(G) (rocSOLVER potrf), X <- X R^{-1} (rocBLAS trsm); the second
+    // pass restores orthogonality to rounding for condition numbers up to
+    // ~1e7.  Householder QR (rocSOLVER geqrf + ungqr) when rows < cols or when
+    // a Cholesky factorisation fails.
+    int qr_orth(int64_t rows, int64_t cols, const double* re, const double* im) {
+        const int64_t k = std::min(rows, cols);
+        QZ.ensure(2 * rows * cols, s);
+        HIPCHK(rm_planar_to_cm(re, im, rows, cols, QZ.p, s));
+        rocblas_double_complex* X = (rocblas_double_complex*)QZ.p;
+        const rocblas_double_complex one(1.0, 0.0);
+        const double one_r = 1.0, zero_r = 0.0;
+        bool ok = false;
+        {
+            Timer t(st, MPS_KCLASS_EIGH, 0, 0);
+            if (rows >= cols) {
+                QG.ensure(2 * cols * cols, s);
+                QI.ensure(2, s);
+                rocblas_double_complex* G = (rocblas_double_complex*)QG.p;
+                bool st_ok = true;
+                for (int pass = 0; pass < 2 && st_ok; ++pass) {
+                    st_ok = rocblas_zherk(st->blas, rocblas_fill_upper, rocblas_operation_conjugate_transpose, (int)cols,
+                                          (int)rows, &one_r, X, (int)rows, &zero_r, G, (int)cols) == rocblas_status_success;
+                    st_ok = st_ok && rocsolver_zpotrf(st->blas, rocblas_fill_upper, (int)cols, G, (int)cols,
+                                                      QI.p + pass) == rocblas_status_success;
+                    st_ok = st_ok && rocblas_ztrsm(st->blas, rocblas_side_right, rocblas_fill_upper,
+                                                   rocblas_operation_none, rocblas_diagonal_non_unit, (int)rows,
+                                                   (int)cols, &one, G, (int)cols, X, (int)rows) == rocblas_status_success;
+                }
+                int hinfo[2] = {1, 1};
+                if (st_ok) {
+                    HIPCHK(hipMemcpyAsync(hinfo, QI.p, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+                    HIPCHK(hipStreamSynchronize(s));
+                }
+                ok = st_ok && hinfo[0] == 0 && hinfo[1] == 0;
+                if (!ok) HIPCHK(rm_planar_to_cm(re, im, rows, cols, QZ.p, s));   // restart from M
+            }
+            if (!ok) {
+                QT.ensure(2 * k, s);
+                rocblas_double_complex* tau = (rocblas_double_complex*)QT.p;
+                if (rocsolver_zgeqrf(st->blas, (int)rows, (int)cols, X, (int)rows, tau) != rocblas_status_success ||
+                    rocsolver_zungqr(st->blas, (int)rows, (int)k, (int)k, X, (int)rows, tau) != rocblas_status_success)
+                    fail(MPS_ERR_DEVICE, "rocsolver QR failed");
+            }
+            t.done();
+        }
+        U64.ensure(rows * k, s);
+        HIPCHK(cm_to_rm_planar(QZ.p, rows, k, U64.re(), U64.im(), s));
+        return (int)k;
     }
 
     void set_scalar(int idx, double v) {
@@ -1048,11 +1103,56 @@ struct Engine {
         return f;
     }
 
+    // Single-site pass in view o (the paper's update with one free tensor):
+    // F_j = (L_j A_j W_j) R_{j+1}^T over the MPO bond and the psi bond right of
+    // site j (rows (cL, s), columns cR), f = |F|^2, M = F / sqrt(f); the centre
+    // moves right by an FP64 QR of M.  Bond dimensions can only shrink (when
+    // 2 cL < cR).  The last site keeps M.
+    double sweep_single(int o) {
+        double f = 0;
+        for (int j = 0; j < n; ++j) {
+            left_block(o, j);
+            const int bL = bnd(o, j), bM = bnd(o, j + 1);
+            const int64_t cL = cb[bL], cM = cb[bM], wM = mpo.w[bM], DM = st->bond[bM];
+            const int64_t rows = 2 * cL, K = wM * DM;
+            TH.ensure(rows * cM, s);
+            TH64.ensure(rows * cM, s);
+            if (split)
+                gemm_split(st, MPS_KCLASS_CONTRACT, rows, cM, K, (const float*)T2.re(), (const float*)T2.im(), K,
+                           (const float*)env[bM].re(), (const float*)env[bM].im(), K, (float*)TH.re(),
+                           (float*)TH.im(), cM);
+            else
+                gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_T, rows, cM, K, T2.re(), T2.im(), K, env[bM].re(),
+                        env[bM].im(), K, TH.re(), TH.im(), cM);
+            HIPCHK((convert_planar<R, double>(TH.re(), TH.im(), rows * cM, TH64.re(), TH64.im(), s)));
+            HIPCHK(norm2<double>(TH64.re(), TH64.im(), rows * cM, st->partial.p, st->dscal.p + 1, s));
+            HIPCHK(hipMemcpyAsync(&f, st->dscal.p + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (!(f > 0) || !std::isfinite(f)) fail(MPS_ERR_NUMERIC, "local tensor has zero or non-finite norm");
+            if (f > 1.0 + 1e-3) fail(MPS_ERR_NUMERIC, "partial fidelity above 1: " + std::to_string(f));
+            if (j == n - 1) {
+                const int k0 = site(o, j);
+                phi[k0].ensure(rows * cM, s);
+                HIPCHK((convert_planar<double, double>(TH64.re(), TH64.im(), rows * cM, phi[k0].re(), phi[k0].im(), s)));
+                set_scalar(0, 1.0 / std::sqrt(f));
+                HIPCHK(scale_by_device_scalar<double>(phi[k0].re(), phi[k0].im(), rows * cM, st->dscal.p, s));
+                log_step(f, f, (int)cM);
+                break;
+            }
+            const int k = qr_orth(rows, cM, TH64.re(), TH64.im());
+            finish_left(o, j, Trunc{k, f, f, true}, true);
+            log_step(f, f, k);
+        }
+        return f;
+    }
+
     void log_step(double f, double s2, int k) {
         st->log_step_f.push_back(f);
         st->log_step_s2.push_back(s2);
         st->log_step_chi.push_back(k);
     }
+
+    bool single_site = false;
 
     double run(const mps_gate* gates, int n_gates, int n_sweeps) {
         mpo = build_layer_mpo(n, gates, n_gates);
@@ -1063,7 +1163,7 @@ struct Engine {
         if (n >= 2) {
             int o = 1 - oz;
             for (int sw = 0; sw < n_sweeps; ++sw) {
-                f = sweep(o);
+                f = single_site ? sweep_single(o) : sweep(o);
                 last = o;
                 o = 1 - o;
             }
@@ -1111,7 +1211,8 @@ void check_state(const mps_state* st) {
 }
 
 
-void apply_layer_impl(mps_state* st, const mps_gate* gates, int n_gates, int chi, int n_sweeps, double* f_layer) {
+void apply_layer_impl(mps_state* st, const mps_gate* gates, int n_gates, int chi, int n_sweeps, double* f_layer,
+                      bool single_site = false) {
     check_state(st);
     if (n_gates < 0 || (n_gates > 0 && !gates)) fail(MPS_ERR_ARG, "gates is NULL");
     if (chi < 1 || chi > st->max_chi) fail(MPS_ERR_ARG, "chi must be in [1, max_chi]");
@@ -1124,9 +1225,11 @@ void apply_layer_impl(mps_state* st, const mps_gate* gates, int n_gates, int chi
         if (st->prec == MPS_FP32 || st->prec == MPS_BF16X3) {
             Engine<float> e(st, chi);
             e.split = st->prec == MPS_BF16X3;
+            e.single_site = single_site;
             f = e.run(gates, n_gates, n_sweeps);
         } else {
             Engine<double> e(st, chi);
+            e.single_site = single_site;
             f = e.run(gates, n_gates, n_sweeps);
         }
         HIPCHK(hipStreamSynchronize(st->stream));
@@ -1227,6 +1330,11 @@ mps_status mps_destroy(mps_state* st) {
 mps_status apply_layer_dmrg(mps_state* st, const mps_gate* gates, int n_gates, int chi, int n_sweeps,
                             double* f_layer) {
     return run_guarded([&] { apply_layer_impl(st, gates, n_gates, chi, n_sweeps, f_layer); });
+}
+
+mps_status apply_layer_dmrg_single_site(mps_state* st, const mps_gate* gates, int n_gates, int chi, int n_sweeps,
+                            double* f_layer) {
+    return run_guarded([&] { apply_layer_impl(st, gates, n_gates, chi, n_sweeps, f_layer, true); });
 }
 
 mps_status apply_layer_dmrg_batched(mps_state* const* states, int batch, const mps_gate* const* gates,

@@ -112,6 +112,12 @@ template <typename T>
 hipError_t norm2(const T* re, const T* im, int64_t n, double* partial, double* out,
                  hipStream_t stream);
 
+// Planar row-major rows x cols <-> interleaved column-major (LAPACK layout).
+hipError_t rm_planar_to_cm(const double* re, const double* im, int64_t rows, int64_t cols, double* out_z,
+                           hipStream_t stream);
+hipError_t cm_to_rm_planar(const double* in_z, int64_t rows, int64_t cols, double* re, double* im,
+                           hipStream_t stream);
+
 // Row-major planar Hermitian n x n -> interleaved column-major (LAPACK layout).
 // Only the row-major lower triangle is meaningful on input; it becomes the
 // column-major upper triangle, which is what the eigensolver reads.

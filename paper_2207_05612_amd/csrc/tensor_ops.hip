@@ -551,4 +551,59 @@ hipError_t adjoint_to_f32(const double* re, const double* im, int64_t m, int64_t
     return hipGetLastError();
 }
 
+// Planar row-major (rows x cols) <-> interleaved column-major (LAPACK layout),
+// through 64 x 64 LDS tiles so that both sides are read and written in order.
+__global__ __launch_bounds__(256) void rm_planar_to_cm_kernel(const double* __restrict__ re,
+                                                             const double* __restrict__ im, int64_t rows,
+                                                             int64_t cols, double2* __restrict__ out) {
+    __shared__ double2 t[64][65];
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int a = ty; a < 64; a += 4) {
+        const int64_t r = r0 + a, c = c0 + tx;
+        if (r < rows && c < cols) t[a][tx] = make_double2(re[r * cols + c], im[r * cols + c]);
+    }
+    __syncthreads();
+    for (int a = ty; a < 64; a += 4) {
+        const int64_t c = c0 + a, r = r0 + tx;
+        if (r < rows && c < cols) out[r + c * rows] = t[tx][a];
+    }
+}
+
+__global__ __launch_bounds__(256) void cm_to_rm_planar_kernel(const double2* __restrict__ in, int64_t rows,
+                                                             int64_t cols, double* __restrict__ re,
+                                                             double* __restrict__ im) {
+    __shared__ double2 t[64][65];
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int a = ty; a < 64; a += 4) {
+        const int64_t c = c0 + a, r = r0 + tx;
+        if (r < rows && c < cols) t[tx][a] = in[r + c * rows];
+    }
+    __syncthreads();
+    for (int a = ty; a < 64; a += 4) {
+        const int64_t r = r0 + a, c = c0 + tx;
+        if (r < rows && c < cols) {
+            re[r * cols + c] = t[a][tx].x;
+            im[r * cols + c] = t[a][tx].y;
+        }
+    }
+}
+
+hipError_t rm_planar_to_cm(const double* re, const double* im, int64_t rows, int64_t cols, double* out_z,
+                           hipStream_t stream) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64));
+    hipLaunchKernelGGL(rm_planar_to_cm_kernel, grid, dim3(256), 0, stream, re, im, rows, cols, (double2*)out_z);
+    return hipGetLastError();
+}
+
+hipError_t cm_to_rm_planar(const double* in_z, int64_t rows, int64_t cols, double* re, double* im,
+                           hipStream_t stream) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64));
+    hipLaunchKernelGGL(cm_to_rm_planar_kernel, grid, dim3(256), 0, stream, (const double2*)in_z, rows, cols, re, im);
+    return hipGetLastError();
+}
+
 }  // namespace mpsk

@@ -25,7 +25,8 @@ MPS_FP64, MPS_FP32, MPS_BF16X3 = 0, 1, 3
 KCLASS = {"contract": 0, "mpo": 1, "gram": 2, "eigh": 3, "other": 4, "tridiag": 5}
 
 # every symbol declared in include/mps_dmrg.h
-EXPORTS = ("mps_create", "mps_destroy", "apply_layer_dmrg", "apply_layer_dmrg_batched", "fidelity", "sample",
+EXPORTS = ("mps_create", "mps_destroy", "apply_layer_dmrg", "apply_layer_dmrg_single_site",
+           "apply_layer_dmrg_batched", "fidelity", "sample",
            "mps_last_error",
            "mps_amplitude", "mps_to_statevector", "mps_bond_dims", "mps_get_tensor", "mps_step_log",
            "mps_expect_zz", "mps_set_profiling", "mps_kernel_stats", "mps_kernel_selftest_cgemm",
@@ -61,6 +62,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mps_create": (i32, [i32, P, i32, i32, P, ctypes.POINTER(P)]),
         "mps_destroy": (i32, [P]),
         "apply_layer_dmrg": (i32, [P, P, i32, i32, i32, dp]),
+        "apply_layer_dmrg_single_site": (i32, [P, P, i32, i32, i32, dp]),
         "apply_layer_dmrg_batched": (i32, [ctypes.POINTER(P), i32, ctypes.POINTER(P), ip, ip, i32, dp]),
         "fidelity": (i32, [P, dp, dp, ip, ctypes.POINTER(i64)]),
         "sample": (i32, [P, i64, u64, P]),
@@ -134,11 +136,18 @@ class MPS:
             pass
 
     # -- the compression step ------------------------------------------------
-    def apply_layer_dmrg(self, layer, chi: int, n_sweeps: int) -> float:
+    def apply_layer_dmrg(self, layer, chi: int, n_sweeps: int, update: str = "two-site") -> float:
+        """update = "two-site" (apply_layer_dmrg) or "single-site" (apply_layer_dmrg_single_site)."""
         rec = layer if isinstance(layer, np.ndarray) else circuits.pack_layer(layer)
         rec = np.ascontiguousarray(rec, dtype=circuits.GATE_DTYPE)
         f = ctypes.c_double(0.0)
-        _check(_lib.apply_layer_dmrg(self._h, rec.ctypes.data, len(rec), chi, n_sweeps, ctypes.byref(f)))
+        if update == "two-site":
+            fn = _lib.apply_layer_dmrg
+        elif update == "single-site":
+            fn = _lib.apply_layer_dmrg_single_site
+        else:
+            raise ValueError("update must be 'two-site' or 'single-site'")
+        _check(fn(self._h, rec.ctypes.data, len(rec), chi, n_sweeps, ctypes.byref(f)))
         return f.value
 
     def fidelity(self):

@@ -1,0 +1,177 @@
+"""GPU parity of the single-site update (apply_layer_dmrg_single_site) with the oracle.
+
+The single-site rule (Sec. IV.B, eq:optimization with one free tensor) keeps
+the zip-up's bond dimensions and moves the orthogonality centre by an FP64
+QR.  The QR basis is gauge (a unitary within the kept columns), so the
+comparisons use gauge-invariant quantities: f of every layer, bond
+dimensions, amplitudes and statevectors.
+
+Tolerances (as for the two-site path):
+  * FP64: per-layer f within 1e-10 relative, identical bond dimensions,
+    amplitudes within 1e-9 relative L2 (1e-7 at 20 qubits after ten
+    truncated layers);
+  * FP32 and split BF16: per-layer f within 1e-4 relative; amplitudes within
+    1e-5 (FP32) and 1e-3 (split), or 8x the oracle's own amplitude change
+    under relative input noise of the path's unit roundoff, whichever is
+    larger (the kept subspace of a truncated layer can be ill-conditioned).
+"""
+import numpy as np
+import pytest
+
+from paper_2207_05612_amd import circuits, mps
+from oracle import dmrg
+from oracle import statevector as sv
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32, BF16X3 = mps.MPS_FP64, mps.MPS_FP32, mps.MPS_BF16X3
+F_TOL = {FP64: 1e-10, FP32: 1e-4, BF16X3: 1e-4}
+AMP_TOL = {FP64: 1e-9, FP32: 1e-5, BF16X3: 1e-3}
+EPS = {FP64: 2.2e-16, FP32: 1.2e-7, BF16X3: 2.4e-7}
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def run_gpu(c, chi, sweeps, prec, depth=None):
+    st = mps.MPS(c.n, None, max_chi=max(chi, 1), precision=prec)
+    layers = c.layers if depth is None else c.layers[:depth]
+    fs = np.array([st.apply_layer_dmrg(layer, chi, sweeps, update="single-site") for layer in layers])
+    return st, fs
+
+
+def run_oracle(c, chi, sweeps, depth=None):
+    st = dmrg.product_state(c.n)
+    layers = c.layers if depth is None else c.layers[:depth]
+    for layer in layers:
+        dmrg.apply_layer(st, layer, chi, sweeps, update="single-site")
+    return st
+
+
+def sensitivity(c, chi, sweeps, noise, bits=None, trials=3):
+    """Largest amplitude change of the oracle under relative noise on every layer's input tensors."""
+    ref = run_oracle(c, chi, sweeps)
+    pick = (lambda s: dmrg.to_statevector(s)) if bits is None else (
+        lambda s: np.array([dmrg.amplitude(s, b) for b in bits]))
+    want = pick(ref)
+    worst = 0.0
+    for t in range(trials):
+        rng = np.random.default_rng(t)
+        st = dmrg.product_state(c.n)
+        for layer in c.layers:
+            st.tensors = [x * (1 + noise * rng.standard_normal(x.shape)) for x in st.tensors]
+            dmrg.apply_layer(st, layer, chi, sweeps, update="single-site")
+        worst = max(worst, rel_l2(pick(st), want))
+    return worst
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32, BF16X3])
+def test_exact_regime_statevector(prec):
+    """12 qubits, chi = 64 = 2^(n/2): the single-site layers reproduce the statevector, F~ = 1."""
+    c = circuits.plain_fp64_workload(0)
+    st, fs = run_gpu(c, 64, 2, prec)
+    psi = sv.run(c)
+    err = rel_l2(st.statevector(), psi)
+    print("prec=%d exact-regime statevector rel-L2 %.2e" % (prec, err))
+    assert err < AMP_TOL[prec]
+    assert abs(st.fidelity()["F_tilde"] - 1.0) < F_TOL[prec] * 10
+    ora = run_oracle(c, 64, 2)
+    assert st.bond_dims() == ora.bond_dims()
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32, BF16X3])
+@pytest.mark.parametrize("chi", [4, 8])
+def test_truncated_matches_oracle(chi, prec):
+    c = circuits.plain_fp64_workload(1)
+    st, fs = run_gpu(c, chi, 2, prec)
+    ora = run_oracle(c, chi, 2)
+    of = np.array(ora.layer_f)
+    rel = np.max(np.abs(fs - of) / of)
+    print("chi=%d prec=%d max rel f err %.2e" % (chi, prec, rel))
+    assert rel < F_TOL[prec]
+    f_log, _, k_log = st.step_log()
+    ofl = np.array([r.f for r in ora.step_log])
+    assert np.max(np.abs(f_log - ofl) / ofl) < F_TOL[prec]
+    if prec == FP64:
+        assert list(k_log) == [r.chi_kept for r in ora.step_log]
+        assert st.bond_dims() == ora.bond_dims()
+    tol = AMP_TOL[prec]
+    if prec != FP64:
+        tol = max(tol, 8.0 * sensitivity(c, chi, 2, EPS[prec] / 2))
+    err = rel_l2(st.statevector(), dmrg.to_statevector(ora))
+    print("chi=%d prec=%d amplitude rel-L2 %.2e (bound %.2e)" % (chi, prec, err, tol))
+    assert err < tol
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_f_delta_is_the_overlap_with_the_exact_layer(prec):
+    """f_delta = |<phi|U|psi>|^2 with both statevectors taken from the GPU state (P4)."""
+    c = circuits.plain_fp64_workload(3)
+    st = mps.MPS(c.n, None, max_chi=6, precision=prec)
+    for layer in c.layers:
+        before = st.statevector()
+        f = st.apply_layer_dmrg(layer, 6, 3, update="single-site")
+        target = sv.apply_layer(before, c.n, layer)
+        ov = abs(np.vdot(st.statevector(), target)) ** 2
+        assert abs(ov - f) < (1e-10 if prec == FP64 else 1e-5), (ov, f)
+        f_log, _, _ = st.step_log()
+        assert 0.0 < f <= 1.0 + 1e-6
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32, BF16X3])
+def test_grid_20_qubits(prec):
+    """20 qubits on a 4x5 grid, Haar gates, depth 10, chi 16."""
+    c = circuits.random_circuit(circuits.grid_from_shape(5, 4), 10, seed=3)
+    st, fs = run_gpu(c, 16, 2, prec)
+    ora = run_oracle(c, 16, 2)
+    of = np.array(ora.layer_f)
+    rel = np.max(np.abs(fs - of) / of)
+    print("20 qubits prec=%d max rel f err %.2e" % (prec, rel))
+    assert rel < F_TOL[prec]
+    bits = np.random.default_rng(0).integers(0, 2, size=(64, c.n)).astype(np.uint8)
+    amp = st.amplitudes(bits)
+    want = np.array([dmrg.amplitude(ora, b) for b in bits])
+    err = rel_l2(amp, want)
+    tol = 1e-7 if prec == FP64 else max(AMP_TOL[prec], 8.0 * sensitivity(c, 16, 2, EPS[prec] / 2, bits=bits))
+    print("20 qubits prec=%d amplitude rel-L2 %.2e (bound %.2e)" % (prec, err, tol))
+    assert err < tol
+    if prec == FP64:
+        assert st.bond_dims() == ora.bond_dims()
+
+
+def test_mixed_updates_and_errors():
+    """Two-site and single-site layers may alternate on one state; argument errors leave it unchanged."""
+    c = circuits.plain_fp64_workload(2)
+    st = mps.MPS(c.n, None, max_chi=8, precision=FP64)
+    ora = dmrg.product_state(c.n)
+    for d, layer in enumerate(c.layers):
+        upd = "single-site" if d % 2 else "two-site"
+        f = st.apply_layer_dmrg(layer, 8, 1, update=upd)
+        fo = dmrg.apply_layer(ora, layer, 8, 1, update=upd)
+        assert abs(f - fo) / fo < 1e-10
+    with pytest.raises(mps.MpsError) as e:
+        st.apply_layer_dmrg(c.layers[0], 9, 1, update="single-site")          # chi > max_chi
+    assert e.value.code == mps.MPS_ERR_ARG
+    assert st.fidelity()["n_layers"] == len(c.layers)
+    assert rel_l2(st.statevector(), dmrg.to_statevector(ora)) < 1e-9
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16X3])
+def test_full_size_properties_chi1024(prec):
+    """54 qubits, chi 1024: two two-site layers, then single-site layers of the benchmark circuit;
+    0 < f <= 1, f non-decreasing over the steps of a layer (up to the rounding of the local tensor),
+    bond dimensions <= chi."""
+    c = circuits.sycamore_like_54_workload(0)
+    chi = 1024
+    st = mps.MPS(c.n, None, max_chi=chi, precision=prec)
+    for d in range(6):
+        upd = "two-site" if d < 2 else "single-site"
+        n_before = len(st.step_log()[0])
+        f = st.apply_layer_dmrg(c.layers[d], chi, 2, update=upd)
+        assert 0.0 < f <= 1.0 + 1e-6
+        f_log = st.step_log()[0][n_before:]
+        if upd == "single-site":
+            assert np.all(np.diff(f_log) >= -5e-6 * np.abs(f_log[1:])), f_log
+        print("layer %d (%s) f=%.6f maxbond=%d" % (d, upd, f, max(st.bond_dims())))
+    assert max(st.bond_dims()) <= chi
