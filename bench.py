@@ -53,6 +53,8 @@ def parse():
     p.add_argument("--compare-fp64", type=int, default=1,
                    help="also time the same layers with FP64 contractions (1 = yes)")
     p.add_argument("--cpu-baseline", type=int, default=1)
+    p.add_argument("--single-site", type=int, default=1,
+                   help="also time the single-site update (split and FP64) on the same layers (1 = yes)")
     p.add_argument("--samples", type=int, default=65536,
                    help="bitstrings sampled from the final MPS of the timed run (0 = skip)")
     p.add_argument("--progress", action="store_true", help="print one line per layer to stderr")
@@ -74,10 +76,11 @@ def mark(torch):
     torch.cuda._sleep(1000)
 
 
-def run_layers(mps, circuit, precision, chi, sweeps, warmup, steps, torch, progress=False, samples=0):
+def run_layers(mps, circuit, precision, chi, sweeps, warmup, steps, torch, progress=False, samples=0,
+               update="two-site"):
     st = mps.MPS(circuit.n, None, max_chi=chi, precision=precision)
     for d in range(warmup):
-        f = st.apply_layer_dmrg(circuit.layers[d], chi, sweeps)
+        f = st.apply_layer_dmrg(circuit.layers[d], chi, sweeps, update=update)
         if progress:
             print("warmup layer %d f=%.6f" % (d, f), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -87,7 +90,7 @@ def run_layers(mps, circuit, precision, chi, sweeps, warmup, steps, torch, progr
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for d in range(warmup, warmup + steps):
-        fs.append(st.apply_layer_dmrg(circuit.layers[d], chi, sweeps))
+        fs.append(st.apply_layer_dmrg(circuit.layers[d], chi, sweeps, update=update))
         if progress:
             print("timed layer %d f=%.6f" % (d, fs[-1]), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -252,6 +255,19 @@ def main():
                             "f_delta": fs64}
         out["speedup_vs_fp64"] = value / (args.steps / dt64)
         out["max_rel_f_delta_diff_vs_fp64"] = max(abs(a - b) / b for a, b in zip(fs, fs64))
+    if args.single_site:
+        ss = {}
+        for name, pr in (("split", prec), ("fp64", mps.MPS_FP64)):
+            d_ss, f_ss, st_ss, _, _, _ = run_layers(mps, c, pr, args.chi, args.sweeps, args.warmup, args.steps, torch,
+                                                    args.progress, 0, update="single-site")
+            cs = st_ss["contract"]
+            ss[name] = {"value": args.steps / d_ss, "f_delta": f_ss,
+                        "contraction_tflops": cs["flops"] / (cs["ms"] * 1e-3) / 1e12 if cs["ms"] > 0 else 0.0,
+                        "time_split_ms": {k: round(v["ms"], 1) for k, v in st_ss.items()}}
+        out["single_site"] = {"update": "single-site sweeps after the same zip-up (paper's update rule)",
+                              "value": ss["split"]["value"], "unit": "gate-layers/s",
+                              "speedup_vs_fp64_single_site": ss["split"]["value"] / ss["fp64"]["value"],
+                              "split": ss["split"], "fp64": ss["fp64"]}
     if args.cpu_baseline:
         layer_flops = con["flops"] / args.steps
         out["cpu_baseline"] = cpu_baseline(args.chi, args.sweeps, layer_flops, (c.n - 1) * (1 + args.sweeps))
