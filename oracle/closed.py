@@ -1,0 +1,51 @@
+"""Closed simulation mode of the FP64 oracle -- TEST INFRASTRUCTURE ONLY.
+
+The paper's closed mode (Sec. IV.C) computes the amplitude <x|U|0> of a
+given bitstring x from two MPS: the forward MPS U_{d1} ... U_1 |0> and the
+backward MPS U_{d1+1}^dagger ... U_D^dagger |x>, both built with the
+compression step, and contracts them: <x|U|0> = <backward|forward>.  Here the
+middle part of depth D2 of the paper is empty (every layer belongs to one of
+the two MPS).
+
+A layer applies its one-qubit gates, then its two-qubit gates.  The daggered
+layers applied to |x> therefore regroup as
+  [2q_D^+], [1q_D^+, 2q_{D-1}^+], ..., [1q_{d1+2}^+, 2q_{d1+1}^+], [1q_{d1+1}^+]
+so that each regrouped layer again has its one-qubit gates first.
+"""
+from __future__ import annotations
+
+from typing import List, Sequence
+
+import numpy as np
+
+from . import dmrg
+
+
+def dagger_layers(layers: Sequence) -> List[list]:
+    """U_1^+ ... U_m^+ applied right to left, as layers (one-qubit gates first)."""
+    out = []
+    m = len(layers)
+    for idx in range(m, -1, -1):
+        regrouped = []
+        if idx < m:                       # one-qubit gates of layer idx (0-based), daggered
+            regrouped += [(q0, q1, np.asarray(u).conj().T) for q0, q1, u in layers[idx] if q1 < 0]
+        if idx > 0:                       # two-qubit gates of layer idx - 1, daggered
+            regrouped += [(q0, q1, np.asarray(u).conj().T) for q0, q1, u in layers[idx - 1] if q1 >= 0]
+        out.append(regrouped)
+    return out
+
+
+def closed_amplitude(circuit, bits, chi: int, n_sweeps: int, d1: int, update: str = "two-site"):
+    """<x|U|0> from the forward MPS of layers [0, d1) and the backward MPS of layers [d1, D).
+
+    Returns (amplitude, forward state, backward state); the fidelity estimate of
+    the amplitude is F~_forward * F~_backward."""
+    if not 0 <= d1 <= len(circuit.layers):
+        raise ValueError("0 <= d1 <= depth required")
+    fwd = dmrg.product_state(circuit.n)
+    for layer in circuit.layers[:d1]:
+        dmrg.apply_layer(fwd, layer, chi, n_sweeps, update=update)
+    bwd = dmrg.product_state(circuit.n, bits)
+    for layer in dagger_layers(circuit.layers[d1:]):
+        dmrg.apply_layer(bwd, layer, chi, n_sweeps, update=update)
+    return dmrg.overlap(bwd, fwd), fwd, bwd

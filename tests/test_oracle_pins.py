@@ -381,3 +381,56 @@ def test_single_site_update_is_the_local_optimum():
         assert val <= f_best + 1e-12
     st.tensors[ctr] = base
     assert abs(abs(np.vdot(dmrg.to_statevector(st), target)) ** 2 - f_best) < 1e-12
+
+
+# ------------------------------------------------------ closed mode ---------
+def test_dagger_layers_invert_the_circuit():
+    """The regrouped daggered layers applied after the circuit give back the input state."""
+    from oracle import closed
+    c = circuits.plain_fp64_workload(4)
+    psi = sv.run(c)
+    for layer in closed.dagger_layers(c.layers):
+        psi = sv.apply_layer(psi, c.n, layer)
+    want = sv.zero_state(c.n)
+    assert np.linalg.norm(psi - want) < 1e-12
+
+
+@pytest.mark.parametrize("d1", [0, 3, 8])
+@pytest.mark.parametrize("update", ["two-site", "single-site"])
+def test_closed_amplitude_exact_regime(d1, update):
+    """Closed mode at chi = 2^(n/2): <x|U|0> equals the statevector amplitude for every split d1."""
+    from oracle import closed
+    c = circuits.plain_fp64_workload(0)
+    psi = sv.run(c)
+    rng = np.random.default_rng(d1)
+    for _ in range(3):
+        bits = rng.integers(0, 2, size=c.n)
+        amp, fwd, bwd = closed.closed_amplitude(c, bits, chi=64, n_sweeps=2, d1=d1, update=update)
+        idx = int("".join(str(int(b)) for b in bits), 2)       # site 0 = most significant bit
+        assert abs(amp - psi[idx]) < 1e-12 * max(1.0, abs(psi[idx])) + 1e-13
+        assert abs(fwd.log_f) < 1e-12 and abs(bwd.log_f) < 1e-12
+
+
+def test_closed_amplitude_truncated_bounds():
+    """With truncation, the closed-mode amplitude is |<bwd|fwd>| <= 1 and its error against the
+    exact amplitude is bounded by the infidelity of the two MPS (Cauchy-Schwarz with
+    |phi_fwd - P psi_fwd|^2 <= 2 (1 - sqrt F))."""
+    from oracle import closed
+    c = circuits.plain_fp64_workload(1)
+    psi = sv.run(c)
+    rng = np.random.default_rng(9)
+    for d1 in (3, 5):
+        bits = rng.integers(0, 2, size=c.n)
+        amp, fwd, bwd = closed.closed_amplitude(c, bits, chi=4, n_sweeps=2, d1=d1)
+        idx = int("".join(str(int(b)) for b in bits), 2)
+        exact_fwd = sv.run(c, depth=d1)
+        # |<bwd|fwd> - <bwd_exact|fwd_exact>| <= |fwd - fwd_exact| + |bwd - bwd_exact|
+        xb = sv.zero_state(c.n, bits)
+        for layer in closed.dagger_layers(c.layers[d1:]):
+            xb = sv.apply_layer(xb, c.n, layer)
+        pf, pb = dmrg.to_statevector(fwd), dmrg.to_statevector(bwd)
+        # align global phases (the MPS carry the phase of the exact states up to the fit)
+        ef = np.linalg.norm(pf - exact_fwd * np.exp(1j * np.angle(np.vdot(exact_fwd, pf))))
+        eb = np.linalg.norm(pb - xb * np.exp(1j * np.angle(np.vdot(xb, pb))))
+        assert abs(abs(amp) - abs(psi[idx])) <= ef + eb + 1e-12
+        assert abs(np.vdot(xb, exact_fwd) - psi[idx]) < 1e-12      # exact closed identity
