@@ -185,6 +185,13 @@ mps_status mps_step_log(const mps_state* state, double* f, double* sum_s2,
 /* <phi| Z_i Z_j |phi> (or <Z_i> when i == j) in FP64. */
 mps_status mps_expect_zz(const mps_state* state, int i, int j, double* value);
 
+/* <bra|ket> in FP64 (MPS-MPS overlap; the closed simulation mode of
+ * Sec. IV.C contracts a forward and a backward MPS this way).  Both states
+ * must have the same number of sites; neither is modified.  The bra's stream
+ * is synchronised first; the work runs on the ket's stream and is complete
+ * on return.  re, im: HOST outputs. */
+mps_status mps_overlap(const mps_state* bra, const mps_state* ket, double* re, double* im);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /* Kernel classes timed when profiling is on (hipEvents around every launch on

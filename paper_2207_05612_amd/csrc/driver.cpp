@@ -1181,14 +1181,15 @@ struct Engine {
     }
 };
 
-// Forward-layout FP64 copy of site k into dst ([D_k][2][D_k+1]).
-void forward_tensor(const mps_state* st, int k, Planar<double>& dst) {
+// Forward-layout FP64 copy of site k into dst ([D_k][2][D_k+1]), on `on`
+// (default: the state's stream).
+void forward_tensor(const mps_state* st, int k, Planar<double>& dst, hipStream_t on = nullptr) {
+    const hipStream_t s = on ? on : st->stream;
     const int64_t sz = (int64_t)st->bond[k] * 2 * st->bond[k + 1];
-    dst.ensure(sz, st->stream);
+    dst.ensure(sz, s);
     const int Dl = st->orient == 0 ? st->bond[k] : st->bond[k + 1];
     const int Dr = st->orient == 0 ? st->bond[k + 1] : st->bond[k];
-    HIPCHK(site_to_view<double>(st->ten[k].re(), st->ten[k].im(), Dl, Dr, st->orient, dst.re(), dst.im(),
-                                st->stream));
+    HIPCHK(site_to_view<double>(st->ten[k].re(), st->ten[k].im(), Dl, Dr, st->orient, dst.re(), dst.im(), s));
 }
 
 mps_status run_guarded(const std::function<void()>& fn) {
@@ -1624,6 +1625,47 @@ mps_status mps_expect_zz(const mps_state* st_c, int i, int j, double* value) {
         *value = v;
         e.release(s); x.release(s); a.release(s); az.release(s);
         flush_timings(st);
+    });
+}
+
+mps_status mps_overlap(const mps_state* bra_c, const mps_state* ket_c, double* re, double* im) {
+    return run_guarded([&] {
+        check_state(bra_c);
+        check_state(ket_c);
+        if (!re || !im) fail(MPS_ERR_ARG, "NULL output");
+        if (bra_c->n != ket_c->n) fail(MPS_ERR_ARG, "the states have different numbers of sites");
+        mps_state* ket = const_cast<mps_state*>(ket_c);
+        const mps_state* bra = bra_c;
+        // transfer matrices E_{k+1} = sum_s B_k[:, s, :]^H E_k A_k[:, s, :] on the ket's stream
+        HIPCHK(hipStreamSynchronize(bra->stream));
+        const hipStream_t s = ket->stream;
+        int maxB = 1, maxK = 1;
+        for (int c = 0; c <= ket->n; ++c) {
+            maxB = std::max(maxB, bra->bond[c]);
+            maxK = std::max(maxK, ket->bond[c]);
+        }
+        Planar<double> e, x, a, b;
+        e.ensure((int64_t)maxB * maxK, s);
+        x.ensure((int64_t)maxB * 2 * maxK, s);
+        HIPCHK(fill_planar<double>(e.re(), e.im(), 1, 1.0, s));
+        for (int k = 0; k < ket->n; ++k) {
+            forward_tensor(ket, k, a, s);
+            forward_tensor(bra, k, b, s);
+            const int64_t Bk = bra->bond[k], Bn = bra->bond[k + 1], Kk = ket->bond[k], Kn = ket->bond[k + 1];
+            gemm<double>(ket, MPS_KCLASS_OTHER, OP_N, OP_N, Bk, 2 * Kn, Kk, e.re(), e.im(), Kk, a.re(), a.im(), 2 * Kn,
+                         x.re(), x.im(), 2 * Kn);
+            gemm<double>(ket, MPS_KCLASS_OTHER, OP_C, OP_N, Bn, Kn, 2 * Bk, b.re(), b.im(), Bn, x.re(), x.im(), Kn,
+                         e.re(), e.im(), Kn);
+        }
+        double v[2] = {0, 0};
+        HIPCHK(hipMemcpyAsync(&v[0], e.re(), sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&v[1], e.im(), sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        *re = v[0];
+        *im = v[1];
+        e.release(s); x.release(s); a.release(s); b.release(s);
+        HIPCHK(hipStreamSynchronize(s));
+        flush_timings(ket);
     });
 }
 

@@ -30,7 +30,7 @@ EXPORTS = ("mps_create", "mps_destroy", "apply_layer_dmrg", "apply_layer_dmrg_si
            "mps_last_error",
            "mps_amplitude", "mps_to_statevector", "mps_bond_dims", "mps_get_tensor", "mps_step_log",
            "mps_expect_zz", "mps_set_profiling", "mps_kernel_stats", "mps_kernel_selftest_cgemm",
-           "mps_kernel_selftest_eigh")
+           "mps_kernel_selftest_eigh", "mps_overlap")
 
 _lib = None
 
@@ -77,6 +77,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mps_kernel_stats": (i32, [P, i32, ctypes.POINTER(i64), dp, dp, dp]),
         "mps_kernel_selftest_cgemm": (i32, [i32, i32, i32, i32, i32, i32, dp, dp, dp]),
         "mps_kernel_selftest_eigh": (i32, [i32, dp, i32, dp, dp, ip]),
+        "mps_overlap": (i32, [P, P, dp, dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -226,6 +227,13 @@ def selftest_cgemm(precision: int, opa: int, opb: int, a: np.ndarray, b: np.ndar
     _check(lib.mps_kernel_selftest_cgemm(precision, opa, opb, M, N, K, _dptr(a.view(np.float64)),
                                          _dptr(b.view(np.float64)), _dptr(c.view(np.float64))))
     return c
+
+
+def overlap(bra: "MPS", ket: "MPS") -> complex:
+    """<bra|ket> (see mps_overlap)."""
+    re, im = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.mps_overlap(bra._h, ket._h, ctypes.byref(re), ctypes.byref(im)))
+    return complex(re.value, im.value)
 
 
 EIGH_ROCSOLVER, EIGH_PERSISTENT = 0, 1

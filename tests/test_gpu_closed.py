@@ -1,0 +1,95 @@
+"""Closed simulation mode and MPS-MPS overlap on the GPU, through the C ABI.
+
+* mps_overlap against the oracle's overlap of the same states (FP64 MPS
+  tensors: 1e-12 relative), <phi|phi> = 1, and <x|phi> equal to the
+  amplitude of x.
+* closed_amplitude (forward MPS of the first d1 layers, backward MPS of the
+  daggered rest from |x>) against the statevector amplitude in the exact
+  regime (FP64: 1e-10 relative to the largest amplitude magnitude), and
+  against the oracle's closed mode in the truncated regime (FP64: 1e-9).
+"""
+import numpy as np
+import pytest
+
+from paper_2207_05612_amd import circuits, closed, mps
+from oracle import closed as oclosed
+from oracle import dmrg
+from oracle import statevector as sv
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = mps.MPS_FP64, mps.MPS_FP32
+
+
+def index_of(bits):
+    return int("".join(str(int(b)) for b in bits), 2)
+
+
+def test_backward_layers_match_oracle_regrouping():
+    c = circuits.plain_fp64_workload(4)
+    a = closed.backward_layers(c.layers[3:])
+    b = oclosed.dagger_layers(c.layers[3:])
+    assert len(a) == len(b)
+    for la, lb in zip(a, b):
+        assert [(g[0], g[1]) for g in la] == [(g[0], g[1]) for g in lb]
+        for ga, gb in zip(la, lb):
+            assert np.array_equal(ga[2], gb[2])
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_overlap(prec):
+    c = circuits.plain_fp64_workload(2)
+    g1 = mps.MPS(c.n, None, max_chi=8, precision=prec)
+    g2 = mps.MPS(c.n, None, max_chi=16, precision=prec)
+    o1, o2 = dmrg.product_state(c.n), dmrg.product_state(c.n)
+    for d, layer in enumerate(c.layers[:5]):
+        g1.apply_layer_dmrg(layer, 8, 2)
+        dmrg.apply_layer(o1, layer, 8, 2)
+        if d < 4:
+            g2.apply_layer_dmrg(layer, 16, 2)
+            dmrg.apply_layer(o2, layer, 16, 2)
+    got = mps.overlap(g2, g1)
+    # the overlap of the two GPU states against the statevectors of the same GPU states
+    want = np.vdot(g2.statevector(), g1.statevector())
+    assert abs(got - want) < 1e-12 * max(1.0, abs(want))
+    assert abs(mps.overlap(g1, g1) - 1.0) < 1e-12
+    if prec == FP64:
+        assert abs(got - dmrg.overlap(o2, o1)) < 1e-10
+    bits = np.random.default_rng(1).integers(0, 2, size=c.n).astype(np.uint8)
+    x = mps.MPS(c.n, bits, max_chi=1, precision=prec)
+    assert abs(mps.overlap(x, g1) - g1.amplitudes(bits[None, :])[0]) < 1e-12
+    with pytest.raises(mps.MpsError):
+        mps.overlap(mps.MPS(c.n + 1, None, max_chi=1, precision=prec), g1)
+
+
+@pytest.mark.parametrize("update", ["two-site", "single-site"])
+@pytest.mark.parametrize("d1", [0, 4, 8])
+def test_closed_amplitude_exact_regime(d1, update):
+    c = circuits.plain_fp64_workload(0)
+    psi = sv.run(c)
+    scale = np.abs(psi).max()
+    rng = np.random.default_rng(d1 + 7)
+    for _ in range(2):
+        bits = rng.integers(0, 2, size=c.n)
+        amp, fwd, bwd = closed.closed_amplitude(c, bits, chi=64, n_sweeps=2, d1=d1, update=update)
+        assert abs(amp - psi[index_of(bits)]) < 1e-10 * scale, (amp, psi[index_of(bits)])
+        assert abs(fwd.fidelity()["F_tilde"] - 1.0) < 1e-10
+        assert abs(bwd.fidelity()["F_tilde"] - 1.0) < 1e-10
+        fwd.close()
+        bwd.close()
+
+
+@pytest.mark.parametrize("update", ["two-site", "single-site"])
+def test_closed_amplitude_truncated_matches_oracle(update):
+    c = circuits.random_circuit(circuits.grid_from_shape(4, 4), 8, seed=5)
+    rng = np.random.default_rng(11)
+    for d1 in (3, 5):
+        bits = rng.integers(0, 2, size=c.n)
+        amp, fwd, bwd = closed.closed_amplitude(c, bits, chi=8, n_sweeps=2, d1=d1, update=update)
+        want, ofwd, obwd = oclosed.closed_amplitude(c, bits, chi=8, n_sweeps=2, d1=d1, update=update)
+        print("d1=%d %s amp %.3e%+.3ej oracle %.3e%+.3ej" % (d1, update, amp.real, amp.imag, want.real, want.imag))
+        assert abs(amp - want) < 1e-9 * max(abs(want), 1e-3)
+        assert abs(fwd.fidelity()["log_F_tilde"] - ofwd.log_f) < 1e-9
+        assert abs(bwd.fidelity()["log_F_tilde"] - obwd.log_f) < 1e-9
+        fwd.close()
+        bwd.close()
