@@ -11,6 +11,10 @@ A layer applies its one-qubit gates, then its two-qubit gates.  The daggered
 layers applied to |x> therefore regroup as
   [2q_D^+], [1q_D^+, 2q_{D-1}^+], ..., [1q_{d1+2}^+, 2q_{d1+1}^+], [1q_{d1+1}^+]
 so that each regrouped layer again has its one-qubit gates first.
+
+Metropolis sampling over amplitudes (App. on Metropolis sampling): from x_t a
+uniformly random x' is proposed and accepted with probability
+min(|Psi_x'/Psi_x_t|^2, 1); a refused move repeats x_t.
 """
 from __future__ import annotations
 
@@ -49,3 +53,22 @@ def closed_amplitude(circuit, bits, chi: int, n_sweeps: int, d1: int, update: st
     for layer in dagger_layers(circuit.layers[d1:]):
         dmrg.apply_layer(bwd, layer, chi, n_sweeps, update=update)
     return dmrg.overlap(bwd, fwd), fwd, bwd
+
+
+def metropolis(amplitude, x0, proposals, uniforms):
+    """Metropolis chain over bitstrings with the given proposals and uniform draws.
+
+    amplitude(bits) -> complex.  Returns (chain of visited bitstrings, including x0,
+    number of accepted moves)."""
+    x = np.asarray(x0, dtype=np.uint8).copy()
+    px = abs(amplitude(x)) ** 2
+    chain = [x.copy()]
+    accepted = 0
+    for prop, u in zip(proposals, uniforms):
+        pp = abs(amplitude(prop)) ** 2
+        ratio = 1.0 if px == 0.0 else min(pp / px, 1.0)
+        if u < ratio:
+            x, px = np.asarray(prop, dtype=np.uint8).copy(), pp
+            accepted += 1
+        chain.append(x.copy())
+    return chain, accepted

@@ -371,3 +371,13 @@ def qaoa_parameter_sets(count: int, p: int, seed: int = 0):
 def maxcut_expectation_from_zz(edges, final_position, zz) -> float:
     """<C> = sum_E (1 - <Z_u Z_v>)/2, zz(i, j) giving <Z_i Z_j> on chain sites."""
     return float(sum(0.5 * (1.0 - zz(final_position[u], final_position[v])) for u, v in edges))
+
+
+def metropolis_draws(n: int, n_steps: int, seed: int):
+    """Seeded random inputs of a Metropolis chain over bitstrings: per step a uniformly random
+    proposed bitstring (n bits, site order) and one uniform number in [0, 1) for the acceptance.
+    Both the oracle and the library's sampler take these as inputs."""
+    rng = np.random.default_rng(seed)
+    proposals = rng.integers(0, 2, size=(n_steps, n)).astype(np.uint8)
+    uniforms = rng.random(n_steps)
+    return proposals, uniforms

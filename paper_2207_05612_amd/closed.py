@@ -50,3 +50,49 @@ def closed_amplitude(circuit, bits, chi: int, n_sweeps: int, d1: int, precision:
     for layer in backward_layers(circuit.layers[d1:]):
         bwd.apply_layer_dmrg(layer, chi, n_sweeps, update=update)
     return mps.overlap(bwd, fwd), fwd, bwd
+
+
+class ClosedAmplitudes:
+    """Amplitudes <x|U|0> of one circuit for many bitstrings: the forward MPS of the
+    first d1 layers is built once, a backward MPS per bitstring."""
+
+    def __init__(self, circuit, chi: int, n_sweeps: int, d1: int, precision: int = mps.MPS_FP64,
+                 update: str = "two-site"):
+        if not 0 <= d1 <= len(circuit.layers):
+            raise ValueError("0 <= d1 <= depth required")
+        self.circuit, self.chi, self.n_sweeps, self.precision, self.update = circuit, chi, n_sweeps, precision, update
+        self.back = backward_layers(circuit.layers[d1:])
+        self.fwd = mps.MPS(circuit.n, None, max_chi=chi, precision=precision)
+        for layer in circuit.layers[:d1]:
+            self.fwd.apply_layer_dmrg(layer, chi, n_sweeps, update=update)
+        self.log_f_backward = []        # log F~ of each backward MPS
+
+    def __call__(self, bits) -> complex:
+        bwd = mps.MPS(self.circuit.n, np.asarray(bits, dtype=np.uint8), max_chi=self.chi, precision=self.precision)
+        try:
+            for layer in self.back:
+                bwd.apply_layer_dmrg(layer, self.chi, self.n_sweeps, update=self.update)
+            self.log_f_backward.append(bwd.fidelity()["log_F_tilde"])
+            return mps.overlap(bwd, self.fwd)
+        finally:
+            bwd.close()
+
+    def close(self) -> None:
+        self.fwd.close()
+
+
+def metropolis(amplitude, x0, proposals, uniforms):
+    """Metropolis chain over bitstrings (App. on Metropolis sampling): the proposal of each
+    step is accepted when its uniform draw is below min(|Psi_x'|^2 / |Psi_x|^2, 1).
+    Returns (visited bitstrings including x0, accepted moves, |Psi|^2 of each visited one)."""
+    cur = np.asarray(x0, dtype=np.uint8).copy()
+    w_cur = abs(amplitude(cur)) ** 2
+    visited, weights, n_acc = [cur.copy()], [w_cur], 0
+    for prop, u in zip(proposals, uniforms):
+        w_new = abs(amplitude(prop)) ** 2
+        if w_cur == 0.0 or u < min(w_new / w_cur, 1.0):
+            cur, w_cur = np.asarray(prop, dtype=np.uint8).copy(), w_new
+            n_acc += 1
+        visited.append(cur.copy())
+        weights.append(w_cur)
+    return visited, n_acc, weights

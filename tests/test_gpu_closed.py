@@ -93,3 +93,32 @@ def test_closed_amplitude_truncated_matches_oracle(update):
         assert abs(bwd.fidelity()["log_F_tilde"] - obwd.log_f) < 1e-9
         fwd.close()
         bwd.close()
+
+
+def test_metropolis_chain_matches_oracle():
+    """The library's closed-mode Metropolis chain (amplitudes from forward/backward MPS at
+    chi = 2^(n/2)) and the oracle's chain over exact statevector amplitudes, with the same
+    seeded proposals and uniforms, accept the same moves (no uniform lies within 1e-9 of its
+    acceptance ratio for these draws, which the test checks)."""
+    c = circuits.plain_fp64_workload(0)
+    psi = sv.run(c)
+    props, us = circuits.metropolis_draws(c.n, 120, seed=21)
+    amps = closed.ClosedAmplitudes(c, chi=64, n_sweeps=1, d1=4)
+    try:
+        chain, acc, weights = closed.metropolis(amps, props[0], props[1:], us[1:])
+    finally:
+        amps.close()
+    exact = lambda b: psi[index_of(b)]
+    ochain, oacc = oclosed.metropolis(exact, props[0], props[1:], us[1:])
+    p = np.abs(psi) ** 2
+    cur = index_of(props[0])
+    for prop, u in zip(props[1:], us[1:]):
+        ratio = min(p[index_of(prop)] / p[cur], 1.0)
+        assert abs(u - ratio) > 1e-9
+        if u < ratio:
+            cur = index_of(prop)
+    assert acc == oacc
+    assert all(np.array_equal(a, b) for a, b in zip(chain, ochain))
+    for x, w in zip(chain, weights):
+        assert abs(w - p[index_of(x)]) < 1e-10 * p.max()
+    print("accepted %d of %d proposals" % (acc, len(props) - 1))

@@ -434,3 +434,42 @@ def test_closed_amplitude_truncated_bounds():
         eb = np.linalg.norm(pb - xb * np.exp(1j * np.angle(np.vdot(xb, pb))))
         assert abs(abs(amp) - abs(psi[idx])) <= ef + eb + 1e-12
         assert abs(np.vdot(xb, exact_fwd) - psi[idx]) < 1e-12      # exact closed identity
+
+
+def test_metropolis_acceptance_integral_is_ln2():
+    """The paper's average acceptance for independent exponential weights,
+    int_0^inf int_0^inf min(x/y, 1) e^-x e^-y dx dy, equals ln 2 = 0.693 (its "~70%")."""
+    from scipy import integrate
+
+    def inner(y):          # integral over x, split at the kink x = y of min(x/y, 1)
+        a = integrate.quad(lambda x: x / y * math.exp(-x), 0.0, y, epsabs=1e-13)[0]
+        return a + integrate.quad(lambda x: math.exp(-x), y, math.inf, epsabs=1e-13)[0]
+
+    val = integrate.quad(lambda y: math.exp(-y) * inner(y), 0.0, math.inf, epsabs=1e-12, limit=200)[0]
+    assert abs(val - math.log(2)) < 1e-8
+
+
+def test_metropolis_chain_on_porter_thomas_state():
+    """Oracle Metropolis chain over the exact amplitudes of a chaotic 12-qubit state: the visited
+    bitstrings follow |Psi|^2 (collision probability sum p^2 = 2/2^n for Porter-Thomas), and at
+    stationarity the mean acceptance is 1/2 (the current weight is size-biased, Gamma(2)); for a
+    uniformly drawn current bitstring it is the paper's ln 2."""
+    from oracle import closed
+    c = circuits.random_circuit(circuits.Grid(12, 3), 14, seed=2)
+    psi = sv.run(c)
+    p = np.abs(psi) ** 2
+    n = c.n
+    amp = lambda bits: psi[int("".join(str(int(b)) for b in bits), 2)]
+    props, us = circuits.metropolis_draws(n, 40000, seed=3)
+    chain, acc = closed.metropolis(amp, props[0], props[1:], us[1:])
+    rate = acc / (len(chain) - 1)
+    assert abs(rate - 0.5) < 0.02, rate
+    idx = np.array([int("".join(str(int(b)) for b in x), 2) for x in chain[2000:]])
+    # E_chain[p(x)] = sum p^2: Porter-Thomas gives 2/2^n
+    mean_p = p[idx].mean() * 2 ** n
+    assert abs(mean_p - 2.0 * (p ** 2).sum() * 2 ** n / 2.0) < 0.1
+    assert abs((p ** 2).sum() * 2 ** n - 2.0) < 0.15
+    # uniformly drawn current states: mean of min(p'/p, 1) is ln 2
+    rng = np.random.default_rng(4)
+    a, b = rng.integers(0, 2 ** n, 200000), rng.integers(0, 2 ** n, 200000)
+    assert abs(np.minimum(p[b] / p[a], 1.0).mean() - math.log(2)) < 0.02
