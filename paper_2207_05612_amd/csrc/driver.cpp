@@ -524,14 +524,38 @@ void gemm_split(mps_state* st, int cls, int64_t M, int64_t N, int64_t K, const f
     }
 }
 
+// Split count for a GEMM with `active` output tiles over k range K: fill whole
+// rounds of `slots` resident workgroups (256 CUs x workgroups per CU) with
+// chunks of at least min_chunk terms; among equally full schedules the
+// smallest count wins.
+int fill_split(int64_t active, int64_t K, int64_t slots, int64_t min_chunk, int max_split) {
+    int best = 1;
+    double best_eff = 0;
+    for (int ks = 1; ks <= max_split; ++ks) {
+        if (ks > 1 && K / ks < min_chunk) break;
+        const int64_t work = active * ks;
+        const int64_t rounds = (work + slots - 1) / slots;
+        // rounds shorter than a few slots' worth waste the machine at the tail
+        const double eff = (double)work / (double)(rounds * slots);
+        if (eff > best_eff + 1e-3) {
+            best_eff = eff;
+            best = ks;
+        }
+    }
+    return best;
+}
+
 // Hermitian Gram product (lower tiles only) with FP64 accumulation; long k
-// ranges are split so that enough tiles run and partial sums add in FP64.
+// ranges are split so that whole rounds of workgroups run, and partial sums
+// add in FP64.
 template <typename TIn>
 void gram_product(mps_state* st, int opa, int opb, int dim, int64_t K, const TIn* re, const TIn* im, int64_t ld,
                   double* out_re, double* out_im) {
-    const int64_t tiles = (int64_t)((dim + 127) / 128) * ((dim + 63) / 64) / 2 + 1;   // lower half
-    int ks = 1;
-    if (K >= 4096) ks = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)32, K / 2048, (1024 + tiles - 1) / tiles}));
+    // non-empty lower tiles of the 128 x 64 FP64 tiling: row tile i holds columns up to 2i + 1
+    const int64_t gm = (dim + 127) / 128, gn = (dim + 63) / 64;
+    int64_t active = 0;
+    for (int64_t i = 0; i < gm; ++i) active += std::min<int64_t>(gn, 2 * i + 2);
+    const int ks = K >= 4096 ? fill_split(active, K, 512, 1024, 32) : 1;
     const int chunks = splitk_chunks((int)K, ks, 8);
     if (chunks > 1) {
         st->splitws64.ensure((int64_t)dim * dim * chunks, st->stream);
