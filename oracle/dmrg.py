@@ -1,9 +1,9 @@
 """FP64 oracle of the DMRG compression step -- TEST INFRASTRUCTURE ONLY.
 
 Plain NumPy complex128 implementation of one compression step of the paper
-(Sec. IV.B, "The main building block of the algorithm: the compression
-step"), in its two-site variant (mentioned in the same section), with K = 1
-layer per step and one qubit per MPS tensor (Sec. IV.A with r_tau = 1).
+(Sec. IV.B, the compression step), in its two-site variant (mentioned in the
+same section), with K >= 1 layers per step and one qubit per MPS tensor
+(Sec. IV.A with r_tau = 1).
 
 Steps, in the paper's order:
   * the layer's gates become an MPO: one-qubit gates are absorbed into the
@@ -30,6 +30,11 @@ Readings where the paper is silent (each one is listed in the design notes):
     are dropped;
   * composite MPO bonds order the open gates by their left chain site, the
     leftmost gate being the most significant digit.
+
+K > 1 layers per step (Sec. IV.B, the contraction of Sec. IV.B.2 with K layers
+between the two MPS): the MPO of the step is the site-by-site product of the K
+layer MPOs (step_mpo); everything else is unchanged, with one f_delta for the
+K layers.
 
 Single-site variant (the paper's production rule, Sec. IV.B, eq:optimization
 with one free tensor): the same zip-up, then sweeps that optimise one tensor
@@ -153,6 +158,27 @@ def layer_mpo(n: int, layer) -> Tuple[List[np.ndarray], List[SplitGate]]:
                 w[bi, :, :, bo] += g1[k]
         mpo.append(w)
     return mpo, gates
+
+
+def step_mpo(n: int, layers) -> List[np.ndarray]:
+    """Dense MPO of K consecutive layers U_K ... U_1 (Sec. IV.B with K > 1 layers per step).
+
+    Site by site, the later layer acts on the output leg of the earlier one:
+    W_k[(b_1 .. b_K), s, t, (b_1' .. b_K')] = sum over the inner physical indices
+    of the product of the K layer tensors, the bond of layer 1 being the most
+    significant part of the composite index."""
+    layers = list(layers)
+    if not layers:
+        raise ValueError("a step needs at least one layer")
+    mpo = layer_mpo(n, layers[0])[0]
+    for layer in layers[1:]:
+        nxt = layer_mpo(n, layer)[0]
+        out = []
+        for w1, w2 in zip(mpo, nxt):
+            c = np.einsum("asub,cutd->acstbd", w2, w1)   # w2 after w1 on the physical leg
+            out.append(c.reshape(w1.shape[0] * w2.shape[0], 2, 2, w1.shape[3] * w2.shape[3]))
+        mpo = out
+    return mpo
 
 
 def mpo_bond_dims(mpo: Sequence[np.ndarray]) -> List[int]:
@@ -376,13 +402,20 @@ def apply_layer(state: OracleMPS, layer, chi: int, n_sweeps: int, update: str = 
 
     update = "two-site" (SVD split of each pair, bond dimensions up to chi) or
     "single-site" (bond dimensions of the zip-up, QR moves of the centre)."""
+    return apply_layers(state, [layer], chi, n_sweeps, update)
+
+
+def apply_layers(state: OracleMPS, layers, chi: int, n_sweeps: int, update: str = "two-site") -> float:
+    """One compression step over K consecutive layers: fit a bond-chi MPS to
+    U_K ... U_1 |psi> with the MPO of step_mpo; return f_delta (one f for the K layers)."""
     if chi < 1 or n_sweeps < 0:
         raise ValueError("chi >= 1 and n_sweeps >= 0 required")
     if update not in ("two-site", "single-site"):
         raise ValueError("update must be 'two-site' or 'single-site'")
+    layers = list(layers)
     single = update == "single-site"
     n = state.n
-    w, _ = layer_mpo(n, layer)
+    w = step_mpo(n, layers)
     a = state.tensors
     envs: Dict[int, np.ndarray] = {}
     log: List[StepRecord] = []
@@ -407,8 +440,8 @@ def apply_layer(state: OracleMPS, layer, chi: int, n_sweeps: int, update: str = 
     state.tensors = b
     state.center = center
     state.log_f += math.log(f)
-    state.n_layers += 1
-    state.n_2q += sum(1 for g in layer if g[1] >= 0)
+    state.n_layers += len(layers)
+    state.n_2q += sum(1 for layer in layers for g in layer if g[1] >= 0)
     state.step_log.extend(log)
     state.layer_f.append(f)
     return f

@@ -94,6 +94,30 @@ def test_mpo_equals_dense_layer():
     assert np.allclose(_mpo_dense(mpo), sv.layer_matrix(n, layer), atol=1e-12)
 
 
+def _random_layer(n, rng, pairs):
+    haar = lambda: circuits.haar_unitary_from_normals(rng.standard_normal(32))
+    layer = [(int(q), -1, circuits.ONE_QUBIT_SET[int(rng.integers(3))]) for q in rng.permutation(n)[: n // 2]]
+    return layer + [(a, b, haar()) for a, b in pairs]
+
+
+def test_step_mpo_equals_ordered_layer_product():
+    """K > 1 layers per step: the step MPO contracted to a 2^n x 2^n matrix equals
+    U_3 U_2 U_1 built gate by gate from the statevector module (order of the layers, gates
+    that reach past each other, q0 > q1, an empty layer in the middle)."""
+    n = 6
+    rng = np.random.default_rng(11)
+    l1 = _random_layer(n, rng, [(0, 3), (4, 1), (2, 5)])
+    l2 = []
+    l3 = _random_layer(n, rng, [(1, 2), (5, 0), (3, 4)])
+    l4 = _random_layer(n, rng, [(0, 1), (2, 4)])
+    mpo = dmrg.step_mpo(n, [l1, l2, l3, l4])
+    want = sv.layer_matrix(n, l4) @ sv.layer_matrix(n, l3) @ sv.layer_matrix(n, l1)
+    assert np.allclose(_mpo_dense(mpo), want, atol=1e-12)
+    # bond dimensions multiply over the layers
+    per = [dmrg.mpo_bond_dims(dmrg.layer_mpo(n, l)[0]) for l in (l1, l3, l4)]
+    assert dmrg.mpo_bond_dims(mpo) == [a * b * c for a, b, c in zip(*per)]
+
+
 def test_mpo_rejects_overlapping_gates():
     with pytest.raises(ValueError):
         dmrg.layer_mpo(4, [(0, 1, np.eye(4)), (1, 2, np.eye(4))])
@@ -359,6 +383,55 @@ def test_single_site_invariants_and_overlap(chi):
                 assert np.allclose(m @ m.conj().T, np.eye(m.shape[0]), atol=1e-12)
         assert st.bond_dims()[0] == st.bond_dims()[-1] == 1
         del dims_before
+
+
+@pytest.mark.parametrize("update", ["two-site", "single-site"])
+@pytest.mark.parametrize("K", [2, 3])
+def test_multi_layer_steps_exact_regime(K, update):
+    """P1 with K layers per step: chi >= 2^(n/2) reproduces the statevector, F~ = 1, and the
+    layer and gate counts cover every layer."""
+    c = circuits.plain_fp64_workload(0)
+    st = dmrg.product_state(c.n)
+    for d in range(0, len(c.layers), K):
+        f = dmrg.apply_layers(st, c.layers[d:d + K], chi=64, n_sweeps=2, update=update)
+        assert abs(f - 1.0) < 1e-12
+    psi = sv.run(c)
+    assert np.linalg.norm(dmrg.to_statevector(st) - psi) / np.linalg.norm(psi) < 1e-12
+    assert abs(math.exp(st.log_f) - 1.0) < 1e-12
+    assert st.n_layers == len(c.layers) and st.n_2q == c.n_2q
+    assert len(st.layer_f) == -(-len(c.layers) // K)
+
+
+@pytest.mark.parametrize("update", ["two-site", "single-site"])
+def test_multi_layer_step_invariants_truncated(update):
+    """P4 with K = 2: ||phi|| = 1, 0 < f <= 1, f non-decreasing over the sweeps, and f_delta
+    equal to |<phi|U_2 U_1|psi>|^2 from statevector simulation of both layers."""
+    c = circuits.plain_fp64_workload(2)
+    st = dmrg.product_state(c.n)
+    for d in range(0, len(c.layers) - 1, 2):
+        before = len(st.step_log)
+        prev_vec = dmrg.to_statevector(st)
+        f = dmrg.apply_layers(st, c.layers[d:d + 2], chi=6, n_sweeps=2, update=update)
+        phi = dmrg.to_statevector(st)
+        assert abs(np.linalg.norm(phi) - 1.0) < 1e-12
+        assert 0.0 < f <= 1.0 + 1e-12
+        fs = [r.f for r in st.step_log[before:]]
+        if update == "single-site":
+            assert all(b >= a - 1e-12 for a, b in zip(fs, fs[1:])), fs
+        target = sv.apply_layer(sv.apply_layer(prev_vec, c.n, c.layers[d]), c.n, c.layers[d + 1])
+        assert abs(abs(np.vdot(phi, target)) ** 2 - f) < 1e-11
+        assert max(st.bond_dims()) <= 6
+
+
+def test_empty_layers_leave_a_step_unchanged():
+    """A step of one layer padded with empty layers (the identity) is the one-layer step."""
+    c = circuits.plain_fp64_workload(1)
+    a, b = dmrg.product_state(c.n), dmrg.product_state(c.n)
+    for layer in c.layers[:6]:
+        fa = dmrg.apply_layer(a, layer, chi=5, n_sweeps=2)
+        fb = dmrg.apply_layers(b, [[], layer, []], chi=5, n_sweeps=2)
+        assert abs(fa - fb) < 1e-13
+    assert np.allclose(dmrg.to_statevector(a), dmrg.to_statevector(b), atol=1e-12)
 
 
 def test_single_site_update_is_the_local_optimum():
