@@ -120,6 +120,33 @@ mps_status apply_layer_dmrg(mps_state* state, const mps_gate* gates, int n_gates
 mps_status apply_layer_dmrg_single_site(mps_state* state, const mps_gate* gates, int n_gates,
                                         int chi, int n_sweeps, double* f_layer);
 
+/* Update rules of apply_layers_dmrg. */
+typedef enum {
+    MPS_UPDATE_TWO_SITE = 0,    /* the sweeps of apply_layer_dmrg            */
+    MPS_UPDATE_SINGLE_SITE = 1  /* the sweeps of apply_layer_dmrg_single_site */
+} mps_update;
+
+/* One compression step over K = n_layers consecutive layers (Sec. IV.B with
+ * K > 1; the contraction strategy of Sec. IV.B.2 with K layers between the two
+ * MPS): |phi> maximises |<phi|U_K ... U_1|psi>|^2 over bond-chi MPS.  The MPO
+ * of the step is the product of the K layer MPOs: its bond c carries the
+ * operator-Schmidt indices of every two-qubit gate of any of the K layers
+ * with min site < c <= max site, so its bond dimensions are the products of
+ * the K layers' (at most 2^24).  Zip-up, sweeps, truncation and f_step are
+ * those of the update rule; F~ is multiplied by the one f_step, and the layer
+ * count of `fidelity` grows by K.  K = 1 is apply_layer_dmrg (update 0) or
+ * apply_layer_dmrg_single_site (update 1).
+ *   gates     the records of layer 1, then layer 2, ... (sum of n_gates
+ *             records, host memory, copied); each layer obeys the rules of
+ *             mps_gate (one-qubit gates act first, disjoint two-qubit gates).
+ *   n_gates   K host ints, the record count of each layer (>= 0).
+ *   n_layers  K, 1 <= K <= 64.
+ *   update    an mps_update value.
+ *   chi, n_sweeps, f_step as chi, n_sweeps, f_layer of apply_layer_dmrg.
+ * On error the state is unchanged for MPS_ERR_ARG, and invalid otherwise. */
+mps_status apply_layers_dmrg(mps_state* state, const mps_gate* gates, const int* n_gates,
+                             int n_layers, int chi, int n_sweeps, int update, double* f_step);
+
 /* Apply one layer to each of `batch` independent states (the compression
  * step above, per instance), concurrently: instances are driven by up to 8
  * host threads and run on their own streams, so give every state its own

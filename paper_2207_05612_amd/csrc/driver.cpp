@@ -193,13 +193,20 @@ void svd4(const cd m_in[4][4], double sigma[4], cd u[4][4], cd v[4][4]) {
 
 // ------------------------------------------------------------ layer MPO ----
 struct HostGate {
-    int i, j, r;
+    int i, j, r, layer;
     cd x[4][2][2], y[4][2][2];  // [a][s][t]
 };
 
+// The MPO of one compression step: K layers applied in order.  Bond c carries
+// the mixed-radix index of the operator-Schmidt indices of every two-qubit gate
+// (of any of the K layers) with i < c <= j; the digits are ordered by (i, layer),
+// the smallest being the most significant.  At each site the K layers act one
+// after the other on the physical leg, each on its own gate's digit; view[o][j]
+// lists those factors in the order they are applied (one-qubit factors are
+// folded into a neighbouring factor, so a site has max(1, #gates at it) of them).
 struct LayerMpo {
-    std::vector<int64_t> w;              // n + 1 bond dims
-    std::vector<MpoSiteOp> view[2];      // per view-site
+    std::vector<int64_t> w;                        // n + 1 bond dims
+    std::vector<std::vector<MpoSiteOp>> view[2];   // per view-site
     int n_2q = 0;
 };
 
@@ -213,6 +220,7 @@ void set_op(MpoSiteOp& op, int r_in, int r_out, int lo, int64_t H, const cd (*op
     op.r_out = r_out;
     op.lo = lo;
     op.H = (int)H;
+    op.out_ws = 0;
     for (int i = 0; i < 16; ++i) op.re[i] = op.im[i] = 0;
     const int r = std::max(r_in, r_out);
     for (int a = 0; a < r; ++a)
@@ -225,125 +233,227 @@ void set_op(MpoSiteOp& op, int r_in, int r_out, int lo, int64_t H, const cd (*op
             }
 }
 
-LayerMpo build_layer_mpo(int n, const mps_gate* gates, int n_gates) {
-    std::vector<cd> g1m(4 * (size_t)n);
-    auto G1 = [&](int k, int s, int t) -> cd& { return g1m[(size_t)k * 4 + s * 2 + t]; };
-    for (int k = 0; k < n; ++k) {
-        G1(k, 0, 0) = 1; G1(k, 0, 1) = 0; G1(k, 1, 0) = 0; G1(k, 1, 1) = 1;
-    }
-    std::vector<int> used(n, 0);
-    std::vector<HostGate> hg;
-    for (int gi = 0; gi < n_gates; ++gi) {
-        const mps_gate& g = gates[gi];
-        for (int e = 0; e < 32; ++e)
-            if (!std::isfinite(g.m[e])) fail(MPS_ERR_ARG, "gate matrix has a non-finite entry");
-        if (g.q1 < 0) {
-            if (g.q1 != -1 || g.q0 < 0 || g.q0 >= n) fail(MPS_ERR_ARG, "one-qubit gate site out of range");
-            cd u[2][2], cur[2][2], out[2][2];
-            for (int s = 0; s < 2; ++s)
-                for (int t = 0; t < 2; ++t) {
-                    u[s][t] = cd(g.m[2 * (s * 2 + t)], g.m[2 * (s * 2 + t) + 1]);
-                    cur[s][t] = G1(g.q0, s, t);
+// One factor before it is folded: the gate's digit goes from r_in to r_out values.
+struct ProtoOp {
+    int r_in, r_out;
+    int64_t lo, H;
+    cd m[4][2][2];
+};
+
+// Fold the one-qubit factors (r_in = r_out = 1 on an absent digit) into their
+// neighbours and turn the rest into MpoSiteOps; all but the last write the
+// intermediate layout.
+std::vector<MpoSiteOp> fold_site_ops(const std::vector<ProtoOp>& seq, const std::vector<bool>& is_1q, int64_t w_in) {
+    std::vector<ProtoOp> out;
+    cd pre[2][2] = {{1, 0}, {0, 1}};
+    for (size_t q = 0; q < seq.size(); ++q) {
+        if (is_1q[q]) {
+            cd tmp[2][2];
+            if (out.empty()) {                       // acts before the first gate factor
+                mul2(seq[q].m[0], pre, tmp);
+                std::memcpy(pre, tmp, sizeof(tmp));
+            } else {                                 // acts after the last one
+                ProtoOp& b = out.back();
+                for (int a = 0; a < std::max(b.r_in, b.r_out); ++a) {
+                    mul2(seq[q].m[0], b.m[a], tmp);
+                    std::memcpy(b.m[a], tmp, sizeof(tmp));
                 }
-            mul2(u, cur, out);
-            for (int s = 0; s < 2; ++s)
-                for (int t = 0; t < 2; ++t) G1(g.q0, s, t) = out[s][t];
+            }
             continue;
         }
-        if (g.q0 < 0 || g.q0 >= n || g.q1 >= n || g.q0 == g.q1)
-            fail(MPS_ERR_ARG, "two-qubit gate sites out of range or equal");
-        if (used[g.q0] || used[g.q1]) fail(MPS_ERR_ARG, "two-qubit gates of one layer must be disjoint");
-        used[g.q0] = used[g.q1] = 1;
-        // U[(s0 s1), (t0 t1)] -> Ut[(s_i t_i), (s_j t_j)] with i = min site
-        cd u4[2][2][2][2];
-        for (int s0 = 0; s0 < 2; ++s0)
-            for (int s1 = 0; s1 < 2; ++s1)
-                for (int t0 = 0; t0 < 2; ++t0)
-                    for (int t1 = 0; t1 < 2; ++t1) {
-                        const int e = (s0 * 2 + s1) * 4 + (t0 * 2 + t1);
-                        u4[s0][s1][t0][t1] = cd(g.m[2 * e], g.m[2 * e + 1]);
-                    }
-        const bool swapq = g.q0 > g.q1;
-        cd mt[4][4];
-        for (int si = 0; si < 2; ++si)
-            for (int ti = 0; ti < 2; ++ti)
-                for (int sj = 0; sj < 2; ++sj)
-                    for (int tj = 0; tj < 2; ++tj)
-                        mt[si * 2 + ti][sj * 2 + tj] = swapq ? u4[sj][si][tj][ti] : u4[si][sj][ti][tj];
-        double sig[4];
-        cd uu[4][4], vv[4][4];
-        svd4(mt, sig, uu, vv);
-        HostGate h;
-        h.i = std::min(g.q0, g.q1);
-        h.j = std::max(g.q0, g.q1);
-        h.r = 0;
-        for (int a = 0; a < 4; ++a)
-            if (sig[a] > GATE_RANK_CUTOFF * sig[0]) h.r = a + 1;
-        for (int a = 0; a < h.r; ++a) {
-            const double rs = std::sqrt(sig[a]);
-            for (int s = 0; s < 2; ++s)
-                for (int t = 0; t < 2; ++t) {
-                    h.x[a][s][t] = rs * uu[s * 2 + t][a];
-                    h.y[a][s][t] = rs * std::conj(vv[s * 2 + t][a]);
-                }
-        }
-        hg.push_back(h);
+        ProtoOp g = seq[q];
+        if (out.empty())
+            for (int a = 0; a < std::max(g.r_in, g.r_out); ++a) {
+                cd tmp[2][2];
+                mul2(g.m[a], pre, tmp);
+                std::memcpy(g.m[a], tmp, sizeof(tmp));
+            }
+        out.push_back(g);
     }
-    std::sort(hg.begin(), hg.end(), [](const HostGate& a, const HostGate& b) { return a.i < b.i; });
-    // absorb the one-qubit gates (they act first, on the input leg)
-    for (auto& h : hg) {
-        for (int a = 0; a < h.r; ++a) {
-            cd gi[2][2], gj[2][2], tmp[2][2];
-            for (int s = 0; s < 2; ++s)
-                for (int t = 0; t < 2; ++t) { gi[s][t] = G1(h.i, s, t); gj[s][t] = G1(h.j, s, t); }
-            mul2(h.x[a], gi, tmp);
-            std::memcpy(h.x[a], tmp, sizeof(tmp));
-            mul2(h.y[a], gj, tmp);
-            std::memcpy(h.y[a], tmp, sizeof(tmp));
+    if (out.empty()) {
+        ProtoOp g;
+        g.r_in = g.r_out = 1;
+        g.lo = 1;
+        g.H = w_in;
+        std::memcpy(g.m[0], pre, sizeof(pre));
+        out.push_back(g);
+    }
+    std::vector<MpoSiteOp> ops(out.size());
+    for (size_t q = 0; q < out.size(); ++q) {
+        set_op(ops[q], out[q].r_in, out[q].r_out, (int)out[q].lo, out[q].H, out[q].m);
+        ops[q].out_ws = q + 1 < out.size() ? 1 : 0;
+    }
+    return ops;
+}
+
+// Gates of K consecutive layers (n_gates[l] records each, concatenated) -> MPO.
+LayerMpo build_step_mpo(int n, const mps_gate* gates, const int* n_gates, int K) {
+    if (K < 1) fail(MPS_ERR_ARG, "a step needs at least one layer");
+    std::vector<cd> g1m(4 * (size_t)n * K);
+    auto G1 = [&](int l, int k, int s, int t) -> cd& { return g1m[((size_t)l * n + k) * 4 + s * 2 + t]; };
+    std::vector<HostGate> hg;
+    std::vector<int> at(static_cast<size_t>(n) * K, -1);   // [layer][site] -> index into hg
+    int64_t off = 0;
+    for (int l = 0; l < K; ++l) {
+        if (n_gates[l] < 0) fail(MPS_ERR_ARG, "negative gate count");
+        for (int k = 0; k < n; ++k) {
+            G1(l, k, 0, 0) = 1; G1(l, k, 0, 1) = 0; G1(l, k, 1, 0) = 0; G1(l, k, 1, 1) = 1;
         }
+        const size_t first = hg.size();
+        for (int gi = 0; gi < n_gates[l]; ++gi) {
+            const mps_gate& g = gates[off + gi];
+            for (int e = 0; e < 32; ++e)
+                if (!std::isfinite(g.m[e])) fail(MPS_ERR_ARG, "gate matrix has a non-finite entry");
+            if (g.q1 < 0) {
+                if (g.q1 != -1 || g.q0 < 0 || g.q0 >= n) fail(MPS_ERR_ARG, "one-qubit gate site out of range");
+                cd u[2][2], cur[2][2], out[2][2];
+                for (int s = 0; s < 2; ++s)
+                    for (int t = 0; t < 2; ++t) {
+                        u[s][t] = cd(g.m[2 * (s * 2 + t)], g.m[2 * (s * 2 + t) + 1]);
+                        cur[s][t] = G1(l, g.q0, s, t);
+                    }
+                mul2(u, cur, out);
+                for (int s = 0; s < 2; ++s)
+                    for (int t = 0; t < 2; ++t) G1(l, g.q0, s, t) = out[s][t];
+                continue;
+            }
+            if (g.q0 < 0 || g.q0 >= n || g.q1 >= n || g.q0 == g.q1)
+                fail(MPS_ERR_ARG, "two-qubit gate sites out of range or equal");
+            if (at[(size_t)l * n + g.q0] >= 0 || at[(size_t)l * n + g.q1] >= 0)
+                fail(MPS_ERR_ARG, "two-qubit gates of one layer must be disjoint");
+            // U[(s0 s1), (t0 t1)] -> Ut[(s_i t_i), (s_j t_j)] with i = min site
+            cd u4[2][2][2][2];
+            for (int s0 = 0; s0 < 2; ++s0)
+                for (int s1 = 0; s1 < 2; ++s1)
+                    for (int t0 = 0; t0 < 2; ++t0)
+                        for (int t1 = 0; t1 < 2; ++t1) {
+                            const int e = (s0 * 2 + s1) * 4 + (t0 * 2 + t1);
+                            u4[s0][s1][t0][t1] = cd(g.m[2 * e], g.m[2 * e + 1]);
+                        }
+            const bool swapq = g.q0 > g.q1;
+            cd mt[4][4];
+            for (int si = 0; si < 2; ++si)
+                for (int ti = 0; ti < 2; ++ti)
+                    for (int sj = 0; sj < 2; ++sj)
+                        for (int tj = 0; tj < 2; ++tj)
+                            mt[si * 2 + ti][sj * 2 + tj] = swapq ? u4[sj][si][tj][ti] : u4[si][sj][ti][tj];
+            double sig[4];
+            cd uu[4][4], vv[4][4];
+            svd4(mt, sig, uu, vv);
+            HostGate h;
+            h.i = std::min(g.q0, g.q1);
+            h.j = std::max(g.q0, g.q1);
+            h.layer = l;
+            h.r = 0;
+            for (int a = 0; a < 4; ++a)
+                if (sig[a] > GATE_RANK_CUTOFF * sig[0]) h.r = a + 1;
+            for (int a = 0; a < h.r; ++a) {
+                const double rs = std::sqrt(sig[a]);
+                for (int s = 0; s < 2; ++s)
+                    for (int t = 0; t < 2; ++t) {
+                        h.x[a][s][t] = rs * uu[s * 2 + t][a];
+                        h.y[a][s][t] = rs * std::conj(vv[s * 2 + t][a]);
+                    }
+            }
+            at[(size_t)l * n + h.i] = at[(size_t)l * n + h.j] = (int)hg.size();
+            hg.push_back(h);
+        }
+        // this layer's one-qubit gates act before its two-qubit gates: absorb them on the input leg
+        for (size_t q = first; q < hg.size(); ++q) {
+            HostGate& h = hg[q];
+            for (int a = 0; a < h.r; ++a) {
+                cd gi[2][2], gj[2][2], tmp[2][2];
+                for (int s = 0; s < 2; ++s)
+                    for (int t = 0; t < 2; ++t) { gi[s][t] = G1(l, h.i, s, t); gj[s][t] = G1(l, h.j, s, t); }
+                mul2(h.x[a], gi, tmp);
+                std::memcpy(h.x[a], tmp, sizeof(tmp));
+                mul2(h.y[a], gj, tmp);
+                std::memcpy(h.y[a], tmp, sizeof(tmp));
+            }
+        }
+        off += n_gates[l];
     }
     LayerMpo L;
     L.n_2q = (int)hg.size();
     L.w.assign(n + 1, 1);
-    std::vector<int> start_at(n, -1), end_at(n, -1);
-    for (int g = 0; g < (int)hg.size(); ++g) {
-        start_at[hg[g].i] = g;
-        end_at[hg[g].j] = g;
-    }
     for (int c = 0; c <= n; ++c) {
         int64_t w = 1;
         for (auto& h : hg)
-            if (h.i < c && c <= h.j) w *= h.r;
+            if (h.i < c && c <= h.j) {
+                w *= h.r;
+                if (w > (int64_t)1 << 24) fail(MPS_ERR_ARG, "MPO bond dimension exceeds 2^24");
+            }
         L.w[c] = w;
-        if (w > (int64_t)1 << 24) fail(MPS_ERR_ARG, "MPO bond dimension exceeds 2^24");
     }
+    // digit a is less significant than digit b
+    auto less_sig = [&](int a, int b) {
+        return hg[a].i > hg[b].i || (hg[a].i == hg[b].i && hg[a].layer > hg[b].layer);
+    };
+    auto open_at = [&](int c) {
+        std::vector<int> v;
+        for (int q = 0; q < (int)hg.size(); ++q)
+            if (hg[q].i < c && c <= hg[q].j) v.push_back(q);
+        return v;
+    };
+    auto prod = [&](const std::vector<int>& v) {
+        int64_t p = 1;
+        for (int q : v) p *= hg[q].r;
+        return p;
+    };
+    auto below = [&](const std::vector<int>& v, int g) {
+        int64_t p = 1;
+        for (int q : v)
+            if (q != g && less_sig(q, g)) p *= hg[q].r;
+        return p;
+    };
     L.view[0].resize(n);
     L.view[1].resize(n);
     for (int k = 0; k < n; ++k) {
-        MpoSiteOp& f = L.view[0][k];
-        MpoSiteOp& b = L.view[1][n - 1 - k];
-        if (start_at[k] >= 0) {
-            const HostGate& h = hg[start_at[k]];
-            // the opening gate has the largest left site of bond k+1: least significant
-            set_op(f, 1, h.r, 1, L.w[k], h.x);
-            set_op(b, h.r, 1, 1, L.w[k], h.x);
-        } else if (end_at[k] >= 0) {
-            const HostGate& h = hg[end_at[k]];
-            int64_t lo = 1;
-            for (auto& o : hg)
-                if (o.i < k && k <= o.j && o.i > h.i) lo *= o.r;
-            set_op(f, h.r, 1, (int)lo, L.w[k] / (h.r * lo), h.y);
-            set_op(b, 1, h.r, (int)lo, L.w[k + 1] / lo, h.y);
-        } else {
-            cd g[1][2][2];
-            for (int s = 0; s < 2; ++s)
-                for (int t = 0; t < 2; ++t) g[0][s][t] = G1(k, s, t);
-            set_op(f, 1, 1, 1, L.w[k], g);
-            set_op(b, 1, 1, 1, L.w[k], g);
+        // view 0 runs site k from bond k to bond k+1, view 1 from bond k+1 to bond k
+        for (int o = 0; o < 2; ++o) {
+            std::vector<int> present = open_at(o == 0 ? k : k + 1);
+            const int64_t w_in = prod(present);
+            std::vector<ProtoOp> seq;
+            std::vector<bool> is_1q;
+            for (int l = 0; l < K; ++l) {
+                ProtoOp p;
+                const int g = at[(size_t)l * n + k];
+                if (g < 0) {
+                    p.r_in = p.r_out = 1;
+                    p.lo = 1;
+                    p.H = prod(present);
+                    for (int s = 0; s < 2; ++s)
+                        for (int t = 0; t < 2; ++t) p.m[0][s][t] = G1(l, k, s, t);
+                    seq.push_back(p);
+                    is_1q.push_back(true);
+                    continue;
+                }
+                const HostGate& h = hg[g];
+                const bool opens = (h.i == k) == (o == 0);   // the digit appears in this view's direction
+                const int64_t lo = below(present, g);
+                p.lo = lo;
+                if (opens) {
+                    p.r_in = 1;
+                    p.r_out = h.r;
+                    p.H = prod(present) / lo;
+                    present.push_back(g);
+                } else {
+                    p.r_in = h.r;
+                    p.r_out = 1;
+                    p.H = prod(present) / (h.r * lo);
+                    present.erase(std::find(present.begin(), present.end(), g));
+                }
+                std::memcpy(p.m, h.i == k ? h.x : h.y, sizeof(p.m));
+                seq.push_back(p);
+                is_1q.push_back(false);
+            }
+            L.view[o][o == 0 ? k : n - 1 - k] = fold_site_ops(seq, is_1q, w_in);
         }
     }
     return L;
 }
+
+LayerMpo build_layer_mpo(int n, const mps_gate* gates, int n_gates) { return build_step_mpo(n, gates, &n_gates, 1); }
 
 }  // namespace
 
@@ -743,6 +853,7 @@ struct Engine {
     std::vector<Planar<double>> phi;  // per site, layout of the pass that wrote it
     Planar<R> X, T2, TH, UR, T2T;
     Planar<R> XR, T2R[2];             // right blocks, written on the second stream
+    Planar<R> MT[2][2];               // per lane: intermediates of multi-layer MPO factors
     bool split = false;   // BF16 x 3 contractions (R = float only): operands kept k-contiguous
     Planar<double> TH64, GR, U64, V64, M64;
     EighWork ew;
@@ -755,6 +866,7 @@ struct Engine {
     ~Engine() {
         if (st->stream2) (void)hipStreamSynchronize(st->stream2);   // right blocks in flight
         XR.release(s); T2R[0].release(s); T2R[1].release(s);
+        for (auto& l : MT) { l[0].release(s); l[1].release(s); }
         for (auto& e : env) e.release(s);
         for (int o = 0; o < 2; ++o)
             for (auto& e : psi[o]) e.release(s);
@@ -985,10 +1097,26 @@ struct Engine {
         else
             gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_N, cL * wL, 2 * DM, DL, env[bL].re(), env[bL].im(), DL,
                     psi[o][j].re(), psi[o][j].im(), 2 * DM, xb.re(), xb.im(), 2 * DM, &ln);
-        const MpoSiteOp& op = mpo.view[o][j];
-        Timer t(st, MPS_KCLASS_MPO, 0, 2.0 * sizeof(R) * (cL * wL * 2 * DM + cL * 2 * wM * DM), ln.s);
-        HIPCHK(mpo_apply<R>(op, cL, DM, xb.re(), xb.im(), out.re(), out.im(), ln.s));
-        t.done();
+        const std::vector<MpoSiteOp>& ops = mpo.view[o][j];
+        // several layers acting at this site: one factor after the other, through
+        // two temporaries of the lane
+        Planar<R>* tmp = MT[ln.s == s ? 0 : 1];
+        const R* in_re = xb.re();
+        const R* in_im = xb.im();
+        int64_t w_in = wL;
+        for (size_t q = 0; q < ops.size(); ++q) {
+            const MpoSiteOp& op = ops[q];
+            const int64_t w_out = (int64_t)op.H * op.r_out * op.lo;
+            Planar<R>& dst = q + 1 == ops.size() ? out : tmp[q & 1];
+            dst.ensure(cL * 2 * w_out * DM, ln.s);
+            Timer t(st, MPS_KCLASS_MPO, 0, 2.0 * sizeof(R) * (cL * w_in * 2 * DM + cL * 2 * w_out * DM), ln.s);
+            HIPCHK(mpo_apply<R>(op, cL, DM, in_re, in_im, dst.re(), dst.im(), ln.s));
+            t.done();
+            in_re = dst.re();
+            in_im = dst.im();
+            w_in = w_out;
+        }
+        if (w_in != wM) fail(MPS_ERR_DEVICE, "MPO factors do not end on the bond dimension");
     }
 
     void left_block(int o, int j) { block(o, j, X, T2, main_lane(st)); }
@@ -1178,8 +1306,8 @@ struct Engine {
 
     bool single_site = false;
 
-    double run(const mps_gate* gates, int n_gates, int n_sweeps) {
-        mpo = build_layer_mpo(n, gates, n_gates);
+    double run(const mps_gate* gates, const int* n_gates, int n_layers, int n_sweeps) {
+        mpo = build_step_mpo(n, gates, n_gates, n_layers);
         setup();
         const int oz = st->center == 0 ? 0 : 1;
         double f = zipup(oz);
@@ -1236,14 +1364,22 @@ void check_state(const mps_state* st) {
 }
 
 
-void apply_layer_impl(mps_state* st, const mps_gate* gates, int n_gates, int chi, int n_sweeps, double* f_layer,
-                      bool single_site = false) {
+// One compression step over n_layers consecutive layers (n_gates[l] records each).
+void apply_step_impl(mps_state* st, const mps_gate* gates, const int* n_gates, int n_layers, int chi, int n_sweeps,
+                     double* f_layer, bool single_site) {
     check_state(st);
-    if (n_gates < 0 || (n_gates > 0 && !gates)) fail(MPS_ERR_ARG, "gates is NULL");
+    if (n_layers < 1 || n_layers > 64) fail(MPS_ERR_ARG, "n_layers must be in [1, 64]");
+    if (!n_gates) fail(MPS_ERR_ARG, "n_gates is NULL");
+    int64_t total = 0;
+    for (int l = 0; l < n_layers; ++l) {
+        if (n_gates[l] < 0) fail(MPS_ERR_ARG, "negative gate count");
+        total += n_gates[l];
+    }
+    if (total > 0 && !gates) fail(MPS_ERR_ARG, "gates is NULL");
     if (chi < 1 || chi > st->max_chi) fail(MPS_ERR_ARG, "chi must be in [1, max_chi]");
     if (n_sweeps < 0) fail(MPS_ERR_ARG, "n_sweeps must be >= 0");
     // argument validation happens in the MPO build, before any device work
-    (void)build_layer_mpo(st->n, gates, n_gates);
+    (void)build_step_mpo(st->n, gates, n_gates, n_layers);
     const size_t log_mark = st->log_step_f.size();
     double f = 0;
     try {
@@ -1251,11 +1387,11 @@ void apply_layer_impl(mps_state* st, const mps_gate* gates, int n_gates, int chi
             Engine<float> e(st, chi);
             e.split = st->prec == MPS_BF16X3;
             e.single_site = single_site;
-            f = e.run(gates, n_gates, n_sweeps);
+            f = e.run(gates, n_gates, n_layers, n_sweeps);
         } else {
             Engine<double> e(st, chi);
             e.single_site = single_site;
-            f = e.run(gates, n_gates, n_sweeps);
+            f = e.run(gates, n_gates, n_layers, n_sweeps);
         }
         HIPCHK(hipStreamSynchronize(st->stream));
         if (!(f > 0) || !std::isfinite(f)) fail(MPS_ERR_NUMERIC, "non-positive layer fidelity");
@@ -1269,8 +1405,13 @@ void apply_layer_impl(mps_state* st, const mps_gate* gates, int n_gates, int chi
     }
     flush_timings(st);
     st->log_f += std::log(f);
-    st->n_layers += 1;
+    st->n_layers += n_layers;
     if (f_layer) *f_layer = f;
+}
+
+void apply_layer_impl(mps_state* st, const mps_gate* gates, int n_gates, int chi, int n_sweeps, double* f_layer,
+                      bool single_site = false) {
+    apply_step_impl(st, gates, &n_gates, 1, chi, n_sweeps, f_layer, single_site);
 }
 
 }  // namespace
@@ -1360,6 +1501,14 @@ mps_status apply_layer_dmrg(mps_state* st, const mps_gate* gates, int n_gates, i
 mps_status apply_layer_dmrg_single_site(mps_state* st, const mps_gate* gates, int n_gates, int chi, int n_sweeps,
                             double* f_layer) {
     return run_guarded([&] { apply_layer_impl(st, gates, n_gates, chi, n_sweeps, f_layer, true); });
+}
+
+mps_status apply_layers_dmrg(mps_state* st, const mps_gate* gates, const int* n_gates, int n_layers, int chi,
+                             int n_sweeps, int update, double* f_step) {
+    return run_guarded([&] {
+        if (update != MPS_UPDATE_TWO_SITE && update != MPS_UPDATE_SINGLE_SITE) fail(MPS_ERR_ARG, "unknown update rule");
+        apply_step_impl(st, gates, n_gates, n_layers, chi, n_sweeps, f_step, update == MPS_UPDATE_SINGLE_SITE);
+    });
 }
 
 mps_status apply_layer_dmrg_batched(mps_state* const* states, int batch, const mps_gate* const* gates,

@@ -70,8 +70,14 @@ hipError_t cgemm_bf16x3_nt(int M, int N, int K, CView<float> A, CView<float> B, 
 //   w_in = H * r_in * lo, w_out = H * r_out * lo; one of r_in, r_out is 1.
 //   out[p][s][(h r_out + a_out) lo + l][q] =
 //       sum_{a_in, t} op[a_out][a_in][s][t] in[p][(h r_in + a_in) lo + l][t][q]
+// One factor of a site's MPO tensor: it maps the bond digit of one gate
+// (stride lo, H combinations of the more significant digits) from r_in to
+// r_out values and the physical index t to s.  Input layout [P][w_in][2 (t)][Q];
+// output [P][2 (s)][w_out][Q], or [P][w_out][2 (s)][Q] when out_ws is set (the
+// input layout of the next factor, for sites where several layers act).
 struct MpoSiteOp {
     int r_in, r_out, lo, H;
+    int out_ws;
     double re[16], im[16];     // [(a_out * r_in + a_in) * 4 + s * 2 + t]
 };
 template <typename T>

@@ -22,7 +22,7 @@ static inline unsigned grid_for(int64_t n, int block) {
 // ---------------------------------------------------------------- MPO ------
 template <typename T>
 struct MpoOpT {
-    int r_in, r_out, lo, H;
+    int r_in, r_out, lo, H, out_ws;
     T re[16], im[16];
 };
 
@@ -68,7 +68,8 @@ __global__ __launch_bounds__(256) void mpo_apply_kernel(MpoOpT<T> op, int64_t P,
                         ai += orr * xi[a * 2 + t] + oii * xr[a * 2 + t];
                     }
                 }
-                const int64_t off = ((p * 2 + s) * w_out + (h * r_out + ao) * lo + l) * Q + q;
+                const int64_t wo = (h * r_out + ao) * lo + l;
+                const int64_t off = op.out_ws ? ((p * w_out + wo) * 2 + s) * Q + q : ((p * 2 + s) * w_out + wo) * Q + q;
                 out_re[off] = ar;
                 out_im[off] = ai;
             }
@@ -82,7 +83,7 @@ hipError_t mpo_apply(const MpoSiteOp& op, int64_t P, int64_t Q, const T* in_re, 
     if (op.r_in < 1 || op.r_out < 1 || op.r_in > 4 || op.r_out > 4 || op.r_in * op.r_out > 4)
         return hipErrorInvalidValue;
     MpoOpT<T> o;
-    o.r_in = op.r_in; o.r_out = op.r_out; o.lo = op.lo; o.H = op.H;
+    o.r_in = op.r_in; o.r_out = op.r_out; o.lo = op.lo; o.H = op.H; o.out_ws = op.out_ws;
     for (int i = 0; i < 16; ++i) { o.re[i] = (T)op.re[i]; o.im[i] = (T)op.im[i]; }
     const int64_t total = P * op.H * op.lo * Q;
     if (total <= 0) return hipSuccess;

@@ -22,6 +22,8 @@ LIB_PATH = os.path.join(HERE, "libmpsdmrg.so")
 
 MPS_OK, MPS_ERR_ARG, MPS_ERR_OOM, MPS_ERR_DEVICE, MPS_ERR_NUMERIC, MPS_ERR_STATE = 0, -1, -2, -3, -4, -5
 MPS_FP64, MPS_FP32, MPS_BF16X3 = 0, 1, 3
+MPS_UPDATE_TWO_SITE, MPS_UPDATE_SINGLE_SITE = 0, 1
+_UPDATES = {"two-site": MPS_UPDATE_TWO_SITE, "single-site": MPS_UPDATE_SINGLE_SITE}
 KCLASS = {"contract": 0, "mpo": 1, "gram": 2, "eigh": 3, "other": 4, "tridiag": 5}
 
 # every symbol declared in include/mps_dmrg.h
@@ -30,7 +32,7 @@ EXPORTS = ("mps_create", "mps_destroy", "apply_layer_dmrg", "apply_layer_dmrg_si
            "mps_last_error",
            "mps_amplitude", "mps_to_statevector", "mps_bond_dims", "mps_get_tensor", "mps_step_log",
            "mps_expect_zz", "mps_set_profiling", "mps_kernel_stats", "mps_kernel_selftest_cgemm",
-           "mps_kernel_selftest_eigh", "mps_overlap")
+           "mps_kernel_selftest_eigh", "mps_overlap", "apply_layers_dmrg")
 
 _lib = None
 
@@ -78,6 +80,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mps_kernel_selftest_cgemm": (i32, [i32, i32, i32, i32, i32, i32, dp, dp, dp]),
         "mps_kernel_selftest_eigh": (i32, [i32, dp, i32, dp, dp, ip]),
         "mps_overlap": (i32, [P, P, dp, dp]),
+        "apply_layers_dmrg": (i32, [P, P, ip, i32, i32, i32, i32, dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -149,6 +152,20 @@ class MPS:
         else:
             raise ValueError("update must be 'two-site' or 'single-site'")
         _check(fn(self._h, rec.ctypes.data, len(rec), chi, n_sweeps, ctypes.byref(f)))
+        return f.value
+
+    def apply_layers_dmrg(self, layers, chi: int, n_sweeps: int, update: str = "two-site") -> float:
+        """One compression step over K = len(layers) consecutive layers (apply_layers_dmrg)."""
+        if update not in _UPDATES:
+            raise ValueError("update must be 'two-site' or 'single-site'")
+        recs = [np.ascontiguousarray(l if isinstance(l, np.ndarray) else circuits.pack_layer(l),
+                                     dtype=circuits.GATE_DTYPE) for l in layers]
+        counts = np.ascontiguousarray([len(r) for r in recs], dtype=np.int32)
+        allrec = np.ascontiguousarray(np.concatenate(recs) if recs else np.zeros(0, circuits.GATE_DTYPE),
+                                      dtype=circuits.GATE_DTYPE)
+        f = ctypes.c_double(0.0)
+        _check(_lib.apply_layers_dmrg(self._h, allrec.ctypes.data if len(allrec) else None, _iptr(counts),
+                                      len(recs), chi, n_sweeps, _UPDATES[update], ctypes.byref(f)))
         return f.value
 
     def fidelity(self):
@@ -260,6 +277,10 @@ def mps_create(n, bits=None, max_chi=1024, precision=MPS_FP32, stream=None) -> M
 
 def apply_layer_dmrg(state: MPS, layer, chi: int, n_sweeps: int) -> float:
     return state.apply_layer_dmrg(layer, chi, n_sweeps)
+
+
+def apply_layers_dmrg(state: MPS, layers, chi: int, n_sweeps: int, update: str = "two-site") -> float:
+    return state.apply_layers_dmrg(layers, chi, n_sweeps, update)
 
 
 def apply_layer_dmrg_batched(states: Sequence[MPS], layers, chis: Sequence[int], n_sweeps: int) -> np.ndarray:
