@@ -198,6 +198,88 @@ def random_circuit(grid: Grid, depth: int, seed: int, two_qubit: str = "haar",
                                                   two_qubit, seed))
 
 
+# ------------------------------------------------------ Sycamore layout ----
+@dataclasses.dataclass
+class SycamoreLayout:
+    """The processor topology of the paper's Fig. 1: n_c columns holding n_b and n_b - 1
+    qubits alternately (column 0 holds n_b).  Qubit (c, y) has column c and height y:
+    y = 0, 2, .., 2(n_b - 1) in even columns and y = 1, 3, .., 2n_b - 3 in odd ones, so
+    nearest neighbours are the diagonal pairs (c, y)-(c + 1, y +- 1).  Chain order is
+    column by column, bottom to top (the order of the vertical groupings).
+
+    Coupler classes, each a matching:
+      A: (c, y)-(c+1, y+1), c even     B: (c, y)-(c+1, y+1), c odd
+      C: (c, y)-(c+1, y-1), c even     D: (c, y)-(c+1, y-1), c odd
+    A quarter turn of the lattice maps A -> C -> B -> D -> A, the letter map that takes
+    the paper's Sequence I string to its Sequence II string.
+    """
+    n_b: int
+    n_c: int
+
+    def column_len(self, c: int) -> int:
+        return self.n_b if c % 2 == 0 else self.n_b - 1
+
+    @property
+    def n(self) -> int:
+        return sum(self.column_len(c) for c in range(self.n_c))
+
+    def coords(self) -> List[Tuple[int, int]]:
+        return [(c, 2 * r + (c % 2)) for c in range(self.n_c) for r in range(self.column_len(c))]
+
+    def site(self, c: int, y: int) -> int:
+        if not (0 <= c < self.n_c) or (y - c) % 2 != 0 or not (0 <= (y - c % 2) // 2 < self.column_len(c)):
+            raise ValueError("no qubit at (%d, %d)" % (c, y))
+        return sum(self.column_len(k) for k in range(c)) + (y - c % 2) // 2
+
+    def has(self, c: int, y: int) -> bool:
+        try:
+            self.site(c, y)
+            return True
+        except ValueError:
+            return False
+
+    def pattern_pairs(self, letter: str) -> List[Tuple[int, int]]:
+        """Chain-site pairs (i < j) of coupler class A, B, C or D."""
+        parity = 0 if letter in "AC" else 1
+        dy = 1 if letter in "AB" else -1
+        pairs = []
+        for c, y in self.coords():
+            if c % 2 == parity and self.has(c + 1, y + dy):
+                a, b = self.site(c, y), self.site(c + 1, y + dy)
+                pairs.append((min(a, b), max(a, b)))
+        return sorted(pairs)
+
+
+# Sequence I is the supremacy pattern ABCD-CDAB; Sequence II is the same pattern turned by a
+# quarter (CDBA-BACD).
+SEQUENCE_I = "ABCDCDAB"
+SEQUENCE_II = "CDBABACD"
+FSIM_THETA, FSIM_PHI = 1.0, np.pi / 2     # the fixed fSim of the paper's Sequences I and II
+
+
+def sycamore_circuit(layout: SycamoreLayout, depth: int, seed: int, sequence: str = "I",
+                     two_qubit: str = "fsim") -> Circuit:
+    """Sequence I or II on the Sycamore layout: per layer a random one-qubit gate from
+    {sqrt X, sqrt Y, sqrt W} on every qubit, then a two-qubit gate on every coupler of the
+    layer's class: fSim(1, pi/2) (``two_qubit="fsim"``, the paper's choice) or a Haar U(4)
+    per coupler (``"haar"``, whose Schmidt spectra have no structural ties)."""
+    pattern = {"I": SEQUENCE_I, "II": SEQUENCE_II}[sequence]
+    if two_qubit not in ("fsim", "haar"):
+        raise ValueError(two_qubit)
+    rng = np.random.default_rng(seed)
+    u2 = fsim(FSIM_THETA, FSIM_PHI)
+    layers: List[List[Gate]] = []
+    for d in range(depth):
+        choice = rng.integers(0, 3, size=layout.n)
+        layer: List[Gate] = [(s, -1, ONE_QUBIT_SET[int(choice[s])]) for s in range(layout.n)]
+        for i, j in layout.pattern_pairs(pattern[d % len(pattern)]):
+            layer.append((i, j, u2 if two_qubit == "fsim" else haar_unitary_from_normals(rng.standard_normal(32))))
+        layers.append(layer)
+    return Circuit(n=layout.n, layers=layers,
+                   label="sycamore_nb%d_nc%d_seq%s_d%d_%s_s%d" % (layout.n_b, layout.n_c, sequence, depth,
+                                                                 two_qubit, seed))
+
+
 def random_brickwork(n: int, depth: int, seed: int) -> Circuit:
     """Nearest-neighbour chain brickwork of Haar gates with random 1q gates.
 
@@ -228,6 +310,11 @@ def grid36_workload(seed: int) -> Circuit:
 def sycamore_like_54_workload(seed: int = 0, depth: int = 20) -> Circuit:
     """54 qubits on a 6x9 grid (snake over width 6), fSim(theta, phi) 2q gates."""
     return random_circuit(grid_from_shape(9, 6), depth, seed, "fsim")
+
+
+def sycamore_54_workload(seed: int = 0, depth: int = 20, sequence: str = "I") -> Circuit:
+    """The paper's 54-qubit processor (n_b = 5, n_c = 12), Sequence I or II, depth 20."""
+    return sycamore_circuit(SycamoreLayout(5, 12), depth, seed, sequence)
 
 
 def batched_instances(count: int = 64, seed: int = 0):

@@ -546,3 +546,76 @@ def test_metropolis_chain_on_porter_thomas_state():
     rng = np.random.default_rng(4)
     a, b = rng.integers(0, 2 ** n, 200000), rng.integers(0, 2 ** n, 200000)
     assert abs(np.minimum(p[b] / p[a], 1.0).mean() - math.log(2)) < 0.02
+
+
+# ------------------------------------------------------- Sycamore layout ---
+def test_sycamore_layout_couplers():
+    """Fig. 1 topology: n_c columns of n_b and n_b - 1 qubits (54 for n_b = 5, n_c = 12); each
+    coupler class is a matching and the four classes split the nearest-neighbour couplers."""
+    lay = circuits.SycamoreLayout(5, 12)
+    assert lay.n == 54
+    coords = lay.coords()
+    assert len(set(coords)) == 54 and sorted(lay.site(c, y) for c, y in coords) == list(range(54))
+    nn = set()
+    for a, (c1, y1) in enumerate(coords):
+        for b, (c2, y2) in enumerate(coords):
+            if a < b and abs(c1 - c2) == 1 and abs(y1 - y2) == 1:
+                nn.add((lay.site(c1, y1), lay.site(c2, y2)))
+    seen = []
+    for letter in "ABCD":
+        pairs = lay.pattern_pairs(letter)
+        flat = [q for p in pairs for q in p]
+        assert len(flat) == len(set(flat))                         # a matching
+        seen += pairs
+    assert len(seen) == len(set(seen)) and set(seen) == {(min(p), max(p)) for p in nn}
+    degree = np.bincount([q for p in seen for q in p], minlength=54)
+    assert degree.max() == 4 and degree.min() >= 1
+
+
+def test_sycamore_sequence_two_is_the_quarter_turn():
+    """The letter map that takes Sequence I's string to Sequence II's (A->C, B->D, C->B,
+    D->A) is the map of coupler classes under a quarter turn of the lattice."""
+    mp = dict(zip(circuits.SEQUENCE_I, circuits.SEQUENCE_II))
+    assert mp == {"A": "C", "B": "D", "C": "B", "D": "A"}
+
+    def cls(p, q):
+        (c1, y1), (c2, y2) = sorted([p, q])
+        return {(0, 1): "A", (1, 1): "B", (0, -1): "C", (1, -1): "D"}[(c1 % 2, y2 - y1)]
+
+    lay = circuits.SycamoreLayout(7, 10)
+    pos = {lay.site(c, y): (c, y) for c, y in lay.coords()}
+    turn = lambda c, y: (-y + 1, c + 1)
+    for letter in "ABCD":
+        for i, j in lay.pattern_pairs(letter):
+            assert cls(pos[i], pos[j]) == letter
+            assert cls(turn(*pos[i]), turn(*pos[j])) == mp[letter]
+
+
+def test_fixed_fsim_has_four_schmidt_values():
+    """fSim(1, pi/2) has four non-zero operator-Schmidt values (the hard regime of the
+    paper's Sequences I and II), so every coupler multiplies the MPO bond by 4.  The
+    spectrum of fSim(theta, phi) has the closed form
+    sqrt(1 + cos^2 theta +- 2 cos theta cos(phi/2)), sin theta, sin theta."""
+    for th, ph in ((circuits.FSIM_THETA, circuits.FSIM_PHI), (0.3, 2.5), (1.2, 0.4)):
+        g = dmrg.split_two_qubit(0, 1, circuits.fsim(th, ph))
+        got = np.sort(np.einsum("ast,ast->a", g.x.conj(), g.x).real)     # |X_a|^2 = sigma_a
+        c = np.cos(th)
+        want = np.sort([np.sqrt(1 + c * c + 2 * c * np.cos(ph / 2)), np.sqrt(1 + c * c - 2 * c * np.cos(ph / 2)),
+                        np.sin(th), np.sin(th)])
+        assert g.x.shape[0] == 4 and np.allclose(got, want, atol=1e-12)
+
+
+@pytest.mark.parametrize("sequence", ["I", "II"])
+def test_sycamore_circuit_exact_regime(sequence):
+    """Sequences I and II on a 10-qubit layout (n_b = 3, n_c = 4): chi = 32 = 2^(n/2)
+    reproduces the statevector, one and two layers per step."""
+    c = circuits.sycamore_circuit(circuits.SycamoreLayout(3, 4), 8, seed=2, sequence=sequence)
+    assert c.n == 10 and c.n_2q == sum(len(circuits.SycamoreLayout(3, 4).pattern_pairs(
+        {"I": circuits.SEQUENCE_I, "II": circuits.SEQUENCE_II}[sequence][d % 8])) for d in range(8))
+    psi = sv.run(c)
+    st = dmrg.run_circuit(c, chi=32, n_sweeps=1)
+    assert np.linalg.norm(dmrg.to_statevector(st) - psi) < 1e-12
+    st2 = dmrg.product_state(c.n)
+    for d in range(0, 8, 2):
+        dmrg.apply_layers(st2, c.layers[d:d + 2], chi=32, n_sweeps=1)
+    assert np.linalg.norm(dmrg.to_statevector(st2) - psi) < 1e-12
