@@ -619,3 +619,40 @@ def test_sycamore_circuit_exact_regime(sequence):
     for d in range(0, 8, 2):
         dmrg.apply_layers(st2, c.layers[d:d + 2], chi=32, n_sweeps=1)
     assert np.linalg.norm(dmrg.to_statevector(st2) - psi) < 1e-12
+
+
+# ------------------------------------------------------- fidelity measures -
+def test_fidelity_measures_special_cases():
+    """F and F_B on states where they are fixed: F(psi, psi) = 1; F_B = 0 exactly against a
+    uniform-modulus state; F_B of a product of independent blocks factorises as
+    prod_b (1 + F_B,b) - 1; F <= 1 with equality only up to a phase."""
+    from oracle import analysis
+    rng = np.random.default_rng(4)
+    a = chaotic.porter_thomas(8, rng); a /= np.linalg.norm(a)
+    assert abs(analysis.fidelity(a, a) - 1.0) < 1e-13
+    assert abs(analysis.fidelity(a, 1j * a) - 1.0) < 1e-13
+    flat = np.exp(2j * np.pi * rng.random(256)) / 16.0
+    assert abs(analysis.xeb_exact(flat, a)) < 1e-13 and abs(analysis.xeb_exact(a, flat)) < 1e-13
+    b1 = chaotic.porter_thomas(4, rng); b1 /= np.linalg.norm(b1)
+    b2 = chaotic.porter_thomas(4, rng); b2 /= np.linalg.norm(b2)
+    c1 = chaotic.porter_thomas(4, rng); c1 /= np.linalg.norm(c1)
+    c2 = chaotic.porter_thomas(4, rng); c2 /= np.linalg.norm(c2)
+    whole = analysis.xeb_exact(np.kron(b1, b2), np.kron(c1, c2))
+    parts = (1 + analysis.xeb_exact(b1, c1)) * (1 + analysis.xeb_exact(b2, c2)) - 1
+    assert abs(whole - parts) < 1e-12
+    assert analysis.fidelity(b1, c1) < 1.0
+
+
+def test_xeb_estimator_converges_to_the_exact_value():
+    """eq:FB-estim: samples drawn from Q give an unbiased estimate of eq:FB-sup."""
+    from oracle import analysis
+    rng = np.random.default_rng(6)
+    p = chaotic.porter_thomas(10, rng); p /= np.linalg.norm(p)
+    q = 0.8 * p + 0.6 * chaotic.porter_thomas(10, rng) / 32.0
+    q /= np.linalg.norm(q)
+    exact = analysis.xeb_exact(q, p)
+    probs_q = np.abs(q) ** 2
+    xs = rng.choice(1024, size=200000, p=probs_q / probs_q.sum())
+    est = analysis.xeb_estimate(np.abs(p[xs]) ** 2, 10)
+    sd = np.std(1024 * np.abs(p[xs]) ** 2) / math.sqrt(len(xs))
+    assert abs(est - exact) < 4 * sd, (est, exact, sd)
