@@ -281,6 +281,44 @@ mps_status mps_kernel_selftest_cgemm(int precision, int opa, int opb, int M, int
  * MPS_EIGENSOLVER = rocsolver | persistent, default persistent). */
 mps_status mps_kernel_selftest_eigh(int n, const double* a, int method, double* w, double* z, int* used);
 
+/* ---- The exact state, for measuring the simulation (Sec. VI, VII) ---------
+ * The brute-force statevector U|0> (the perfect state of eq:F-sup) held in
+ * device memory: FP64 planar, 2^n amplitudes, chain site q is bit n-1-q of
+ * the index (site 0 most significant, as in mps_to_statevector).  It needs
+ * 16 * 2^n bytes (64 GiB at 32 qubits); sv_compare_mps needs twice that again
+ * as scratch.  A state belongs to one thread at a time. */
+typedef struct sv_state sv_state;
+
+/* Create |x> on n_qubits qubits, 1 <= n_qubits <= 34.  init_bits: n_qubits
+ * bytes of 0/1 (NULL = |0...0>).  hip_stream: stream for all its work.
+ * MPS_ERR_OOM when the device cannot hold it.  Release with sv_destroy. */
+mps_status sv_create(int n_qubits, const uint8_t* init_bits, void* hip_stream, sv_state** out);
+
+/* Release a statevector.  NULL is accepted. */
+mps_status sv_destroy(sv_state* sv);
+
+/* Apply one layer (the gate records and rules of mps_gate: one-qubit gates
+ * first, disjoint two-qubit gates) exactly.  The layer's one-qubit gates are
+ * folded into the two-qubit gate on their qubit; the others are applied two
+ * at a time.  MPS_ERR_ARG (state unchanged) for invalid gates. */
+mps_status sv_apply_layer(sv_state* sv, const mps_gate* gates, int n_gates);
+
+/* out[2t], out[2t+1] = amplitude of index indices[t] (HOST arrays; indices in
+ * [0, 2^n)). */
+mps_status sv_amplitudes(const sv_state* sv, int64_t count, const int64_t* indices, double* out);
+
+/* Measure an MPS against the exact state (n_sites == n_qubits): the MPS is
+ * expanded to its 2^n amplitudes phi on the device, then, with psi the exact
+ * state and all sums in a fixed order,
+ *   overlap[2] = <phi|psi> (re, im);
+ *   *F   = |<phi|psi>|^2 (eq:F-sup);
+ *   *F_B = 2^n sum_x |psi_x|^2 |phi_x|^2 - 1 (eq:FB-sup);
+ *   norms[2] = <phi|phi>, <psi|psi>.
+ * Any output may be NULL.  Runs on the MPS's stream after the statevector's
+ * stream has drained; allocates 2 x 16 x 2^n bytes of scratch for the call. */
+mps_status sv_compare_mps(const sv_state* sv, mps_state* mps, double* overlap, double* F, double* F_B,
+                          double* norms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1982,3 +1982,256 @@ extern "C" mps_status mps_kernel_selftest_cgemm(int precision, int opa, int opb,
         else fail(MPS_ERR_ARG, "unknown precision");
     });
 }
+
+// ======================================================= exact statevector ===
+// The brute-force state U|0> kept in HBM, against which an MPS is measured
+// (F of eq:F-sup, F_B of eq:FB-sup).
+struct sv_state {
+    int n = 0;
+    hipStream_t stream = nullptr;
+    double* re = nullptr;   // one allocation: re block of 2^n, then im block
+    double* im = nullptr;
+};
+
+namespace {
+
+constexpr int SV_MAX_QUBITS = 34;
+
+struct SvTwo {
+    int q0, q1;
+    cd u[4][4];   // row 2 s_q0 + s_q1
+};
+
+// One layer under the rules of mps_gate: per-qubit products of the one-qubit gates (list
+// order) and the two-qubit gates, checked for range, finiteness and disjointness.
+void parse_sv_layer(int n, const mps_gate* gates, int n_gates, std::vector<cd>& g1, std::vector<SvTwo>& two) {
+    if (n_gates < 0 || (n_gates > 0 && !gates)) fail(MPS_ERR_ARG, "gates is NULL");
+    g1.assign(4 * (size_t)n, cd(0));
+    for (int q = 0; q < n; ++q) g1[4 * q] = g1[4 * q + 3] = 1.0;
+    std::vector<int> used(n, 0);
+    two.clear();
+    for (int gi = 0; gi < n_gates; ++gi) {
+        const mps_gate& g = gates[gi];
+        for (int e = 0; e < 32; ++e)
+            if (!std::isfinite(g.m[e])) fail(MPS_ERR_ARG, "gate matrix has a non-finite entry");
+        if (g.q1 < 0) {
+            if (g.q1 != -1 || g.q0 < 0 || g.q0 >= n) fail(MPS_ERR_ARG, "one-qubit gate site out of range");
+            cd u[2][2], cur[2][2], out[2][2];
+            for (int s = 0; s < 2; ++s)
+                for (int t = 0; t < 2; ++t) {
+                    u[s][t] = cd(g.m[2 * (s * 2 + t)], g.m[2 * (s * 2 + t) + 1]);
+                    cur[s][t] = g1[4 * (size_t)g.q0 + s * 2 + t];
+                }
+            mul2(u, cur, out);
+            for (int s = 0; s < 2; ++s)
+                for (int t = 0; t < 2; ++t) g1[4 * (size_t)g.q0 + s * 2 + t] = out[s][t];
+            continue;
+        }
+        if (g.q0 < 0 || g.q0 >= n || g.q1 >= n || g.q0 == g.q1)
+            fail(MPS_ERR_ARG, "two-qubit gate sites out of range or equal");
+        if (used[g.q0] || used[g.q1]) fail(MPS_ERR_ARG, "two-qubit gates of one layer must be disjoint");
+        used[g.q0] = used[g.q1] = 1;
+        SvTwo t;
+        t.q0 = g.q0;
+        t.q1 = g.q1;
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c) t.u[r][c] = cd(g.m[2 * (r * 4 + c)], g.m[2 * (r * 4 + c) + 1]);
+        two.push_back(t);
+    }
+}
+
+// (G_a x G_b)[(s_a s_b), (t_a t_b)] = G_a[s_a][t_a] G_b[s_b][t_b]
+void kron2(const cd* ga, const cd* gb, cd out[4][4]) {
+    for (int sa = 0; sa < 2; ++sa)
+        for (int sb = 0; sb < 2; ++sb)
+            for (int ta = 0; ta < 2; ++ta)
+                for (int tb = 0; tb < 2; ++tb) out[sa * 2 + sb][ta * 2 + tb] = ga[sa * 2 + ta] * gb[sb * 2 + tb];
+}
+
+SvGate2 to_gate2(const cd u[4][4]) {
+    SvGate2 g;
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+            g.re[r * 4 + c] = u[r][c].real();
+            g.im[r * 4 + c] = u[r][c].imag();
+        }
+    return g;
+}
+
+void sv_apply_layer_impl(sv_state* sv, const mps_gate* gates, int n_gates) {
+    const int n = sv->n;
+    std::vector<cd> g1;
+    std::vector<SvTwo> two;
+    parse_sv_layer(n, gates, n_gates, g1, two);
+    std::vector<int> in_two(n, 0);
+    // each two-qubit gate with the one-qubit gates of its qubits folded in: U (G_q0 x G_q1)
+    for (const SvTwo& t : two) {
+        in_two[t.q0] = in_two[t.q1] = 1;
+        cd k[4][4], u[4][4];
+        kron2(&g1[4 * (size_t)t.q0], &g1[4 * (size_t)t.q1], k);
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c) {
+                u[r][c] = 0;
+                for (int m = 0; m < 4; ++m) u[r][c] += t.u[r][m] * k[m][c];
+            }
+        HIPCHK(sv_apply_2q(sv->re, sv->im, n, n - 1 - t.q0, n - 1 - t.q1, to_gate2(u), sv->stream));
+    }
+    // the remaining one-qubit gates, two per pass
+    std::vector<int> lone;
+    for (int q = 0; q < n; ++q) {
+        const cd* g = &g1[4 * (size_t)q];
+        if (!in_two[q] && !(g[0] == cd(1) && g[1] == cd(0) && g[2] == cd(0) && g[3] == cd(1))) lone.push_back(q);
+    }
+    size_t i = 0;
+    for (; i + 1 < lone.size(); i += 2) {
+        cd k[4][4];
+        kron2(&g1[4 * (size_t)lone[i]], &g1[4 * (size_t)lone[i + 1]], k);
+        HIPCHK(sv_apply_2q(sv->re, sv->im, n, n - 1 - lone[i], n - 1 - lone[i + 1], to_gate2(k), sv->stream));
+    }
+    if (i < lone.size()) {
+        SvGate1 g;
+        for (int e = 0; e < 4; ++e) {
+            g.re[e] = g1[4 * (size_t)lone[i] + e].real();
+            g.im[e] = g1[4 * (size_t)lone[i] + e].imag();
+        }
+        HIPCHK(sv_apply_1q(sv->re, sv->im, n, n - 1 - lone[i], g, sv->stream));
+    }
+}
+
+// The MPS as a statevector on the device: contract the sites in chain order,
+// cur (2^k x D_k) * A_k (D_k x 2 D_{k+1}) read as (2^(k+1) x D_{k+1}); then the
+// fixed-order reductions of sv_compare against the exact state.
+void sv_compare_impl(const sv_state* sv, mps_state* st, double* out5) {
+    if (st->n != sv->n) fail(MPS_ERR_ARG, "the MPS and the statevector have different numbers of qubits");
+    const int n = sv->n;
+    HIPCHK(hipStreamSynchronize(sv->stream));
+    const hipStream_t s = st->stream;
+    int64_t need = 1;
+    for (int k = 0; k < n; ++k) need = std::max<int64_t>(need, ((int64_t)1 << k) * 2 * st->bond[k + 1]);
+    if (need > ((int64_t)2 << n)) fail(MPS_ERR_ARG, "MPS bond dimensions exceed the state space");
+    Planar<double> cur, nxt, t;
+    cur.ensure(need, s);
+    nxt.ensure(need, s);
+    HIPCHK(fill_planar<double>(cur.re(), cur.im(), 1, 1.0, s));
+    int64_t rows = 1;
+    constexpr int64_t CH = (int64_t)1 << 24;
+    for (int k = 0; k < n; ++k) {
+        forward_tensor(st, k, t, s);
+        const int64_t Dk = st->bond[k], Dn = st->bond[k + 1];
+        for (int64_t r0 = 0; r0 < rows; r0 += CH) {
+            const int64_t m = std::min(CH, rows - r0);
+            gemm<double>(st, MPS_KCLASS_OTHER, OP_N, OP_N, m, 2 * Dn, Dk, cur.re() + r0 * Dk, cur.im() + r0 * Dk, Dk,
+                         t.re(), t.im(), 2 * Dn, nxt.re() + r0 * 2 * Dn, nxt.im() + r0 * 2 * Dn, 2 * Dn);
+        }
+        rows *= 2;
+        std::swap(cur, nxt);
+    }
+    const int nb = sv_compare_blocks();
+    Raw<double> part;
+    part.ensure((int64_t)nb * 5, s);
+    HIPCHK(sv_compare(cur.re(), cur.im(), sv->re, sv->im, (uint64_t)1 << n, part.p, s));
+    std::vector<double> h((size_t)nb * 5);
+    HIPCHK(hipMemcpyAsync(h.data(), part.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int k = 0; k < 5; ++k) out5[k] = 0;
+    for (int b = 0; b < nb; ++b)
+        for (int k = 0; k < 5; ++k) out5[k] += h[(size_t)b * 5 + k];
+    cur.release(s); nxt.release(s); t.release(s); part.release(s);
+    HIPCHK(hipStreamSynchronize(s));
+    flush_timings(st);
+}
+
+}  // namespace
+
+extern "C" {
+
+mps_status sv_create(int n_qubits, const uint8_t* init_bits, void* hip_stream, sv_state** out) {
+    return run_guarded([&] {
+        if (!out) fail(MPS_ERR_ARG, "out is NULL");
+        *out = nullptr;
+        if (n_qubits < 1 || n_qubits > SV_MAX_QUBITS) fail(MPS_ERR_ARG, "n_qubits must be in [1, 34]");
+        uint64_t one_at = 0;
+        if (init_bits)
+            for (int k = 0; k < n_qubits; ++k) {
+                if (init_bits[k] > 1) fail(MPS_ERR_ARG, "init_bits must be 0 or 1");
+                one_at = (one_at << 1) | init_bits[k];
+            }
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(MPS_ERR_DEVICE, "no HIP device available");
+        const uint64_t dim = (uint64_t)1 << n_qubits;
+        void* p = nullptr;
+        if (hipMalloc(&p, sizeof(double) * 2 * dim) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(MPS_ERR_OOM, "cannot allocate the statevector");
+        }
+        sv_state* sv = new sv_state();
+        sv->n = n_qubits;
+        sv->stream = (hipStream_t)hip_stream;
+        sv->re = (double*)p;
+        sv->im = sv->re + dim;
+        const hipError_t e = sv_fill(sv->re, sv->im, dim, one_at, sv->stream);
+        if (e != hipSuccess || hipStreamSynchronize(sv->stream) != hipSuccess) {
+            (void)hipFree(p);
+            delete sv;
+            fail(MPS_ERR_DEVICE, "statevector initialisation failed");
+        }
+        *out = sv;
+    });
+}
+
+mps_status sv_destroy(sv_state* sv) {
+    return run_guarded([&] {
+        if (!sv) return;
+        (void)hipStreamSynchronize(sv->stream);
+        (void)hipFree(sv->re);
+        delete sv;
+    });
+}
+
+mps_status sv_apply_layer(sv_state* sv, const mps_gate* gates, int n_gates) {
+    return run_guarded([&] {
+        if (!sv) fail(MPS_ERR_ARG, "statevector is NULL");
+        sv_apply_layer_impl(sv, gates, n_gates);
+        HIPCHK(hipStreamSynchronize(sv->stream));
+    });
+}
+
+mps_status sv_amplitudes(const sv_state* sv, int64_t count, const int64_t* indices, double* out) {
+    return run_guarded([&] {
+        if (!sv) fail(MPS_ERR_ARG, "statevector is NULL");
+        if (count < 0 || (count > 0 && (!indices || !out))) fail(MPS_ERR_ARG, "bad amplitude arguments");
+        const int64_t dim = (int64_t)1 << sv->n;
+        for (int64_t t = 0; t < count; ++t)
+            if (indices[t] < 0 || indices[t] >= dim) fail(MPS_ERR_ARG, "index out of range");
+        if (count == 0) return;
+        const hipStream_t s = sv->stream;
+        Raw<int64_t> di;
+        Raw<double> dout;
+        di.ensure(count, s);
+        dout.ensure(2 * count, s);
+        HIPCHK(hipMemcpyAsync(di.p, indices, sizeof(int64_t) * count, hipMemcpyHostToDevice, s));
+        HIPCHK(sv_gather(sv->re, sv->im, di.p, count, dout.p, s));
+        HIPCHK(hipMemcpyAsync(out, dout.p, sizeof(double) * 2 * count, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        di.release(s);
+        dout.release(s);
+        HIPCHK(hipStreamSynchronize(s));
+    });
+}
+
+mps_status sv_compare_mps(const sv_state* sv, mps_state* mps, double* overlap, double* F, double* F_B,
+                          double* norms) {
+    return run_guarded([&] {
+        if (!sv) fail(MPS_ERR_ARG, "statevector is NULL");
+        check_state(mps);
+        double r[5];
+        sv_compare_impl(sv, mps, r);
+        const double dim = std::ldexp(1.0, sv->n);
+        if (overlap) { overlap[0] = r[0]; overlap[1] = r[1]; }
+        if (F) *F = r[0] * r[0] + r[1] * r[1];
+        if (F_B) *F_B = dim * r[2] - 1.0;
+        if (norms) { norms[0] = r[3]; norms[1] = r[4]; }
+    });
+}
+
+}  // extern "C"

@@ -199,4 +199,19 @@ hipError_t cgemm_f64_batched_splitk(int opa, int opb, int M, int N, int K, CView
 hipError_t cgemm_f64_sub(int opa, int opb, int M, int N, int K, CView<double> A, CView<double> B, CViewMut<double> C,
                          hipStream_t stream);
 
+// ---- exact statevector (FP64 planar, chain site q = index bit n-1-q) ----
+struct SvGate2 { double re[16], im[16]; };   // [row * 4 + col], row = 2 s_a + s_b
+struct SvGate1 { double re[4], im[4]; };     // [row * 2 + col]
+hipError_t sv_fill(double* re, double* im, uint64_t dim, uint64_t one_at, hipStream_t s);
+// U on the qubits at index bits pa (high bit of U's row) and pb.
+hipError_t sv_apply_2q(double* re, double* im, int n, int pa, int pb, const SvGate2& g, hipStream_t s);
+hipError_t sv_apply_1q(double* re, double* im, int n, int p, const SvGate1& g, hipStream_t s);
+// out[2t], out[2t+1] = amplitude idx[t] (device arrays).
+hipError_t sv_gather(const double* re, const double* im, const int64_t* idx, int64_t count, double* out,
+                     hipStream_t s);
+// sv_compare_blocks() x 5 partial sums: conj(p) q (re, im), |p|^2 |q|^2, |p|^2, |q|^2.
+int sv_compare_blocks();
+hipError_t sv_compare(const double* pr, const double* pi, const double* qr, const double* qi, uint64_t dim,
+                      double* partials, hipStream_t s);
+
 }  // namespace mpsk

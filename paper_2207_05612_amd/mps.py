@@ -32,7 +32,8 @@ EXPORTS = ("mps_create", "mps_destroy", "apply_layer_dmrg", "apply_layer_dmrg_si
            "mps_last_error",
            "mps_amplitude", "mps_to_statevector", "mps_bond_dims", "mps_get_tensor", "mps_step_log",
            "mps_expect_zz", "mps_set_profiling", "mps_kernel_stats", "mps_kernel_selftest_cgemm",
-           "mps_kernel_selftest_eigh", "mps_overlap", "apply_layers_dmrg")
+           "mps_kernel_selftest_eigh", "mps_overlap", "apply_layers_dmrg",
+           "sv_create", "sv_destroy", "sv_apply_layer", "sv_amplitudes", "sv_compare_mps")
 
 _lib = None
 
@@ -81,6 +82,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mps_kernel_selftest_eigh": (i32, [i32, dp, i32, dp, dp, ip]),
         "mps_overlap": (i32, [P, P, dp, dp]),
         "apply_layers_dmrg": (i32, [P, P, ip, i32, i32, i32, i32, dp]),
+        "sv_create": (i32, [i32, P, P, ctypes.POINTER(P)]),
+        "sv_destroy": (i32, [P]),
+        "sv_apply_layer": (i32, [P, P, i32]),
+        "sv_amplitudes": (i32, [P, i64, P, dp]),
+        "sv_compare_mps": (i32, [P, P, dp, dp, dp, dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -308,3 +314,46 @@ def sample(state: MPS, n_samples: int, seed: int) -> np.ndarray:
 
 def mps_destroy(state: MPS) -> None:
     state.close()
+
+
+class Statevector:
+    """Handle of an exact on-GPU statevector (owns an ``sv_state*``): the perfect state
+    against which an MPS is measured (F of eq:F-sup, F_B of eq:FB-sup)."""
+
+    def __init__(self, n: int, bits: Optional[Sequence[int]] = None, stream: Optional[int] = None):
+        lib = load_library()
+        self.n = n
+        self._h = ctypes.c_void_p()
+        bits_arr = None if bits is None else np.ascontiguousarray(bits, dtype=np.uint8)
+        if stream is None:
+            stream = current_stream()
+        _check(lib.sv_create(n, None if bits_arr is None else bits_arr.ctypes.data, stream, ctypes.byref(self._h)))
+
+    def close(self) -> None:
+        if self._h:
+            _lib.sv_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply_layer(self, layer) -> None:
+        rec = np.ascontiguousarray(layer if isinstance(layer, np.ndarray) else circuits.pack_layer(layer),
+                                   dtype=circuits.GATE_DTYPE)
+        _check(_lib.sv_apply_layer(self._h, rec.ctypes.data if len(rec) else None, len(rec)))
+
+    def amplitudes_at(self, indices) -> np.ndarray:
+        idx = np.ascontiguousarray(indices, dtype=np.int64)
+        out = np.zeros(2 * len(idx))
+        _check(_lib.sv_amplitudes(self._h, len(idx), idx.ctypes.data if len(idx) else None, _dptr(out)))
+        return out[0::2] + 1j * out[1::2]
+
+    def compare(self, state: "MPS") -> dict:
+        """<phi|psi>, F, F_B and both norms of an MPS phi against this exact state psi."""
+        ov, F, FB, nrm = np.zeros(2), ctypes.c_double(), ctypes.c_double(), np.zeros(2)
+        _check(_lib.sv_compare_mps(self._h, state._h, _dptr(ov), ctypes.byref(F), ctypes.byref(FB), _dptr(nrm)))
+        return {"overlap": complex(ov[0], ov[1]), "F": F.value, "F_B": FB.value,
+                "norm_mps": nrm[0], "norm_exact": nrm[1]}
