@@ -319,6 +319,17 @@ mps_status sv_amplitudes(const sv_state* sv, int64_t count, const int64_t* indic
 mps_status sv_compare_mps(const sv_state* sv, mps_state* mps, double* overlap, double* F, double* F_B,
                           double* norms);
 
+/* Squared Schmidt values of the exact state across the cut after `cut` chain
+ * sites (1 <= cut < n_qubits): the best possible MPS with bond chi at that cut
+ * keeps the weight *kept = sum of the chi largest S_mu^2 (Sec. VI, the best
+ * MPS; at the middle cut it gives eps_SVD), *total = sum of all S_mu^2 (the
+ * norm, 1 for a unit state).  s2 (may be NULL) receives all min(2^cut,
+ * 2^(n-cut)) values, largest first.  The smaller side must hold at most 14
+ * qubits (MPS_ERR_ARG otherwise); the values are the eigenvalues of the FP64
+ * Gram matrix of the smaller side (rocSOLVER, values only), so values below
+ * about 1e-15 of the largest are not resolved.  Host outputs. */
+mps_status sv_schmidt_weights(const sv_state* sv, int cut, int chi, double* kept, double* total, double* s2);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2141,6 +2141,60 @@ void sv_compare_impl(const sv_state* sv, mps_state* st, double* out5) {
     flush_timings(st);
 }
 
+// Eigenvalues (ascending) of the Gram matrix of psi split after `cut` sites: the squared
+// Schmidt values of the cut (the best-MPS reference of Sec. VI).  The smaller side sets the
+// order of the Gram matrix (at most SV_MAX_SCHMIDT_DIM); it is formed by the FP64 Gram GEMM
+// and diagonalised by rocSOLVER (values only).
+constexpr int SV_MAX_SCHMIDT_DIM = 16384;
+
+std::vector<double> sv_schmidt_impl(const sv_state* sv, int cut) {
+    const int n = sv->n;
+    if (cut < 1 || cut >= n) fail(MPS_ERR_ARG, "cut must be in [1, n_qubits - 1]");
+    const int64_t rows = (int64_t)1 << cut, cols = (int64_t)1 << (n - cut);
+    const int64_t dim = std::min(rows, cols);
+    if (dim > SV_MAX_SCHMIDT_DIM) fail(MPS_ERR_ARG, "the smaller side of the cut exceeds 14 qubits");
+    mps_state tmp;
+    tmp.stream = sv->stream;
+    if (rocblas_create_handle(&tmp.blas) != rocblas_status_success) fail(MPS_ERR_DEVICE, "rocblas_create_handle failed");
+    rocblas_set_stream(tmp.blas, tmp.stream);
+    const hipStream_t s = tmp.stream;
+    Planar<double> g;
+    Raw<double> z, ev, ework;
+    Raw<int> info;
+    std::vector<double> w(dim);
+    try {
+        g.ensure(dim * dim, s);
+        if (rows <= cols)
+            gram_product<double>(&tmp, OP_N, OP_C, (int)dim, cols, sv->re, sv->im, cols, g.re(), g.im());
+        else
+            gram_product<double>(&tmp, OP_C, OP_N, (int)dim, rows, sv->re, sv->im, cols, g.re(), g.im());
+        z.ensure(2 * dim * dim, s);
+        HIPCHK(pack_hermitian(g.re(), g.im(), (int)dim, z.p, s));
+        g.release(s);
+        ev.ensure(dim, s);
+        ework.ensure(dim, s);
+        info.ensure(1, s);
+        const rocblas_status rs = rocsolver_zheevd(tmp.blas, rocblas_evect_none, rocblas_fill_upper, (int)dim,
+                                                   (rocblas_double_complex*)z.p, (int)dim, ev.p, ework.p, info.p);
+        if (rs != rocblas_status_success) fail(MPS_ERR_DEVICE, "rocsolver_zheevd failed: status " + std::to_string((int)rs));
+        int hinfo = 0;
+        HIPCHK(hipMemcpyAsync(w.data(), ev.p, sizeof(double) * dim, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (hinfo != 0) fail(MPS_ERR_NUMERIC, "eigensolver did not converge");
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        g.release(s); z.release(s); ev.release(s); ework.release(s); info.release(s); tmp.splitws64.release(s);
+        (void)hipStreamSynchronize(s);
+        rocblas_destroy_handle(tmp.blas);
+        throw;
+    }
+    z.release(s); ev.release(s); ework.release(s); info.release(s); tmp.splitws64.release(s);
+    HIPCHK(hipStreamSynchronize(s));
+    rocblas_destroy_handle(tmp.blas);
+    return w;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2231,6 +2285,22 @@ mps_status sv_compare_mps(const sv_state* sv, mps_state* mps, double* overlap, d
         if (F) *F = r[0] * r[0] + r[1] * r[1];
         if (F_B) *F_B = dim * r[2] - 1.0;
         if (norms) { norms[0] = r[3]; norms[1] = r[4]; }
+    });
+}
+
+mps_status sv_schmidt_weights(const sv_state* sv, int cut, int chi, double* kept, double* total, double* s2) {
+    return run_guarded([&] {
+        if (!sv) fail(MPS_ERR_ARG, "statevector is NULL");
+        if (chi < 1) fail(MPS_ERR_ARG, "chi must be >= 1");
+        const std::vector<double> w = sv_schmidt_impl(sv, cut);
+        const int64_t dim = (int64_t)w.size();
+        double sum = 0, top = 0;
+        for (int64_t i = 0; i < dim; ++i) sum += w[i];
+        for (int64_t i = dim - 1; i >= 0 && dim - 1 - i < chi; --i) top += w[i];
+        if (kept) *kept = top;
+        if (total) *total = sum;
+        if (s2)
+            for (int64_t i = 0; i < dim; ++i) s2[i] = w[dim - 1 - i];
     });
 }
 

@@ -33,7 +33,8 @@ EXPORTS = ("mps_create", "mps_destroy", "apply_layer_dmrg", "apply_layer_dmrg_si
            "mps_amplitude", "mps_to_statevector", "mps_bond_dims", "mps_get_tensor", "mps_step_log",
            "mps_expect_zz", "mps_set_profiling", "mps_kernel_stats", "mps_kernel_selftest_cgemm",
            "mps_kernel_selftest_eigh", "mps_overlap", "apply_layers_dmrg",
-           "sv_create", "sv_destroy", "sv_apply_layer", "sv_amplitudes", "sv_compare_mps")
+           "sv_create", "sv_destroy", "sv_apply_layer", "sv_amplitudes", "sv_compare_mps",
+           "sv_schmidt_weights")
 
 _lib = None
 
@@ -87,6 +88,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "sv_apply_layer": (i32, [P, P, i32]),
         "sv_amplitudes": (i32, [P, i64, P, dp]),
         "sv_compare_mps": (i32, [P, P, dp, dp, dp, dp]),
+        "sv_schmidt_weights": (i32, [P, i32, i32, dp, dp, dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -357,3 +359,10 @@ class Statevector:
         _check(_lib.sv_compare_mps(self._h, state._h, _dptr(ov), ctypes.byref(F), ctypes.byref(FB), _dptr(nrm)))
         return {"overlap": complex(ov[0], ov[1]), "F": F.value, "F_B": FB.value,
                 "norm_mps": nrm[0], "norm_exact": nrm[1]}
+
+    def schmidt(self, cut: int, chi: int):
+        """(kept weight of the chi largest S^2, total weight, all S^2 largest first) at `cut`."""
+        dim = 2 ** min(cut, self.n - cut)
+        kept, total, s2 = ctypes.c_double(), ctypes.c_double(), np.zeros(dim)
+        _check(_lib.sv_schmidt_weights(self._h, cut, chi, ctypes.byref(kept), ctypes.byref(total), _dptr(s2)))
+        return kept.value, total.value, s2

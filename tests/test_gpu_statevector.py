@@ -9,6 +9,8 @@
   8-qubit blocks.  Every amplitude is a product of block amplitudes that the oracle
   computes one by one; an exact MPS has F = 1 and 1 + F_B = prod_b (1 + F_B,b).
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -169,3 +171,46 @@ def test_xeb_sample_estimate_matches_exact_value():
     print("F %.4f F~ %.4f sqrt(F) %.4f F_B %.4f estimate %.4f +- %.4f" % (
         r["F"], st.fidelity()["F_tilde"], np.sqrt(r["F"]), r["F_B"], est, sd))
     assert abs(est - r["F_B"]) < 5 * sd
+
+
+@pytest.mark.parametrize("cut", [3, 8, 12])
+def test_schmidt_weights_match_the_svd(cut):
+    """Squared Schmidt values of a 16-qubit state at cuts with the smaller side on either
+    end, against LAPACK's SVD of the oracle's state (1e-13 absolute, unit-norm state), and the
+    best-MPS weights sum_{mu < chi} S_mu^2."""
+    c = circuits.random_circuit(circuits.grid_from_shape(4, 4), 10, seed=8)
+    g = mps.Statevector(c.n)
+    for layer in c.layers:
+        g.apply_layer(layer)
+    want = sv.schmidt_values(sv.run(c), c.n, cut) ** 2
+    for chi in (1, 5, 64):
+        kept, total, s2 = g.schmidt(cut, chi)
+        assert abs(total - 1.0) < 1e-12
+        assert abs(kept - np.sum(want[:chi])) < 1e-12
+    assert np.max(np.abs(s2 - want)) < 1e-13
+    with pytest.raises(mps.MpsError):
+        g.schmidt(0, 4)
+
+
+def test_depth_curve_matches_the_oracle():
+    """analysis.depth_curve (12 qubits, chi = 6) against the same quantities built from the
+    oracle: its MPS, its statevector, LAPACK's Schmidt values and its F / F_B definitions."""
+    from paper_2207_05612_amd import analysis as gan
+    c = circuits.plain_fp64_workload(2)
+    recs = gan.depth_curve(c, chi=6, n_sweeps=2, n_samples=2000, seed=1)
+    st = dmrg.product_state(c.n)
+    psi = sv.zero_state(c.n)
+    for d, (layer, rec) in enumerate(zip(c.layers, recs)):
+        dmrg.apply_layer(st, layer, 6, 2)
+        psi = sv.apply_layer(psi, c.n, layer)
+        phi = dmrg.to_statevector(st)
+        assert rec["depth"] == d + 1
+        assert abs(rec["F"] - analysis.fidelity(phi, psi)) < 1e-9
+        assert abs(rec["F_B"] - analysis.xeb_exact(phi, psi)) < 1e-8
+        assert abs(rec["F_tilde"] - math.exp(st.log_f)) < 1e-9
+        s2 = sv.schmidt_values(psi, c.n, c.n // 2) ** 2
+        assert abs(rec["F_SVD"] - np.sum(s2[:6]) / np.sum(s2)) < 1e-12
+        assert rec["F"] <= rec["F_SVD"] + 1e-12            # no bond-6 MPS beats the best cut
+        assert abs(rec["F_B_estimate"] - rec["F_B"]) < 5 * rec["F_B_estimate_sd"] + 1e-12
+    print("depth F F~ F_B F_SVD:", [(r["depth"], round(r["F"], 4), round(r["F_tilde"], 4), round(r["F_B"], 4),
+                                     round(r["F_SVD"], 4)) for r in recs])
