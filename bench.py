@@ -57,6 +57,8 @@ def parse():
                    help="also time the single-site update (split and FP64) on the same layers (1 = yes)")
     p.add_argument("--samples", type=int, default=65536,
                    help="bitstrings sampled from the final MPS of the timed run (0 = skip)")
+    p.add_argument("--statevector", type=int, default=32,
+                   help="qubits of the exact-statevector leg (a Sycamore-layout circuit; 0 = skip)")
     p.add_argument("--progress", action="store_true", help="print one line per layer to stderr")
     p.add_argument("--calibrate-copy-mib", type=int, default=0,
                    help="fill, then sum, a device buffer of this many MiB (HBM counter calibration)")
@@ -161,6 +163,41 @@ def cpu_baseline(chi: int, sweeps: int, stats_per_layer_flops: float, n_steps_pe
                       "chi=%d, MPO bond 4, random inputs: %.1f s (SVD %.1f s, contraction %.1f GFLOP/s); "
                       "per-layer time extrapolated from %d updates per layer and the GPU run's algorithmic "
                       "contraction flops per layer" % (chi, t3 - t0, t_svd, rate / 1e9, n_steps_per_layer)}
+
+
+def statevector_leg(mps, circuits, torch, n_qubits):
+    """Gate passes of the exact statevector (HBM-bound: every pass reads and writes all 2^n
+    FP64 complex amplitudes) on a Sycamore-layout circuit of n_qubits, timed with HIP events
+    on the stream the kernels run on."""
+    nb = {28: 4, 32: 5, 33: 6}.get(n_qubits)
+    nc = {28: 8, 32: 7, 33: 6}.get(n_qubits)
+    if nb is None:
+        raise SystemExit("--statevector takes 28, 32 or 33")
+    c = circuits.sycamore_circuit(circuits.SycamoreLayout(nb, nc), 8, seed=0, sequence="I")
+    g = mps.Statevector(c.n)
+    g.apply_layer(c.layers[0])                      # warm-up
+    passes = 0
+    for layer in c.layers[1:]:
+        two = [q for g2 in layer if g2[1] >= 0 for q in (g2[0], g2[1])]
+        lone = len({g1[0] for g1 in layer if g1[1] < 0} - set(two))
+        passes += len(two) // 2 + (lone + 1) // 2
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for layer in c.layers[1:]:
+        g.apply_layer(layer)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    g.close()
+    bytes_per_pass = 2.0 * 16.0 * 2.0 ** c.n
+    achieved = bytes_per_pass * passes / (ms * 1e-3) / 1e9
+    return {"n_qubits": c.n, "layers": len(c.layers) - 1, "gate_passes": passes, "ms": ms,
+            "ms_per_pass": ms / passes,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "algorithmic_bytes_per_launch": bytes_per_pass,
+                         "kernel": "sv_2q_kernel (one two-qubit pass over all amplitudes, FP64 planar)"}}
 
 
 def main():
@@ -268,6 +305,8 @@ def main():
                               "value": ss["split"]["value"], "unit": "gate-layers/s",
                               "speedup_vs_fp64_single_site": ss["split"]["value"] / ss["fp64"]["value"],
                               "split": ss["split"], "fp64": ss["fp64"]}
+    if args.statevector:
+        out["statevector"] = statevector_leg(mps, circuits, torch, args.statevector)
     if args.cpu_baseline:
         layer_flops = con["flops"] / args.steps
         out["cpu_baseline"] = cpu_baseline(args.chi, args.sweeps, layer_flops, (c.n - 1) * (1 + args.sweeps))
