@@ -95,34 +95,54 @@ __global__ __launch_bounds__(NT, 1) void cgemm_bf16x3_nt_kernel(SplitArgs g) {
     // staging: a tile plane is rows x 16 k in groups of 4 consecutive k (4 groups per row);
     // A has 1024 groups per plane (threads take groups tid, tid + 512), B has 512 (group tid)
     float4 ar[2], ai[2], br, bi;
+    // rows past M (N) are read from the last valid row and zeroed when staged, so the loads of
+    // full k tiles carry no per-lane condition and stay in flight across the MFMAs
+    bool a_ok[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) a_ok[u] = m0 + ((tid + NT * u) >> 2) < M;
+    const bool b_ok = n0 + (tid >> 2) < N;
 
-    auto ld4 = [&](const float* base, int64_t ld, int row, int rows_valid, int k, bool full_k) -> float4 {
-        if (full_k) {
-            if (row < rows_valid) return *(const float4*)(base + (int64_t)row * ld + k);
-            return make_float4(0.f, 0.f, 0.f, 0.f);
-        }
+    auto ld4_full = [&](const float* base, int64_t ld, int row, int k) -> float4 {
+        const float* p = base + (int64_t)row * ld + k;
+        if (VEC) return *(const float4*)p;
+        return make_float4(p[0], p[1], p[2], p[3]);
+    };
+    auto ld4_tail = [&](const float* base, int64_t ld, int row, int rows_valid, int k) -> float4 {
         float t[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e)
             t[e] = (row < rows_valid && k + e < K) ? base[(int64_t)row * ld + k + e] : 0.f;
         return make_float4(t[0], t[1], t[2], t[3]);
     };
-    auto load = [&](int k0) {
-        const bool full_k = VEC && (k0 + SBK <= K);
+    // a k tile with every k < K
+    auto load_full = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int grp = tid + NT * u;
+            const int row = min(m0 + (grp >> 2), M - 1), k = k0 + (grp & 3) * 4;
+            ar[u] = ld4_full(g.a_re, g.lda, row, k);
+            ai[u] = ld4_full(g.a_im, g.lda, row, k);
+        }
+        const int row = min(n0 + (tid >> 2), N - 1), k = k0 + (tid & 3) * 4;
+        br = ld4_full(g.b_re, g.ldb, row, k);
+        bi = ld4_full(g.b_im, g.ldb, row, k);
+    };
+    // the last, partial k tile
+    auto load_tail = [&](int k0) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int grp = tid + NT * u;
             const int row = grp >> 2, k = k0 + (grp & 3) * 4;
-            ar[u] = ld4(g.a_re, g.lda, m0 + row, M, k, full_k);
-            ai[u] = ld4(g.a_im, g.lda, m0 + row, M, k, full_k);
+            ar[u] = ld4_tail(g.a_re, g.lda, m0 + row, M, k);
+            ai[u] = ld4_tail(g.a_im, g.lda, m0 + row, M, k);
         }
         const int row = tid >> 2, k = k0 + (tid & 3) * 4;
-        br = ld4(g.b_re, g.ldb, n0 + row, N, k, full_k);
-        bi = ld4(g.b_im, g.ldb, n0 + row, N, k, full_k);
+        br = ld4_tail(g.b_re, g.ldb, n0 + row, N, k);
+        bi = ld4_tail(g.b_im, g.ldb, n0 + row, N, k);
     };
     typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
-    auto put = [&](unsigned short* base, int rows, int p, int row, int kq, float4 v) {
-        const float x[4] = {v.x, v.y, v.z, v.w};
+    auto put = [&](unsigned short* base, int rows, int p, int row, int kq, float4 v, bool ok) {
+        const float x[4] = {ok ? v.x : 0.f, ok ? v.y : 0.f, ok ? v.z : 0.f, ok ? v.w : 0.f};
         u16x4 h, m, l;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -142,12 +162,12 @@ __global__ __launch_bounds__(NT, 1) void cgemm_bf16x3_nt_kernel(SplitArgs g) {
         for (int u = 0; u < 2; ++u) {
             const int grp = tid + NT * u;
             const int row = grp >> 2, kq = (grp & 3) * 4;
-            put(As[buf], SBM, 0, row, kq, ar[u]);
-            put(As[buf], SBM, 1, row, kq, ai[u]);
+            put(As[buf], SBM, 0, row, kq, ar[u], a_ok[u]);
+            put(As[buf], SBM, 1, row, kq, ai[u], a_ok[u]);
         }
         const int row = tid >> 2, kq = (tid & 3) * 4;
-        put(Bs[buf], SBN, 0, row, kq, br);
-        put(Bs[buf], SBN, 1, row, kq, bi);
+        put(Bs[buf], SBN, 0, row, kq, br, b_ok);
+        put(Bs[buf], SBN, 1, row, kq, bi, b_ok);
     };
 
     f32x16 acc_re[2][2], acc_im[2][2];
@@ -158,16 +178,9 @@ __global__ __launch_bounds__(NT, 1) void cgemm_bf16x3_nt_kernel(SplitArgs g) {
 #pragma unroll
             for (int v = 0; v < 16; ++v) { acc_re[i][j][v] = 0.f; acc_im[i][j][v] = 0.f; }
 
-    const int nk = (K - kbeg + SBK - 1) / SBK;
-    load(kbeg);
-    store(0);
-    __syncthreads();
-
     const int lrow = lane & 31;
     const int lchunk = lane >> 5;
-    for (int kt = 0; kt < nk; ++kt) {
-        const int buf = kt & 1;
-        if (kt + 1 < nk) load(kbeg + (kt + 1) * SBK);
+    auto compute = [&](int buf) {
         // kept split pairs: (0,0) (0,1) (0,2) (1,0) (1,1) (2,0), grouped by the A split
 #pragma unroll
         for (int sa = 0; sa < 3; ++sa) {
@@ -195,9 +208,33 @@ __global__ __launch_bounds__(NT, 1) void cgemm_bf16x3_nt_kernel(SplitArgs g) {
                 }
             }
         }
-        if (kt + 1 < nk) store(buf ^ 1);
+    };
+
+    // full k tiles first, then at most one partial tile
+    const int nk_full = (K - kbeg) / SBK;
+    const bool tail = (K - kbeg) % SBK != 0;
+    if (nk_full > 0) load_full(kbeg);
+    else load_tail(kbeg);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int kt = 0; kt + 1 < nk_full; ++kt) {
+        load_full(kbeg + (kt + 1) * SBK);
+        __builtin_amdgcn_sched_barrier(0);   // issue the next tile's loads before this tile's MFMAs
+        compute(buf);
+        __builtin_amdgcn_sched_barrier(0);   // and consume them only after the MFMAs
+        store(buf ^ 1);
         __syncthreads();
+        buf ^= 1;
     }
+    if (nk_full > 0 && tail) {
+        load_tail(kbeg + nk_full * SBK);
+        compute(buf);
+        store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+    compute(buf);
 
 #pragma unroll
     for (int i = 0; i < 2; ++i)
