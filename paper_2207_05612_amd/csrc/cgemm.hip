@@ -127,7 +127,6 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
                 const int64_t off = (OPA == OP_N) ? (int64_t)gm_ * g.lda + gk : (int64_t)gk * g.lda + gm_;
                 vr = a_re[off];
                 vi = a_im[off];
-                if (OPA == OP_C) vi = -vi;
             }
             ra_re[i] = vr;
             ra_im[i] = vi;
@@ -144,7 +143,6 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
                 const int64_t off = (OPB == OP_N) ? (int64_t)gk * g.ldb + gn_ : (int64_t)gn_ * g.ldb + gk;
                 vr = b_re[off];
                 vi = b_im[off];
-                if (OPB == OP_C) vi = -vi;
             }
             rb_re[i] = vr;
             rb_im[i] = vi;
@@ -157,8 +155,10 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
             int m, k;
             if (OPA == OP_N) { k = idx % BK; m = idx / BK; }
             else             { m = idx % BM; k = idx / BM; }
+            // conjugation is applied here, after the MFMAs of the current tile, so that
+            // the loads stay in flight until then
             As[buf][0][k][m] = (TAcc)ra_re[i];
-            As[buf][1][k][m] = (TAcc)ra_im[i];
+            As[buf][1][k][m] = OPA == OP_C ? -(TAcc)ra_im[i] : (TAcc)ra_im[i];
         }
 #pragma unroll
         for (int i = 0; i < EB; ++i) {
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
             if (OPB == OP_N) { n = idx % BN; k = idx / BN; }
             else             { k = idx % BK; n = idx / BK; }
             Bs[buf][0][k][n] = (TAcc)rb_re[i];
-            Bs[buf][1][k][n] = (TAcc)rb_im[i];
+            Bs[buf][1][k][n] = OPB == OP_C ? -(TAcc)rb_im[i] : (TAcc)rb_im[i];
         }
     };
 

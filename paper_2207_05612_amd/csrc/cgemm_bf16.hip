@@ -43,20 +43,17 @@ struct SplitArgs {
     int64_t split_stride;   // C offset of split y
 };
 
-// round-to-nearest-even FP32 -> BF16 bits (finite inputs)
-__device__ inline unsigned short bf16_bits(float x) {
-    unsigned int u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
 __device__ inline float bf16_to_float(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
 
+// FP32 -> BF16 bits by the hardware conversion (v_cvt_pk_bf16_f32): round to nearest even
+__device__ inline unsigned short bf16_rne(float x) { return __builtin_bit_cast(unsigned short, (__bf16)x); }
+
 __device__ inline void split3(float x, unsigned short& h, unsigned short& m, unsigned short& l) {
-    h = bf16_bits(x);
+    h = bf16_rne(x);
     const float r1 = x - bf16_to_float(h);
-    m = bf16_bits(r1);
+    m = bf16_rne(r1);
     const float r2 = r1 - bf16_to_float(m);
-    l = bf16_bits(r2);
+    l = bf16_rne(r2);
 }
 
 constexpr int SBM = 256, SBN = 128, SBK = 16;
