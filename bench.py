@@ -57,6 +57,10 @@ def parse():
                    help="also time the single-site update (split and FP64) on the same layers (1 = yes)")
     p.add_argument("--samples", type=int, default=65536,
                    help="bitstrings sampled from the final MPS of the timed run (0 = skip)")
+    p.add_argument("--multilayer-chi", type=int, default=256,
+                   help="chi of the K = 2 layers-per-step leg on the same layers (0 = skip)")
+    p.add_argument("--closed-amplitudes", type=int, default=4,
+                   help="closed-mode amplitudes timed on the 54-qubit circuit at chi = 64 (0 = skip)")
     p.add_argument("--statevector", type=int, default=32,
                    help="qubits of the exact-statevector leg (a Sycamore-layout circuit; 0 = skip)")
     p.add_argument("--progress", action="store_true", help="print one line per layer to stderr")
@@ -163,6 +167,50 @@ def cpu_baseline(chi: int, sweeps: int, stats_per_layer_flops: float, n_steps_pe
                       "chi=%d, MPO bond 4, random inputs: %.1f s (SVD %.1f s, contraction %.1f GFLOP/s); "
                       "per-layer time extrapolated from %d updates per layer and the GPU run's algorithmic "
                       "contraction flops per layer" % (chi, t3 - t0, t_svd, rate / 1e9, n_steps_per_layer)}
+
+
+def multilayer_leg(mps, circuit, precision, chi, sweeps, warmup, steps, torch):
+    """The timed layers applied two per compression step (one MPO over both layers) against the
+    same layers one per step, both from the same warmed-up state, at a chi where K = 2 fits."""
+    out = {"chi": chi, "layers": steps}
+    for K in (1, 2):
+        st = mps.MPS(circuit.n, None, max_chi=chi, precision=precision)
+        for d in range(warmup):
+            st.apply_layer_dmrg(circuit.layers[d], chi, sweeps)
+        torch.cuda.synchronize()
+        st.set_profiling(True)
+        t0 = time.perf_counter()
+        fs = [st.apply_layers_dmrg(circuit.layers[d:d + K], chi, sweeps)
+              for d in range(warmup, warmup + steps, K)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        con = st.kernel_stats("contract")
+        out["K%d" % K] = {"gate_layers_per_s": steps / dt, "f_steps": fs, "F_tilde": st.fidelity()["F_tilde"],
+                          "contraction_tflops": con["flops"] / (con["ms"] * 1e-3) / 1e12 if con["ms"] > 0 else 0.0}
+        st.close()
+    return out
+
+
+def closed_leg(circuits, torch, n_amp):
+    """Closed-mode amplitudes <x|U|0> of the 54-qubit circuit at chi = 64 (cut after layer 10,
+    forward MPS built once, one backward MPS per bitstring), split precision."""
+    import numpy as np
+    from paper_2207_05612_amd import closed, mps
+    c = circuits.sycamore_like_54_workload(0, depth=20)
+    t0 = time.perf_counter()
+    amps = closed.ClosedAmplitudes(c, chi=64, n_sweeps=1, d1=10, precision=mps.MPS_BF16X3)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    bits = np.random.default_rng(5).integers(0, 2, size=(n_amp, c.n)).astype(np.uint8)
+    t0 = time.perf_counter()
+    vals = [amps(b) for b in bits]
+    torch.cuda.synchronize()
+    t_amp = time.perf_counter() - t0
+    f_fwd = amps.fwd.fidelity()["F_tilde"]
+    amps.close()
+    return {"chi": 64, "d1": 10, "amplitudes": n_amp, "forward_s": t_fwd, "amplitudes_per_s": n_amp / t_amp,
+            "F_tilde_forward": f_fwd, "F_tilde_backward": [float(np.exp(x)) for x in amps.log_f_backward],
+            "abs_amplitudes": [abs(v) for v in vals]}
 
 
 def statevector_leg(mps, circuits, torch, n_qubits):
@@ -305,6 +353,11 @@ def main():
                               "value": ss["split"]["value"], "unit": "gate-layers/s",
                               "speedup_vs_fp64_single_site": ss["split"]["value"] / ss["fp64"]["value"],
                               "split": ss["split"], "fp64": ss["fp64"]}
+    if args.multilayer_chi:
+        out["multilayer"] = multilayer_leg(mps, c, prec, args.multilayer_chi, args.sweeps, args.warmup, args.steps,
+                                           torch)
+    if args.closed_amplitudes:
+        out["closed"] = closed_leg(circuits, torch, args.closed_amplitudes)
     if args.statevector:
         out["statevector"] = statevector_leg(mps, circuits, torch, args.statevector)
     if args.cpu_baseline:
