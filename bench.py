@@ -311,6 +311,8 @@ def main():
         "contraction_tflops": achieved,
         "all_kernels_algorithmic_tflops": total_flops / dt / 1e12,
         "time_split_ms": {k: round(v["ms"], 1) for k, v in stats.items()},
+        "class_algorithmic_tflops": {k: round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2)
+                                     for k, v in stats.items() if v["ms"] > 0 and v["flops"] > 0},
         "f_delta": fs,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,

@@ -340,6 +340,15 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrArgs g) {
         bool ok = true;
         if (tid < P) ok = wait_geq(g.wg_flag + tid, i + 1, g.abort_flag);
         if (__syncthreads_or(!ok)) return;
+        // every published value of this step is complete now: issue the loads of y and of
+        // the partial y^H v together, so that their latencies overlap
+        double2 yq[TQ];
+#pragma unroll
+        for (int q = 0; q < TQ; ++q) {
+            const int r = tid + TT * q;
+            yq[q] = (r >= i + 1 && r < n) ? ld_coh(&g.ybuf[(int64_t)buf * n + r]) : make_double2(0.0, 0.0);
+        }
+        const double2 y1 = ld_coh(&g.ybuf[(int64_t)buf * n + i + 1]);
         double pdr = tid < P ? ld_coh(&g.pdot[(int64_t)buf * P + tid]).x : 0.0;
         pdr = wave_sum(pdr);
         if (lane == 0) red[wave][0] = pdr;
@@ -358,7 +367,7 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrArgs g) {
             const int r = tid + TT * q;
             w[q] = make_double2(0.0, 0.0);
             if (r >= i + 1 && r < n) {
-                const double2 ty = cmul(tau, ld_coh(&g.ybuf[(int64_t)buf * n + r]));
+                const double2 ty = cmul(tau, yq[q]);
                 w[q] = make_double2(ty.x + alw * v[q].x, ty.y + alw * v[q].y);
             }
         }
@@ -367,7 +376,7 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrArgs g) {
             wcol[tid] = make_double2(ty.x + alw * vcol[tid].x, ty.y + alw * vcol[tid].y);
         }
         // w at row i+1 (v there is 1): the scalar of the next column's update
-        const double2 ty1 = cmul(tau, ld_coh(&g.ybuf[(int64_t)buf * n + i + 1]));
+        const double2 ty1 = cmul(tau, y1);
         const double2 w1 = make_double2(ty1.x + alw, ty1.y);
         __syncthreads();   // wcol visible to every wave before the update
         // ---- rank-2 update of the owned columns; column i+2 first, then published
@@ -391,7 +400,8 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrArgs g) {
             if (j == j2 || c < i + 1 || c >= n) continue;
             UPDATE_COL(j);
         }
-        // ---- next column: x_{i+1} = A[:, i+1] (after step i-1) - v conj(w_{i+1}) - w
+        // ---- next column: x_{i+1} = A[:, i+1] (after step i-1, loaded into x above)
+        //      - v conj(w_{i+1}) - w
         {
             const double2* src = g.colbuf + (int64_t)((i + 1) & 1) * n;
 #pragma unroll
