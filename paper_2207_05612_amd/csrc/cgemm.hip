@@ -17,6 +17,8 @@
 // groups of 8 tile rows so that neighbouring tiles share operand panels in L2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace mpsk {
@@ -60,7 +62,9 @@ struct GemmArgs {
     int64_t lda, ldb, ldc;
     int M, N, K;
     int gm, gn;
-    int lower_only;   // skip tiles that hold no element with column <= row
+    int lower_only;   // only the tiles that hold an element with column <= row: blockIdx.x
+                      // enumerates them row by row (n_active of them)
+    int n_active;
     int kchunk;       // k range of split blockIdx.y: [y kchunk, (y+1) kchunk)
     int64_t split_stride;   // C offset of split y (partial sums); 0 without split
     int64_t sa, sb, sc;     // batch strides (elements) of A, B, C: batch z = blockIdx.z
@@ -87,18 +91,32 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs<TIn, TAcc> g) {
     const int wm0 = (wave >> 1) * WM;
     const int wn0 = (wave & 1) * WN;
 
-    // ---- tile mapping: XCD-contiguous, then grouped rows
+    // ---- tile mapping: XCD-contiguous, then grouped rows (or, for lower-triangle
+    //      products, the active tiles row by row, so that every XCD gets the same count)
     int pid = blockIdx.x;
-    const int nb = g.gm * g.gn;
+    const int nb = g.lower_only ? g.n_active : g.gm * g.gn;
     if ((nb & 7) == 0) pid = (pid & 7) * (nb >> 3) + (pid >> 3);
-    constexpr int GROUP = 8;
-    const int group = pid / (GROUP * g.gn);
-    const int first_m = group * GROUP;
-    const int gsz = min(g.gm - first_m, GROUP);
-    const int tm = first_m + (pid % gsz);
-    const int tn = (pid % (GROUP * g.gn)) / gsz;
+    int tm, tn;
+    if (g.lower_only) {
+        int r = 0, rem = pid;
+        for (;;) {
+            const int cnt = min(g.gn, (BM * r + BM - 1) / BN + 1);
+            if (rem < cnt || r + 1 >= g.gm) break;
+            rem -= cnt;
+            ++r;
+        }
+        tm = r;
+        tn = rem;
+    } else {
+        constexpr int GROUP = 8;
+        const int group = pid / (GROUP * g.gn);
+        const int first_m = group * GROUP;
+        const int gsz = min(g.gm - first_m, GROUP);
+        tm = first_m + (pid % gsz);
+        tn = (pid % (GROUP * g.gn)) / gsz;
+    }
     const int m0 = tm * BM, n0 = tn * BN;
-    if (g.lower_only && n0 > m0 + BM - 1) return;   // whole tile above the diagonal (uniform per block)
+    if (g.lower_only && (n0 > m0 + BM - 1 || tn >= g.gn)) return;   // not an active tile (uniform per block)
 
     const int M = g.M, N = g.N;
     // split-K: this block sums k in [kbeg, K) of its own chunk
@@ -260,6 +278,9 @@ static hipError_t launch(int opa, int opb, int M, int N, int K, CView<TIn> A, CV
     g.gm = (M + BM - 1) / BM;
     g.gn = (N + BN - 1) / BN;
     g.lower_only = lower_only;
+    g.n_active = 0;
+    if (lower_only)
+        for (int r = 0; r < g.gm; ++r) g.n_active += std::min(g.gn, (BM * r + BM - 1) / BN + 1);
     g.sa = sa;
     g.sb = sb;
     g.sc = sc;
@@ -270,8 +291,8 @@ static hipError_t launch(int opa, int opb, int M, int N, int K, CView<TIn> A, CV
     ksplit = (K + g.kchunk - 1) / g.kchunk;
     if (ksplit < 1) ksplit = 1;
     g.split_stride = ksplit > 1 ? split_stride : 0;
-    const int64_t nblocks = (int64_t)g.gm * g.gn;
-    if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
+    const int64_t nblocks = lower_only ? (int64_t)g.n_active : (int64_t)g.gm * g.gn;
+    if ((int64_t)g.gm * g.gn > 0x7fffffff) return hipErrorInvalidValue;
     dim3 grid((unsigned)nblocks, (unsigned)ksplit, (unsigned)batch), block(256);
 #define MPS_GEMM_CASE(OA, OB)                                                                     \
     if (opa == OA && opb == OB) {                                                                 \
