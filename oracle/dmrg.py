@@ -225,6 +225,11 @@ def product_state(n: int, bits: Optional[Sequence[int]] = None) -> OracleMPS:
 
 
 # ------------------------------------------------------------ truncation ---
+def chi_at(chi, bond: int) -> int:
+    """The cap of a bond: chi itself, or entry `bond` of a per-bond sequence."""
+    return int(chi) if np.isscalar(chi) else int(chi[bond])
+
+
 def truncated_svd(m: np.ndarray, chi: int):
     """SVD keeping chi' = min(chi, #{S_i^2 > EPS_TRUNC * sum S^2}) values (Sec. VI.A)."""
     u, s, vh = np.linalg.svd(m, full_matrices=False)
@@ -277,7 +282,7 @@ def zipup_left_to_right(a, w, chi, envs, log):
     for k in range(n - 1):
         t = _ein("pba,atx,bstc->pscx", c, a[k], w[k])
         cl, _, wk, dk = t.shape
-        u, s, vh, total = truncated_svd(t.reshape(cl * 2, wk * dk), chi)
+        u, s, vh, total = truncated_svd(t.reshape(cl * 2, wk * dk), chi_at(chi, k + 1))
         b[k] = u.reshape(cl, 2, len(s))
         c = (s[:, None] * vh).reshape(len(s), wk, dk)
         envs[k + 1] = c
@@ -298,7 +303,7 @@ def zipup_right_to_left(a, w, chi, envs, log):
     for k in range(n - 1, 0, -1):
         t = _ein("qez,ytz,bste->ybsq", c, a[k], w[k])
         dk, wk, _, cr = t.shape
-        u, s, vh, total = truncated_svd(t.reshape(dk * wk, 2 * cr), chi)
+        u, s, vh, total = truncated_svd(t.reshape(dk * wk, 2 * cr), chi_at(chi, k))
         b[k] = vh.reshape(len(s), 2, cr)
         c = (u * s[None, :]).reshape(dk, wk, len(s)).transpose(2, 1, 0)
         envs[k] = c
@@ -319,7 +324,7 @@ def sweep_left_to_right(a, w, b, chi, envs, log):
     for k in range(n - 1):
         th = two_site_tensor(envs[k], a[k], w[k], a[k + 1], w[k + 1], envs[k + 2])
         cl, _, _, cr = th.shape
-        u, s, vh, total = truncated_svd(th.reshape(cl * 2, 2 * cr), chi)
+        u, s, vh, total = truncated_svd(th.reshape(cl * 2, 2 * cr), chi_at(chi, k + 1))
         f = float(np.sum(s ** 2))
         b[k] = u.reshape(cl, 2, len(s))
         b[k + 1] = (s[:, None] * vh / math.sqrt(f)).reshape(len(s), 2, cr)
@@ -335,7 +340,7 @@ def sweep_right_to_left(a, w, b, chi, envs, log):
     for k in range(n - 2, -1, -1):
         th = two_site_tensor(envs[k], a[k], w[k], a[k + 1], w[k + 1], envs[k + 2])
         cl, _, _, cr = th.shape
-        u, s, vh, total = truncated_svd(th.reshape(cl * 2, 2 * cr), chi)
+        u, s, vh, total = truncated_svd(th.reshape(cl * 2, 2 * cr), chi_at(chi, k + 1))
         f = float(np.sum(s ** 2))
         b[k + 1] = vh.reshape(len(s), 2, cr)
         b[k] = (u * (s / math.sqrt(f))[None, :]).reshape(cl, 2, len(s))
@@ -407,9 +412,18 @@ def apply_layer(state: OracleMPS, layer, chi: int, n_sweeps: int, update: str = 
 
 def apply_layers(state: OracleMPS, layers, chi: int, n_sweeps: int, update: str = "two-site") -> float:
     """One compression step over K consecutive layers: fit a bond-chi MPS to
-    U_K ... U_1 |psi> with the MPO of step_mpo; return f_delta (one f for the K layers)."""
-    if chi < 1 or n_sweeps < 0:
-        raise ValueError("chi >= 1 and n_sweeps >= 0 required")
+    U_K ... U_1 |psi> with the MPO of step_mpo; return f_delta (one f for the K layers).
+
+    chi is one cap for every bond or a sequence of n + 1 caps, entry c for the bond
+    between sites c - 1 and c (a grouping of the qubits into tensors leaves the bonds
+    inside a group uncapped)."""
+    if np.isscalar(chi):
+        if chi < 1:
+            raise ValueError("chi >= 1 required")
+    elif len(chi) != state.n + 1 or min(list(chi)[1:state.n] or [1]) < 1:
+        raise ValueError("a per-bond chi needs n + 1 entries >= 1")
+    if n_sweeps < 0:
+        raise ValueError("n_sweeps >= 0 required")
     if update not in ("two-site", "single-site"):
         raise ValueError("update must be 'two-site' or 'single-site'")
     layers = list(layers)

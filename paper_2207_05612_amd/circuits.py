@@ -250,6 +250,30 @@ class SycamoreLayout:
         return sorted(pairs)
 
 
+def group_bond_profile(group_sizes: Sequence[int], chi: int) -> List[int]:
+    """Per-bond caps of a grouping of consecutive chain sites into tensors (Sec. IV.A with
+    r_tau > 1): chi on the bonds between groups, and on a bond inside a group the largest
+    Schmidt rank any state can have there, 2^min(c, n - c), so that nothing inside a group is
+    truncated.  Entry c is the bond between sites c - 1 and c (n + 1 entries)."""
+    n = int(sum(group_sizes))
+    if min(group_sizes) < 1:
+        raise ValueError("groups must be non-empty")
+    cuts = set(np.cumsum(group_sizes)[:-1].tolist())
+    return [1] + [chi if c in cuts else 2 ** min(c, n - c) for c in range(1, n)] + [1]
+
+
+def sycamore_column_groups(layout: "SycamoreLayout", columns: Sequence[int]) -> List[int]:
+    """Group sizes (in chain order) of a vertical grouping of the Sycamore layout: group g
+    holds columns[g] consecutive columns (the V groupings of Sec. V.C)."""
+    if sum(columns) != layout.n_c:
+        raise ValueError("the groups must cover every column")
+    sizes, c = [], 0
+    for k in columns:
+        sizes.append(sum(layout.column_len(c + i) for i in range(k)))
+        c += k
+    return sizes
+
+
 # Sequence I is the supremacy pattern ABCD-CDAB; Sequence II is the same pattern turned by a
 # quarter (CDBA-BACD).
 SEQUENCE_I = "ABCDCDAB"

@@ -656,3 +656,38 @@ def test_xeb_estimator_converges_to_the_exact_value():
     est = analysis.xeb_estimate(np.abs(p[xs]) ** 2, 10)
     sd = np.std(1024 * np.abs(p[xs]) ** 2) / math.sqrt(len(xs))
     assert abs(est - exact) < 4 * sd, (est, exact, sd)
+
+
+# ------------------------------------------------------- qubit groupings ---
+def test_constant_bond_profile_is_a_single_chi():
+    """A per-bond cap equal to chi everywhere is the single-chi step."""
+    c = circuits.plain_fp64_workload(1)
+    a, b = dmrg.product_state(c.n), dmrg.product_state(c.n)
+    for layer in c.layers:
+        fa = dmrg.apply_layer(a, layer, 5, 2)
+        fb = dmrg.apply_layers(b, [layer], [1] + [5] * (c.n - 1) + [1], 2)
+        assert fa == fb
+    assert np.array_equal(dmrg.to_statevector(a), dmrg.to_statevector(b))
+
+
+@pytest.mark.parametrize("columns,trivial", [([2, 2], "AC"), ([1, 2, 1], "BD")])
+def test_layers_inside_groups_are_trivial(columns, trivial):
+    """Sec. V.C: with qubits grouped by columns, a layer whose couplers stay inside the groups
+    has f_delta = 1 for any chi (here chi = 2 between groups) and reproduces the exact image of
+    the layer; the other layers keep the bonds between groups at chi or below."""
+    lay = circuits.SycamoreLayout(3, 4)
+    sizes = circuits.sycamore_column_groups(lay, columns)
+    prof = circuits.group_bond_profile(sizes, 2)
+    cuts = np.cumsum(sizes)[:-1]
+    c = circuits.sycamore_circuit(lay, 8, seed=3, sequence="I")
+    st = dmrg.product_state(c.n)
+    for d, layer in enumerate(c.layers):
+        before = dmrg.to_statevector(st)
+        f = dmrg.apply_layers(st, [layer], prof, 2)
+        letter = circuits.SEQUENCE_I[d % 8]
+        if letter in trivial:
+            target = sv.apply_layer(before, c.n, layer)
+            assert abs(f - 1.0) < 1e-12, (d, letter, f)
+            assert abs(abs(np.vdot(dmrg.to_statevector(st), target)) - 1.0) < 1e-12
+        assert all(st.bond_dims()[k] <= 2 for k in cuts)
+    assert min(st.layer_f) < 0.99        # the crossing layers do truncate at chi = 2
