@@ -147,6 +147,22 @@ typedef enum {
 mps_status apply_layers_dmrg(mps_state* state, const mps_gate* gates, const int* n_gates,
                              int n_layers, int chi, int n_sweeps, int update, double* f_step);
 
+/* apply_layers_dmrg with a cap per bond instead of one chi: every truncation
+ * of bond c (between sites c-1 and c) keeps
+ * min(chi_bond[c], #{S_i^2 > 1e-12 sum_j S_j^2}) values.  A grouping of the
+ * qubits into tensors (Sec. IV.A with r_tau > 1, Sec. V.C) is the profile
+ * that caps the bonds between groups at chi and leaves the bonds inside a
+ * group uncapped: an MPS of grouped tensors with bond chi is an MPS of single
+ * qubits with exactly those bond limits, and a layer whose gates stay inside
+ * the groups is applied with f_delta = 1 at any chi.
+ *   chi_bond  n_sites + 1 host ints; entries 1 .. n_sites - 1 must be in
+ *             [1, max_chi] (the two end bonds are 1 and their entries are
+ *             ignored).
+ * Other arguments, ownership and errors as for apply_layers_dmrg. */
+mps_status apply_layers_dmrg_bonds(mps_state* state, const mps_gate* gates, const int* n_gates,
+                                   int n_layers, const int* chi_bond, int n_sweeps, int update,
+                                   double* f_step);
+
 /* Apply one layer to each of `batch` independent states (the compression
  * step above, per instance), concurrently: instances are driven by up to 8
  * host threads and run on their own streams, so give every state its own

@@ -861,7 +861,11 @@ struct Engine {
     Raw<int> QI;
     std::vector<double> hvals;
 
+    std::vector<int> chi_bond;        // per-bond caps (n + 1 entries); empty: chi everywhere
+
     Engine(mps_state* state, int chi_) : st(state), s(state->stream), n(state->n), chi(chi_) {}
+
+    int chi_at(int b) const { return chi_bond.empty() ? chi : chi_bond[b]; }
 
     ~Engine() {
         if (st->stream2) (void)hipStreamSynchronize(st->stream2);   // right blocks in flight
@@ -914,7 +918,8 @@ struct Engine {
     // row-major).  On return U64 holds U (rows x k).  When want_right is set,
     // V64 holds the right factor S V^H / sqrt(f) (k x cols).
     Trunc truncate(const R* m_re, const R* m_im, int64_t rows, int64_t cols, bool want_right,
-                   const double* m64_re, const double* m64_im) {
+                   const double* m64_re, const double* m64_im, int bond) {
+        const int chi = chi_at(bond);
         if (rows <= cols) {
             const int dim = (int)rows;
             GR.ensure((int64_t)dim * dim, s);
@@ -1175,7 +1180,7 @@ struct Engine {
                 log_step(f0, f0, (int)cL);
                 break;
             }
-            Trunc tr = truncate(T2.re(), T2.im(), 2 * cL, wM * DM, false, nullptr, nullptr);
+            Trunc tr = truncate(T2.re(), T2.im(), 2 * cL, wM * DM, false, nullptr, nullptr, bM);
             finish_left(o, j, tr, true);
         }
         return f0;
@@ -1237,7 +1242,7 @@ struct Engine {
             };
             after_reduce = &queue_right;
             HIPCHK((convert_planar<R, double>(TH.re(), TH.im(), rows * cols, TH64.re(), TH64.im(), s)));
-            Trunc tr = truncate(TH.re(), TH.im(), rows, cols, last, TH64.re(), TH64.im());
+            Trunc tr = truncate(TH.re(), TH.im(), rows, cols, last, TH64.re(), TH64.im(), bM);
             after_reduce = nullptr;
             queue_right();          // no-op when the truncation already queued it
             f = tr.f;
@@ -1366,8 +1371,15 @@ void check_state(const mps_state* st) {
 
 // One compression step over n_layers consecutive layers (n_gates[l] records each).
 void apply_step_impl(mps_state* st, const mps_gate* gates, const int* n_gates, int n_layers, int chi, int n_sweeps,
-                     double* f_layer, bool single_site) {
+                     double* f_layer, bool single_site, const int* chi_bond = nullptr) {
     check_state(st);
+    if (chi_bond) {
+        chi = 1;
+        for (int c = 1; c < st->n; ++c) {
+            if (chi_bond[c] < 1 || chi_bond[c] > st->max_chi) fail(MPS_ERR_ARG, "chi_bond entries must be in [1, max_chi]");
+            chi = std::max(chi, chi_bond[c]);
+        }
+    }
     if (n_layers < 1 || n_layers > 64) fail(MPS_ERR_ARG, "n_layers must be in [1, 64]");
     if (!n_gates) fail(MPS_ERR_ARG, "n_gates is NULL");
     int64_t total = 0;
@@ -1387,10 +1399,12 @@ void apply_step_impl(mps_state* st, const mps_gate* gates, const int* n_gates, i
             Engine<float> e(st, chi);
             e.split = st->prec == MPS_BF16X3;
             e.single_site = single_site;
+            if (chi_bond) e.chi_bond.assign(chi_bond, chi_bond + st->n + 1);
             f = e.run(gates, n_gates, n_layers, n_sweeps);
         } else {
             Engine<double> e(st, chi);
             e.single_site = single_site;
+            if (chi_bond) e.chi_bond.assign(chi_bond, chi_bond + st->n + 1);
             f = e.run(gates, n_gates, n_layers, n_sweeps);
         }
         HIPCHK(hipStreamSynchronize(st->stream));
@@ -1508,6 +1522,15 @@ mps_status apply_layers_dmrg(mps_state* st, const mps_gate* gates, const int* n_
     return run_guarded([&] {
         if (update != MPS_UPDATE_TWO_SITE && update != MPS_UPDATE_SINGLE_SITE) fail(MPS_ERR_ARG, "unknown update rule");
         apply_step_impl(st, gates, n_gates, n_layers, chi, n_sweeps, f_step, update == MPS_UPDATE_SINGLE_SITE);
+    });
+}
+
+mps_status apply_layers_dmrg_bonds(mps_state* st, const mps_gate* gates, const int* n_gates, int n_layers,
+                                   const int* chi_bond, int n_sweeps, int update, double* f_step) {
+    return run_guarded([&] {
+        if (update != MPS_UPDATE_TWO_SITE && update != MPS_UPDATE_SINGLE_SITE) fail(MPS_ERR_ARG, "unknown update rule");
+        if (!chi_bond) fail(MPS_ERR_ARG, "chi_bond is NULL");
+        apply_step_impl(st, gates, n_gates, n_layers, 1, n_sweeps, f_step, update == MPS_UPDATE_SINGLE_SITE, chi_bond);
     });
 }
 

@@ -34,7 +34,7 @@ EXPORTS = ("mps_create", "mps_destroy", "apply_layer_dmrg", "apply_layer_dmrg_si
            "mps_expect_zz", "mps_set_profiling", "mps_kernel_stats", "mps_kernel_selftest_cgemm",
            "mps_kernel_selftest_eigh", "mps_overlap", "apply_layers_dmrg",
            "sv_create", "sv_destroy", "sv_apply_layer", "sv_amplitudes", "sv_compare_mps",
-           "sv_schmidt_weights")
+           "sv_schmidt_weights", "apply_layers_dmrg_bonds")
 
 _lib = None
 
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "sv_amplitudes": (i32, [P, i64, P, dp]),
         "sv_compare_mps": (i32, [P, P, dp, dp, dp, dp]),
         "sv_schmidt_weights": (i32, [P, i32, i32, dp, dp, dp]),
+        "apply_layers_dmrg_bonds": (i32, [P, P, ip, i32, ip, i32, i32, dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -162,8 +163,11 @@ class MPS:
         _check(fn(self._h, rec.ctypes.data, len(rec), chi, n_sweeps, ctypes.byref(f)))
         return f.value
 
-    def apply_layers_dmrg(self, layers, chi: int, n_sweeps: int, update: str = "two-site") -> float:
-        """One compression step over K = len(layers) consecutive layers (apply_layers_dmrg)."""
+    def apply_layers_dmrg(self, layers, chi, n_sweeps: int, update: str = "two-site") -> float:
+        """One compression step over K = len(layers) consecutive layers (apply_layers_dmrg).
+
+        chi is one cap for every bond, or n + 1 per-bond caps (apply_layers_dmrg_bonds; see
+        circuits.group_bond_profile for qubit groupings)."""
         if update not in _UPDATES:
             raise ValueError("update must be 'two-site' or 'single-site'")
         recs = [np.ascontiguousarray(l if isinstance(l, np.ndarray) else circuits.pack_layer(l),
@@ -172,8 +176,16 @@ class MPS:
         allrec = np.ascontiguousarray(np.concatenate(recs) if recs else np.zeros(0, circuits.GATE_DTYPE),
                                       dtype=circuits.GATE_DTYPE)
         f = ctypes.c_double(0.0)
-        _check(_lib.apply_layers_dmrg(self._h, allrec.ctypes.data if len(allrec) else None, _iptr(counts),
-                                      len(recs), chi, n_sweeps, _UPDATES[update], ctypes.byref(f)))
+        gp = allrec.ctypes.data if len(allrec) else None
+        if np.isscalar(chi):
+            _check(_lib.apply_layers_dmrg(self._h, gp, _iptr(counts), len(recs), int(chi), n_sweeps,
+                                          _UPDATES[update], ctypes.byref(f)))
+        else:
+            caps = np.ascontiguousarray(chi, dtype=np.int32)
+            if caps.shape != (self.n + 1,):
+                raise ValueError("a per-bond chi needs n + 1 entries")
+            _check(_lib.apply_layers_dmrg_bonds(self._h, gp, _iptr(counts), len(recs), _iptr(caps), n_sweeps,
+                                                _UPDATES[update], ctypes.byref(f)))
         return f.value
 
     def fidelity(self):
