@@ -37,18 +37,22 @@ def error_rate(fid: float, n_2q: int) -> float:
 
 def depth_curve(circuit, chi: int, n_sweeps: int = 1, layers_per_step: int = 1,
                 precision: int = mps.MPS_FP64, update: str = "two-site", n_samples: int = 0,
-                seed: int = 0, schmidt: bool = True, max_depth: Optional[int] = None) -> List[Dict]:
-    """One record per compression step (K = layers_per_step layers each)."""
+                seed: int = 0, schmidt: bool = True, max_depth: Optional[int] = None,
+                bond_caps: Optional[List[int]] = None) -> List[Dict]:
+    """One record per compression step (K = layers_per_step layers each).  bond_caps (n + 1
+    per-bond caps, e.g. circuits.group_bond_profile for a grouping with chi between groups)
+    replaces the single chi in the truncations."""
     n = circuit.n
     layers = circuit.layers if max_depth is None else circuit.layers[:max_depth]
-    st = mps.MPS(n, None, max_chi=chi, precision=precision)
+    caps = chi if bond_caps is None else list(bond_caps)
+    st = mps.MPS(n, None, max_chi=chi if bond_caps is None else max(bond_caps), precision=precision)
     ex = mps.Statevector(n)
     out: List[Dict] = []
     n_2q = 0
     try:
         for d in range(0, len(layers), layers_per_step):
             step = layers[d:d + layers_per_step]
-            f = st.apply_layers_dmrg(step, chi, n_sweeps, update=update)
+            f = st.apply_layers_dmrg(step, caps, n_sweeps, update=update)
             for layer in step:
                 ex.apply_layer(layer)
                 n_2q += sum(1 for g in layer if g[1] >= 0)
