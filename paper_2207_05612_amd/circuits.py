@@ -274,6 +274,34 @@ def sycamore_column_groups(layout: "SycamoreLayout", columns: Sequence[int]) -> 
     return sizes
 
 
+def sycamore_row_groups(layout: "SycamoreLayout", offset: int = 0):
+    """A horizontal grouping of the Sycamore layout (the H groupings of Sec. V.C): qubits grouped
+    by pairs of heights {2m + offset, 2m + 1 + offset} (offset 0 or 1; a lone height at an
+    edge forms its own group).  Returns (order, sizes): order lists the column-major chain
+    sites in the new chain order (group by group, each group by column then height), sizes the
+    group sizes in that order."""
+    if offset not in (0, 1):
+        raise ValueError("offset must be 0 or 1")
+    groups = {}
+    for c, y in layout.coords():
+        groups.setdefault((y + offset) // 2, []).append((c, y))
+    order, sizes = [], []
+    for key in sorted(groups):
+        members = sorted(groups[key])
+        order += [layout.site(c, y) for c, y in members]
+        sizes.append(len(members))
+    return order, sizes
+
+
+def relabel_circuit(circuit: Circuit, order: Sequence[int]) -> Circuit:
+    """The same circuit on a new chain: site order[k] of the old chain becomes site k."""
+    pos = {old: new for new, old in enumerate(order)}
+    if sorted(pos) != list(range(circuit.n)):
+        raise ValueError("order must be a permutation of the chain sites")
+    layers = [[(pos[q0], pos[q1] if q1 >= 0 else -1, u) for q0, q1, u in layer] for layer in circuit.layers]
+    return Circuit(n=circuit.n, layers=layers, label=circuit.label + "_relabelled")
+
+
 # Sequence I is the supremacy pattern ABCD-CDAB; Sequence II is the same pattern turned by a
 # quarter (CDBA-BACD).
 SEQUENCE_I = "ABCDCDAB"

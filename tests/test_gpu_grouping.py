@@ -89,3 +89,23 @@ def test_layers_inside_groups_are_trivial_21_qubits():
         print("layer %d (%s) f=%.6f bonds at group cuts %s" % (d, letter, f, [st.bond_dims()[k] for k in cuts]))
         assert all(st.bond_dims()[k] <= 4 for k in cuts)
     assert st.fidelity()["F_tilde"] < 0.999
+
+
+def test_row_grouping_trivial_layers_21_qubits():
+    """H1 (row pairs, the chain relabelled so each group is contiguous) on 21 qubits: the A and
+    D layers are exact at chi = 4 between groups; the bonds between groups stay <= 4."""
+    lay = circuits.SycamoreLayout(4, 6)
+    order, sizes = circuits.sycamore_row_groups(lay, 0)
+    c = circuits.relabel_circuit(circuits.sycamore_circuit(lay, 8, seed=2, sequence="I"), order)
+    prof = circuits.group_bond_profile(sizes, 4)
+    cuts = np.cumsum(sizes)[:-1]
+    st = mps.MPS(c.n, None, max_chi=max(prof), precision=FP64)
+    for d, layer in enumerate(c.layers):
+        before = st.statevector()
+        f = st.apply_layers_dmrg([layer], prof, 1)
+        if circuits.SEQUENCE_I[d % 8] in "AD":
+            assert abs(f - 1.0) < 1e-12, (d, f)
+            target = sv.apply_layer(before, c.n, layer)
+            assert abs(abs(np.vdot(st.statevector(), target)) - 1.0) < 1e-10
+        assert all(st.bond_dims()[k] <= 4 for k in cuts)
+    assert st.fidelity()["F_tilde"] < 0.999

@@ -691,3 +691,47 @@ def test_layers_inside_groups_are_trivial(columns, trivial):
             assert abs(abs(np.vdot(dmrg.to_statevector(st), target)) - 1.0) < 1e-12
         assert all(st.bond_dims()[k] <= 2 for k in cuts)
     assert min(st.layer_f) < 0.99        # the crossing layers do truncate at chi = 2
+
+
+def _internal_letters(layout, groups_of_site):
+    """Coupler classes whose couplers all stay inside one group."""
+    out = ""
+    for letter in "ABCD":
+        if all(groups_of_site[i] == groups_of_site[j] for i, j in layout.pattern_pairs(letter)):
+            out += letter
+    return out
+
+
+def test_groupings_make_the_paper_s_trivial_layers():
+    """The layers the paper calls trivial for each grouping (Sec. V.C) are exactly the coupler
+    classes that stay inside its groups under this reading of classes A-D: B and D for V1
+    (columns 5, 2, 5 of the 54-qubit processor: 23, 9 and 22 qubits), A and D for H1, B and C
+    for H2."""
+    lay = circuits.SycamoreLayout(5, 12)
+    sizes = circuits.sycamore_column_groups(lay, [5, 2, 5])
+    assert sizes == [23, 9, 22]
+    gid = np.repeat(np.arange(3), sizes)
+    assert _internal_letters(lay, gid) == "BD"
+    for offset, want in ((0, "AD"), (1, "BC")):
+        order, hs = circuits.sycamore_row_groups(lay, offset)
+        gid = np.empty(lay.n, dtype=int)
+        gid[np.array(order)] = np.repeat(np.arange(len(hs)), hs)
+        assert _internal_letters(lay, gid) == want, (offset, _internal_letters(lay, gid))
+
+
+def test_row_grouping_layers_are_trivial_after_relabelling():
+    """H1 on the 10-qubit layout: the chain is relabelled so that each row pair is contiguous;
+    the A and D layers are then exact at chi = 2 between groups."""
+    lay = circuits.SycamoreLayout(3, 4)
+    order, sizes = circuits.sycamore_row_groups(lay, 0)
+    c = circuits.relabel_circuit(circuits.sycamore_circuit(lay, 8, seed=3, sequence="I"), order)
+    prof = circuits.group_bond_profile(sizes, 2)
+    st = dmrg.product_state(c.n)
+    for d, layer in enumerate(c.layers):
+        before = dmrg.to_statevector(st)
+        f = dmrg.apply_layers(st, [layer], prof, 2)
+        if circuits.SEQUENCE_I[d % 8] in "AD":
+            assert abs(f - 1.0) < 1e-12
+            target = sv.apply_layer(before, c.n, layer)
+            assert abs(abs(np.vdot(dmrg.to_statevector(st), target)) - 1.0) < 1e-12
+    assert min(st.layer_f) < 0.99
