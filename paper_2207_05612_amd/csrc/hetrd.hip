@@ -426,6 +426,137 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrArgs g) {
 #undef A_SUB
 #undef A_GET
 
+// Orders up to 128: the reduction of a small truncation is pure latency, so one workgroup
+// holds the whole matrix in registers and the steps are separated by barriers instead of
+// cross-workgroup waits.  Thread t keeps column t % 128 at the interleaved rows
+// t / 128 + 8 q.  Same reflector convention and outputs as hetrd_kernel.
+constexpr int SN = 128;             // largest order
+constexpr int ST = 1024;            // threads
+constexpr int SRB = ST / SN;        // row blocks
+constexpr int SQ = SN / SRB;        // rows per thread
+
+__global__ __launch_bounds__(ST, 1) void hetrd_small_kernel(TrArgs g) {
+    __shared__ double2 xs[SN], vs[SN], ys[SN], wsh[SN];
+    __shared__ double2 part[SRB][SN];
+    __shared__ double red[2];
+    __shared__ double xn2_s;
+    const int tid = threadIdx.x, n = g.n;
+    const int c = tid % SN, rb = tid / SN;
+    const int64_t lda = g.lda;
+    double2 a[SQ];
+#pragma unroll
+    for (int q = 0; q < SQ; ++q) {
+        const int r = rb + SRB * q;
+        a[q] = (r < n && c < n) ? g.a[r + c * lda] : make_double2(0.0, 0.0);
+    }
+    for (int i = 0; i + 1 < n; ++i) {
+        // column i (updated by steps 0 .. i-1)
+        if (c == i) {
+#pragma unroll
+            for (int q = 0; q < SQ; ++q) {
+                const int r = rb + SRB * q;
+                if (r < n) xs[r] = a[q];
+            }
+        }
+        __syncthreads();
+        if (tid < 64) {
+            double p = 0.0;
+            for (int r = i + 2 + tid; r < n; r += 64) p += xs[r].x * xs[r].x + xs[r].y * xs[r].y;
+            p = wave_sum(p);
+            if (tid == 0) {
+                xn2_s = p;
+                g.d[i] = xs[i].x;
+            }
+        }
+        __syncthreads();
+        // reflector: H^H x = (beta, 0, ...), v = (1, x[i+2:] / (alpha - beta))
+        const double xnorm2 = xn2_s;
+        const double2 alpha = xs[i + 1];
+        const double anorm2 = alpha.x * alpha.x + alpha.y * alpha.y + xnorm2;
+        const bool reflect = !(xnorm2 == 0.0 && alpha.y == 0.0) && anorm2 > 1e-300;
+        double2 tau = make_double2(0.0, 0.0);
+        double beta = alpha.x;
+        double2 scale = make_double2(0.0, 0.0);
+        if (reflect) {
+            beta = -copysign(sqrt(anorm2), alpha.x);
+            tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+            const double2 am = make_double2(alpha.x - beta, alpha.y);
+            const double den = am.x * am.x + am.y * am.y;
+            scale = make_double2(am.x / den, -am.y / den);
+        }
+        if (tid < SN) {
+            const int r = tid;
+            double2 vr = make_double2(0.0, 0.0);
+            if (r == i + 1)
+                vr = make_double2(1.0, 0.0);
+            else if (r >= i + 2 && r < n)
+                vr = cmul(xs[r], scale);
+            vs[r] = vr;
+            if (r < n) {
+                g.vh_re[(int64_t)i * n + r] = vr.x;
+                g.vh_im[(int64_t)i * n + r] = -vr.y;
+            }
+        }
+        if (tid == 0) {
+            g.e[i] = beta;
+            g.tau[i] = tau;
+        }
+        __syncthreads();
+        // y_c = sum_r conj(A[r, c]) v_r: partial sums over this thread's rows
+        double2 sp = make_double2(0.0, 0.0);
+        if (c >= i + 1 && c < n) {
+#pragma unroll
+            for (int q = 0; q < SQ; ++q) {
+                const int r = rb + SRB * q;
+                if (r >= i + 1 && r < n) sp = cadd(sp, cjmul(a[q], vs[r]));
+            }
+        }
+        part[rb][c] = sp;
+        __syncthreads();
+        if (tid < SN) {
+            double2 y = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int k = 0; k < SRB; ++k) y = cadd(y, part[k][tid]);
+            ys[tid] = y;
+            double pd = wave_sum(cjmul(y, vs[tid]).x);      // Re(y^H v), over two waves
+            if ((tid & 63) == 0) red[tid >> 6] = pd;
+        }
+        __syncthreads();
+        // w = tau y - (|tau|^2 Re(y^H v) / 2) v
+        const double alw = -0.5 * (tau.x * tau.x + tau.y * tau.y) * (red[0] + red[1]);
+        if (tid < SN) {
+            const int r = tid;
+            double2 w = make_double2(0.0, 0.0);
+            if (r >= i + 1 && r < n) {
+                const double2 ty = cmul(tau, ys[r]);
+                w = make_double2(ty.x + alw * vs[r].x, ty.y + alw * vs[r].y);
+            }
+            wsh[r] = w;
+        }
+        __syncthreads();
+        // A[r, c] -= v_r conj(w_c) + w_r conj(v_c) on the trailing block
+        if (c >= i + 1 && c < n) {
+            const double2 wc = wsh[c], vc = vs[c];
+#pragma unroll
+            for (int q = 0; q < SQ; ++q) {
+                const int r = rb + SRB * q;
+                if (r >= i + 1 && r < n) {
+                    const double2 t1 = cjmul(wc, vs[r]);
+                    const double2 t2 = cjmul(vc, wsh[r]);
+                    a[q].x -= t1.x + t2.x;
+                    a[q].y -= t1.y + t2.y;
+                }
+            }
+        }
+    }
+    // last diagonal entry, after step n-2
+    if (c == n - 1) {
+#pragma unroll
+        for (int q = 0; q < SQ; ++q)
+            if (rb + SRB * q == n - 1) g.d[n - 1] = a[q].x;
+    }
+}
+
 // Full Hermitian matrix, column-major interleaved, from the row-major planar
 // Gram matrix whose lower triangle (row >= column) is valid.
 __global__ __launch_bounds__(256) void herm_full_kernel(const double* __restrict__ re, const double* __restrict__ im,
@@ -563,6 +694,10 @@ hipError_t hetrd_persistent(const double* a_z, int n, double* d, double* e, doub
     *abort_flag = g.abort_flag;
     hipError_t err = hipMemsetAsync(flags, 0, sizeof(int) * (size_t)(g.P + 2), stream);
     if (err != hipSuccess) return err;
+    if (n <= SN) {
+        hipLaunchKernelGGL(hetrd_small_kernel, dim3(1), dim3(ST), 0, stream, g);
+        return hipGetLastError();
+    }
     void* args[] = {&g};
     return hipLaunchCooperativeKernel((const void*)hetrd_kernel, dim3(g.P), dim3(TT), args, 0, stream);
 }
