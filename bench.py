@@ -39,6 +39,7 @@ PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0 / 6.0}
 DTYPE = {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3-f32acc"}
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cgemm_54q_chi1024.json")
+SV_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sv_2q_32q.json")
 
 
 def parse():
@@ -240,10 +241,17 @@ def statevector_leg(mps, circuits, torch, n_qubits):
     g.close()
     bytes_per_pass = 2.0 * 16.0 * 2.0 ** c.n
     achieved = bytes_per_pass * passes / (ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(SV_TRAFFIC_FILE):
+        # HBM bytes per pass from the FETCH_SIZE / WRITE_SIZE passes; valid for the same kernel source
+        rec = json.load(open(SV_TRAFFIC_FILE))
+        with open(os.path.join(ROOT, "paper_2207_05612_amd", "csrc", "statevector.hip"), "rb") as fh:
+            if rec.get("source_hash") == hashlib.sha256(fh.read()).hexdigest()[:16] and rec.get("n_qubits") == c.n:
+                traffic = rec.get("bytes_per_launch")
     return {"n_qubits": c.n, "layers": len(c.layers) - 1, "gate_passes": passes, "ms": ms,
             "ms_per_pass": ms / passes,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                          "algorithmic_bytes_per_launch": bytes_per_pass,
                          "kernel": "sv_2q_kernel (one two-qubit pass over all amplitudes, FP64 planar)"}}
 
