@@ -253,7 +253,7 @@ def statevector_leg(mps, circuits, torch, n_qubits):
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                          "algorithmic_bytes_per_launch": bytes_per_pass,
-                         "kernel": "sv_2q_kernel (one two-qubit pass over all amplitudes, FP64 planar)"}}
+                         "kernel": "sv_2q_kernel, sv_2q_bit0_kernel (one two-qubit pass over all amplitudes, FP64 planar)"}}
 
 
 def main():

@@ -203,7 +203,8 @@ hipError_t cgemm_f64_sub(int opa, int opb, int M, int N, int K, CView<double> A,
 struct SvGate2 { double re[16], im[16]; };   // [row * 4 + col], row = 2 s_a + s_b
 struct SvGate1 { double re[4], im[4]; };     // [row * 2 + col]
 hipError_t sv_fill(double* re, double* im, uint64_t dim, uint64_t one_at, hipStream_t s);
-// U on the qubits at index bits pa (high bit of U's row) and pb.
+// U on the qubits at index bits pa (high bit of U's row) and pb.  re and im must be
+// 16-byte aligned (hipErrorInvalidValue otherwise).
 hipError_t sv_apply_2q(double* re, double* im, int n, int pa, int pb, const SvGate2& g, hipStream_t s);
 hipError_t sv_apply_1q(double* re, double* im, int n, int p, const SvGate1& g, hipStream_t s);
 // out[2t], out[2t+1] = amplitude idx[t] (device arrays).

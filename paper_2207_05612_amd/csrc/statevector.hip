@@ -4,11 +4,10 @@
 //
 // Amplitudes are FP64 planar (re block, then im block); chain site q is bit
 // n-1-q of the index (site 0 most significant).  A gate touches every
-// amplitude once: each thread owns the 4 (or 2) amplitudes a two-qubit (or
-// one-qubit) gate mixes, so a pass streams 2 x 16 bytes per amplitude and the
-// kernels are bound by HBM bandwidth.  Consecutive threads own consecutive
-// index groups, so loads and stores are coalesced unless the gate acts on the
-// lowest bits.  Reductions use a fixed grid and fixed-order partial sums, so
+// amplitude once: each thread owns the amplitudes a two-qubit (or one-qubit)
+// gate mixes, so a pass streams 2 x 16 bytes per amplitude and the kernels are
+// bound by HBM bandwidth.  Consecutive threads own consecutive index groups; the
+// two-qubit passes pair neighbouring amplitudes into 16-byte accesses.  Reductions use a fixed grid and fixed-order partial sums, so
 // their results do not depend on scheduling.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -38,32 +37,78 @@ __global__ __launch_bounds__(256) void sv_fill_kernel(double* __restrict__ re, d
     }
 }
 
-// U (4 x 4, row = 2 s_a + s_b) on the qubits at bit positions pa and pb.
-__global__ __launch_bounds__(256) void sv_2q_kernel(double* __restrict__ re, double* __restrict__ im, uint64_t groups,
+// y = U x for the 4 amplitudes of one group (row and column index 2 s_a + s_b).
+__device__ inline void sv_mix4(const SvGate2& g, const double* xr, const double* xi, double* yr, double* yi) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        double ar = 0, ai = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            ar += g.re[r * 4 + c] * xr[c] - g.im[r * 4 + c] * xi[c];
+            ai += g.re[r * 4 + c] * xi[c] + g.im[r * 4 + c] * xr[c];
+        }
+        yr[r] = ar;
+        yi[r] = ai;
+    }
+}
+
+// U (4 x 4) on the qubits at bit positions pa and pb, both >= 1.  A thread owns
+// the groups 2u and 2u + 1: bit 0 is untouched by the gate, so their amplitudes
+// are neighbours and every access is one 16-byte load or store.
+__global__ __launch_bounds__(256) void sv_2q_kernel(double* __restrict__ re, double* __restrict__ im, uint64_t units,
                                                     int pa, int pb, SvGate2 g) {
     const int lo = min(pa, pb), hi = max(pa, pb);
-    const uint64_t ia = 1ull << pa, ib = 1ull << pb;
+    const uint64_t off[4] = {0, 1ull << pb, 1ull << pa, (1ull << pa) | (1ull << pb)};
+    for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < units;
+         u += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t base = insert_zero(insert_zero(2 * u, lo), hi);
+        double2 vr[4], vi[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            vr[r] = *(const double2*)(re + base + off[r]);
+            vi[r] = *(const double2*)(im + base + off[r]);
+        }
+        double xr[4], xi[4], yr0[4], yi0[4], yr1[4], yi1[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            xr[r] = vr[r].x;
+            xi[r] = vi[r].x;
+        }
+        sv_mix4(g, xr, xi, yr0, yi0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            xr[r] = vr[r].y;
+            xi[r] = vi[r].y;
+        }
+        sv_mix4(g, xr, xi, yr1, yi1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            *(double2*)(re + base + off[r]) = make_double2(yr0[r], yr1[r]);
+            *(double2*)(im + base + off[r]) = make_double2(yi0[r], yi1[r]);
+        }
+    }
+}
+
+// U (4 x 4) on bit 0 and the bit at position hi: the two amplitudes of a group
+// that differ in bit 0 are neighbours, one 16-byte access each.  a_low says
+// whether bit 0 is the gate's first qubit (s_a) or its second (s_b).
+__global__ __launch_bounds__(256) void sv_2q_bit0_kernel(double* __restrict__ re, double* __restrict__ im,
+                                                         uint64_t groups, int hi, int a_low, SvGate2 g) {
+    const uint64_t other = 1ull << hi;
     for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < groups;
          t += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t base = insert_zero(insert_zero(t, lo), hi);
-        const uint64_t idx[4] = {base, base | ib, base | ia, base | ia | ib};
-        double xr[4], xi[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            xr[r] = re[idx[r]];
-            xi[r] = im[idx[r]];
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            double yr = 0, yi = 0;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                yr += g.re[r * 4 + c] * xr[c] - g.im[r * 4 + c] * xi[c];
-                yi += g.re[r * 4 + c] * xi[c] + g.im[r * 4 + c] * xr[c];
-            }
-            re[idx[r]] = yr;
-            im[idx[r]] = yi;
-        }
+        const uint64_t base = insert_zero(2 * t, hi);
+        const double2 pr = *(const double2*)(re + base), pi = *(const double2*)(im + base);
+        const double2 qr = *(const double2*)(re + base + other), qi = *(const double2*)(im + base + other);
+        // bit 0 is s_a: (base, base + 1) holds s_a = 0, 1 at s_b = 0; otherwise it holds s_b = 0, 1 at s_a = 0
+        const double xr[4] = {pr.x, a_low ? qr.x : pr.y, a_low ? pr.y : qr.x, qr.y};
+        const double xi[4] = {pi.x, a_low ? qi.x : pi.y, a_low ? pi.y : qi.x, qi.y};
+        double yr[4], yi[4];
+        sv_mix4(g, xr, xi, yr, yi);
+        *(double2*)(re + base) = make_double2(yr[0], a_low ? yr[2] : yr[1]);
+        *(double2*)(im + base) = make_double2(yi[0], a_low ? yi[2] : yi[1]);
+        *(double2*)(re + base + other) = make_double2(a_low ? yr[1] : yr[2], yr[3]);
+        *(double2*)(im + base + other) = make_double2(a_low ? yi[1] : yi[2], yi[3]);
     }
 }
 
@@ -130,8 +175,17 @@ hipError_t sv_fill(double* re, double* im, uint64_t dim, uint64_t one_at, hipStr
 
 hipError_t sv_apply_2q(double* re, double* im, int n, int pa, int pb, const SvGate2& g, hipStream_t s) {
     if (n < 2 || pa == pb || pa < 0 || pb < 0 || pa >= n || pb >= n) return hipErrorInvalidValue;
+    // the 16-byte accesses need re and im at even offsets from a 16-byte boundary
+    if ((reinterpret_cast<uintptr_t>(re) | reinterpret_cast<uintptr_t>(im)) & 15) return hipErrorInvalidValue;
     const uint64_t groups = 1ull << (n - 2);
-    hipLaunchKernelGGL(sv_2q_kernel, dim3(sv_grid(groups, 256)), dim3(256), 0, s, re, im, groups, pa, pb, g);
+    if (pa == 0 || pb == 0) {
+        const int hi = max(pa, pb);
+        hipLaunchKernelGGL(sv_2q_bit0_kernel, dim3(sv_grid(groups, 256)), dim3(256), 0, s, re, im, groups, hi,
+                           pa == 0 ? 1 : 0, g);
+    } else {
+        const uint64_t units = groups / 2;   // n >= 3 here, so groups is even
+        hipLaunchKernelGGL(sv_2q_kernel, dim3(sv_grid(units, 256)), dim3(256), 0, s, re, im, units, pa, pb, g);
+    }
     return hipGetLastError();
 }
 
