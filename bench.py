@@ -124,15 +124,17 @@ def run_layers(mps, circuit, precision, chi, sweeps, warmup, steps, torch, progr
     return dt, fs, stats, bonds, fid, sampling
 
 
-def cpu_baseline(chi: int, sweeps: int, stats_per_layer_flops: float, n_steps_per_layer: int):
+def cpu_baseline(chi: int, sweeps: int, stats_per_layer_flops: float, n_steps_per_layer: int,
+                 min_seconds: float = 10.0, max_updates: int = 8):
     """Time the FP64 oracle on a bounded sample of the chi = 1024 workload.
 
-    Sample: one two-site update of the oracle (local tensor, truncated SVD and
+    Sample: two-site updates of the oracle (local tensor, truncated SVD and
     environment update) at the workload's chi = 1024 with MPO bonds w = 4
-    (an A/B-layer cut), on random inputs of those shapes.  The time per layer
-    is extrapolated as (steps per layer) x (SVD time) + (contraction flops of
-    the GPU's measured layers) / (oracle contraction rate), and reported in
-    gate-layers/s.
+    (an A/B-layer cut), on fresh random inputs of those shapes each time,
+    repeated until min_seconds of CPU work have run (at most max_updates).
+    The time per layer is extrapolated as (steps per layer) x (mean SVD time)
+    + (contraction flops of the GPU's measured layers) / (oracle contraction
+    rate), and reported in gate-layers/s.
     """
     import numpy as np
     from oracle import dmrg
@@ -142,32 +144,38 @@ def cpu_baseline(chi: int, sweeps: int, stats_per_layer_flops: float, n_steps_pe
         return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(np.prod(shape[1:]))
 
     w = 4
-    lenv, renv = rc(chi, 1, chi), rc(chi, w, chi)
-    a1, a2 = rc(chi, 2, chi), rc(chi, 2, chi)
-    w1, w2 = rc(1, 2, 2, w), rc(w, 2, 2, w)
-    t0 = time.perf_counter()
-    th = dmrg.two_site_tensor(lenv, a1, w1, a2, w2, renv)
-    t1 = time.perf_counter()
-    u, s, vh, total = dmrg.truncated_svd(th.reshape(2 * chi, 2 * chi), chi)
-    t2 = time.perf_counter()
-    b = u.reshape(chi, 2, -1)
-    dmrg.env_left_step(lenv, a1, w1, b)
-    t3 = time.perf_counter()
     flops_contract = 8.0 * (chi * 1 * chi * 2 * chi + chi * 2 * w * chi * 2 * chi + 4 * chi * w * chi * chi
                             + chi * 2 * chi * w * chi) + 8.0 * 4 * chi * chi * w * w
-    rate = flops_contract / ((t1 - t0) + (t3 - t2))
-    t_svd = t2 - t1
-    t_layer = n_steps_per_layer * t_svd + stats_per_layer_flops / rate
+    t_con = t_svd = 0.0
+    updates = 0
+    while updates < max_updates and (updates == 0 or t_con + t_svd < min_seconds):
+        lenv, renv = rc(chi, 1, chi), rc(chi, w, chi)
+        a1, a2 = rc(chi, 2, chi), rc(chi, 2, chi)
+        w1, w2 = rc(1, 2, 2, w), rc(w, 2, 2, w)
+        t0 = time.perf_counter()
+        th = dmrg.two_site_tensor(lenv, a1, w1, a2, w2, renv)
+        t1 = time.perf_counter()
+        u, s, vh, total = dmrg.truncated_svd(th.reshape(2 * chi, 2 * chi), chi)
+        t2 = time.perf_counter()
+        b = u.reshape(chi, 2, -1)
+        dmrg.env_left_step(lenv, a1, w1, b)
+        t3 = time.perf_counter()
+        t_con += (t1 - t0) + (t3 - t2)
+        t_svd += t2 - t1
+        updates += 1
+    rate = flops_contract * updates / t_con
+    t_layer = n_steps_per_layer * t_svd / updates + stats_per_layer_flops / rate
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count()
     threads = int(os.environ.get("OMP_NUM_THREADS", cores))
     return {"value": 1.0 / t_layer, "unit": "gate-layers/s", "cores": min(cores, threads), "kind": "oracle",
-            "sample": "one oracle two-site update (local tensor + zgesdd truncation + environment update) at "
-                      "chi=%d, MPO bond 4, random inputs: %.1f s (SVD %.1f s, contraction %.1f GFLOP/s); "
-                      "per-layer time extrapolated from %d updates per layer and the GPU run's algorithmic "
-                      "contraction flops per layer" % (chi, t3 - t0, t_svd, rate / 1e9, n_steps_per_layer)}
+            "sample": "%d oracle two-site updates (local tensor + zgesdd truncation + environment update) at "
+                      "chi=%d, MPO bond 4, fresh random inputs each: %.1f s in total (SVD %.2f s per update, "
+                      "contraction %.1f GFLOP/s); per-layer time extrapolated from %d updates per layer and the "
+                      "GPU run's algorithmic contraction flops per layer"
+                      % (updates, chi, t_con + t_svd, t_svd / updates, rate / 1e9, n_steps_per_layer)}
 
 
 def multilayer_leg(mps, circuit, precision, chi, sweeps, warmup, steps, torch):
