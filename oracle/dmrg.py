@@ -193,6 +193,8 @@ class StepRecord:
     f: float           # partial fidelity after the step
     sum_s2: float      # sum of all squared singular values of the local tensor
     chi_kept: int
+    gap: float = math.inf   # S_k / S_{k+1} - 1 at the cut (k kept); inf when nothing non-zero is cut
+    kappa: float = 0.0      # first-order sensitivity of the state to the cut (truncated_svd_gap)
 
 
 @dataclasses.dataclass
@@ -230,15 +232,50 @@ def chi_at(chi, bond: int) -> int:
     return int(chi) if np.isscalar(chi) else int(chi[bond])
 
 
-def truncated_svd(m: np.ndarray, chi: int):
-    """SVD keeping chi' = min(chi, #{S_i^2 > EPS_TRUNC * sum S^2}) values (Sec. VI.A)."""
-    u, s, vh = np.linalg.svd(m, full_matrices=False)
+def _svd(m: np.ndarray):
+    """Thin SVD by LAPACK: the divide-and-conquer driver, or the QR-iteration driver
+    when divide and conquer does not converge (it can fail on exactly degenerate
+    spectra, e.g. the states of SWAP networks); both compute the same factorisation."""
+    try:
+        return np.linalg.svd(m, full_matrices=False)
+    except np.linalg.LinAlgError:
+        import scipy.linalg
+        return scipy.linalg.svd(m, full_matrices=False, lapack_driver="gesvd")
+
+
+def truncated_svd_gap(m: np.ndarray, chi: int):
+    """SVD keeping chi' = min(chi, #{S_i^2 > EPS_TRUNC * sum S^2}) values (Sec. VI.A).
+
+    Also returns the conditioning of the cut, (gap, kappa):
+      gap   = S_k / S_{k+1} - 1, the relative gap between the smallest kept and the
+              largest discarded singular value (k kept; inf when nothing non-zero is
+              discarded).  The kept subspace is unique only when it is non-zero.
+      kappa = (S_1^2 / T) (S_k / sqrt(T)) / ((S_k^2 - S_{k+1}^2) / T), T = sum S^2:
+              first-order perturbation theory (Davis-Kahan for the Gram matrix m m^H)
+              turns a perturbation of relative size u of m m^H into a rotation of
+              the kept subspace of at most u lambda_1 / (lambda_k - lambda_{k+1}),
+              which moves the normalised state by that angle times the weight
+              S_k / sqrt(T) of the mixed singular vector; with the same on the right
+              (m^H m), 2 kappa u bounds the state's change at this cut to first
+              order (kappa = 0 when nothing is discarded)."""
+    u, s, vh = _svd(m)
     total = float(np.sum(s ** 2))
     if not total > 0.0 or not np.isfinite(total):
         raise FloatingPointError("local tensor has zero or non-finite norm")
     keep = int(np.count_nonzero(s ** 2 > EPS_TRUNC * total))
     k = max(1, min(chi, keep))
-    return u[:, :k], s[:k], vh[:k], total
+    gap, kappa = math.inf, 0.0
+    if k < len(s) and s[k] > 0.0:
+        gap = float(s[k - 1] / s[k] - 1.0)
+        dl = float(s[k - 1] ** 2 - s[k] ** 2)
+        kappa = math.inf if dl <= 0.0 else float(s[0] ** 2 * s[k - 1] / (dl * math.sqrt(total)))
+    return u[:, :k], s[:k], vh[:k], total, (gap, kappa)
+
+
+def truncated_svd(m: np.ndarray, chi: int):
+    """truncated_svd_gap without the gap."""
+    u, s, vh, total, _ = truncated_svd_gap(m, chi)
+    return u, s, vh, total
 
 
 # ---------------------------------------------------------- contractions ---
@@ -277,42 +314,48 @@ def two_site_tensor(lenv, a1, w1, a2, w2, renv):
 def zipup_left_to_right(a, w, chi, envs, log):
     n = len(a)
     b = [None] * n
+    conds = []
     c = np.ones((1, 1, 1), dtype=np.complex128)
     envs[0] = c
     for k in range(n - 1):
         t = _ein("pba,atx,bstc->pscx", c, a[k], w[k])
         cl, _, wk, dk = t.shape
-        u, s, vh, total = truncated_svd(t.reshape(cl * 2, wk * dk), chi_at(chi, k + 1))
+        u, s, vh, total, cond = truncated_svd_gap(t.reshape(cl * 2, wk * dk), chi_at(chi, k + 1))
         b[k] = u.reshape(cl, 2, len(s))
         c = (s[:, None] * vh).reshape(len(s), wk, dk)
         envs[k + 1] = c
+        conds.append(cond)
     t = _ein("pba,atx,bstc->pscx", c, a[n - 1], w[n - 1])
     f0 = float(np.sum(np.abs(t) ** 2))
     if not f0 > 0.0:
         raise FloatingPointError("zip-up produced a zero state")
     b[n - 1] = t.reshape(t.shape[0], 2, 1) / math.sqrt(f0)
-    log.append(StepRecord("zip", -1, f0, f0, b[n - 1].shape[0]))
+    log.append(StepRecord("zip", -1, f0, f0, b[n - 1].shape[0], min((c[0] for c in conds), default=math.inf),
+                         max((c[1] for c in conds), default=0.0)))
     return b, f0
 
 
 def zipup_right_to_left(a, w, chi, envs, log):
     n = len(a)
     b = [None] * n
+    conds = []
     c = np.ones((1, 1, 1), dtype=np.complex128)
     envs[n] = c
     for k in range(n - 1, 0, -1):
         t = _ein("qez,ytz,bste->ybsq", c, a[k], w[k])
         dk, wk, _, cr = t.shape
-        u, s, vh, total = truncated_svd(t.reshape(dk * wk, 2 * cr), chi_at(chi, k))
+        u, s, vh, total, cond = truncated_svd_gap(t.reshape(dk * wk, 2 * cr), chi_at(chi, k))
         b[k] = vh.reshape(len(s), 2, cr)
         c = (u * s[None, :]).reshape(dk, wk, len(s)).transpose(2, 1, 0)
         envs[k] = c
+        conds.append(cond)
     t = _ein("qez,ytz,bste->ybsq", c, a[0], w[0])
     f0 = float(np.sum(np.abs(t) ** 2))
     if not f0 > 0.0:
         raise FloatingPointError("zip-up produced a zero state")
     b[0] = t.reshape(1, 2, t.shape[3]) / math.sqrt(f0)
-    log.append(StepRecord("zip", -1, f0, f0, b[0].shape[2]))
+    log.append(StepRecord("zip", -1, f0, f0, b[0].shape[2], min((c[0] for c in conds), default=math.inf),
+                         max((c[1] for c in conds), default=0.0)))
     return b, f0
 
 
@@ -324,12 +367,12 @@ def sweep_left_to_right(a, w, b, chi, envs, log):
     for k in range(n - 1):
         th = two_site_tensor(envs[k], a[k], w[k], a[k + 1], w[k + 1], envs[k + 2])
         cl, _, _, cr = th.shape
-        u, s, vh, total = truncated_svd(th.reshape(cl * 2, 2 * cr), chi_at(chi, k + 1))
+        u, s, vh, total, cond = truncated_svd_gap(th.reshape(cl * 2, 2 * cr), chi_at(chi, k + 1))
         f = float(np.sum(s ** 2))
         b[k] = u.reshape(cl, 2, len(s))
         b[k + 1] = (s[:, None] * vh / math.sqrt(f)).reshape(len(s), 2, cr)
         envs[k + 1] = env_left_step(envs[k], a[k], w[k], b[k])
-        log.append(StepRecord("l2r", k + 1, f, total, len(s)))
+        log.append(StepRecord("l2r", k + 1, f, total, len(s), *cond))
     return f
 
 
@@ -340,12 +383,12 @@ def sweep_right_to_left(a, w, b, chi, envs, log):
     for k in range(n - 2, -1, -1):
         th = two_site_tensor(envs[k], a[k], w[k], a[k + 1], w[k + 1], envs[k + 2])
         cl, _, _, cr = th.shape
-        u, s, vh, total = truncated_svd(th.reshape(cl * 2, 2 * cr), chi_at(chi, k + 1))
+        u, s, vh, total, cond = truncated_svd_gap(th.reshape(cl * 2, 2 * cr), chi_at(chi, k + 1))
         f = float(np.sum(s ** 2))
         b[k + 1] = vh.reshape(len(s), 2, cr)
         b[k] = (u * (s / math.sqrt(f))[None, :]).reshape(cl, 2, len(s))
         envs[k + 1] = env_right_step(envs[k + 2], a[k + 1], w[k + 1], b[k + 1])
-        log.append(StepRecord("r2l", k + 1, f, total, len(s)))
+        log.append(StepRecord("r2l", k + 1, f, total, len(s), *cond))
     return f
 
 
