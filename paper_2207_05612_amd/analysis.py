@@ -8,8 +8,11 @@ statevector side by side and records, after every step:
   * the error rates eps = 1 - F^(1/N_2g) (eq:epsilon) and eps~ from F~;
   * eps_SVD of the best MPS: the weight kept by the chi largest Schmidt values of the
     exact state at the middle cut (Sec. VI, best possible MPS);
-  * the chaotic optimum eps_opt = (log 2 - log(4 chi) / (2N)) / D
-    (eq:error_rate_asymptotics).
+  * the chaotic optimum: the best bond-chi MPS of a chaotic state keeps the
+    fidelity F_opt = 4 chi / 2^(N/2) (leading term of App. B, eq:F_chi_rel), and
+    eps_opt = 1 - F_opt^(2/(N D)) (the error per gate with N D / 2 gates,
+    App. B).  The closed form printed as eq:error_rate_asymptotics has its
+    log(4 chi) term four times too small; the derivation's form is used.
 
 Everything runs in the library (C ABI calls); this module only composes them.
 """
@@ -24,8 +27,14 @@ from . import circuits, mps
 
 
 def chaotic_optimum_error(chi: int, n_qubits: int, depth: int) -> float:
-    """eq:error_rate_asymptotics: the error per gate of the best bond-chi MPS of a chaotic state."""
-    return (math.log(2.0) - math.log(4.0 * chi) / (2.0 * n_qubits)) / depth
+    """Error per gate of the best bond-chi MPS of a chaotic state (App. B): with
+    F_opt = 4 chi / 2^(N/2) and N D / 2 two-qubit gates, eps = 1 - F_opt^(2/(N D)),
+    i.e. 1 - exp((2 / (N D)) (log(4 chi) - (N/2) log 2)).  For F_opt >= 1 the
+    optimum is exact and the error 0."""
+    log_f = math.log(4.0 * chi) - 0.5 * n_qubits * math.log(2.0)
+    if log_f >= 0.0:
+        return 0.0
+    return -math.expm1(2.0 * log_f / (n_qubits * depth))
 
 
 def error_rate(fid: float, n_2q: int) -> float:

@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 from paper_2207_05612_amd import circuits, mps
-from oracle import analysis, dmrg
+from oracle import analysis, chaotic, dmrg
 from oracle import statevector as sv
 
 pytestmark = pytest.mark.gpu
@@ -211,6 +211,7 @@ def test_depth_curve_matches_the_oracle():
         s2 = sv.schmidt_values(psi, c.n, c.n // 2) ** 2
         assert abs(rec["F_SVD"] - np.sum(s2[:6]) / np.sum(s2)) < 1e-12
         assert rec["F"] <= rec["F_SVD"] + 1e-12            # no bond-6 MPS beats the best cut
+        assert abs(rec["eps_opt"] - chaotic.eps_opt(6, c.n, d + 1)) < 1e-12
         assert abs(rec["F_B_estimate"] - rec["F_B"]) < 5 * rec["F_B_estimate_sd"] + 1e-12
     print("depth F F~ F_B F_SVD:", [(r["depth"], round(r["F"], 4), round(r["F_tilde"], 4), round(r["F_B"], 4),
                                      round(r["F_SVD"], 4)) for r in recs])
