@@ -735,3 +735,51 @@ def test_row_grouping_layers_are_trivial_after_relabelling():
             target = sv.apply_layer(before, c.n, layer)
             assert abs(abs(np.vdot(dmrg.to_statevector(st), target)) - 1.0) < 1e-12
     assert min(st.layer_f) < 0.99
+
+
+# ------------------------------------------- conditioning of a truncation --
+@pytest.mark.parametrize("gap", [1e-1, 1e-3, 1e-5])
+def test_truncation_sensitivity_bounds_the_state_change(gap):
+    """2 u kappa (truncated_svd_gap) bounds, to first order, how far a relative perturbation u
+    of the Gram matrices moves the normalised truncated state (Davis-Kahan on the left and on
+    the right kept subspace); the gap is the one constructed, and the bound is attained within
+    a modest factor by the worst perturbation (one that couples the last kept and the first
+    discarded singular vectors)."""
+    rng = np.random.default_rng(11)
+    n, k = 40, 10
+
+    def haar(m):
+        q, r = np.linalg.qr(rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)))
+        return q * (np.diag(r) / np.abs(np.diag(r)))
+
+    s = np.sort(rng.uniform(0.2, 1.0, n))[::-1]
+    s[k:] *= s[k - 1] / (s[k] * (1.0 + gap))          # S_k / S_{k+1} = 1 + gap exactly
+    s[k:] = np.minimum(s[k:], s[k - 1] / (1.0 + gap))
+    u_, v_ = haar(n), haar(n)
+    m = (u_ * s) @ v_.conj().T
+    _, ks, _, total, (g, kappa) = dmrg.truncated_svd_gap(m, k)
+    assert len(ks) == k and abs(g - gap) < 1e-9 * max(1.0, gap)
+
+    def state(mat):
+        uu, ss, vv, _ = dmrg.truncated_svd(mat, k)
+        t = (uu * ss) @ vv
+        return t / np.linalg.norm(t)
+
+    ref = state(m)
+    eps = 1e-9
+    worst_ratio = 0.0
+    for trial in range(6):
+        if trial == 0:
+            # worst case: rotate the k-th kept into the first discarded left singular vector
+            e = np.outer(u_[:, k], u_[:, k - 1].conj()) + np.outer(u_[:, k - 1], u_[:, k].conj())
+            e = e @ m
+        else:
+            e = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        e *= eps * np.linalg.norm(m, 2) / np.linalg.norm(e, 2)     # relative perturbation of m (2x in m m^H)
+        phi = state(m + e)
+        ph = np.vdot(ref, phi)
+        d = np.linalg.norm(phi * np.conj(ph) / abs(ph) - ref)
+        worst_ratio = max(worst_ratio, d / (2 * eps * kappa))
+    print("gap %.0e kappa %.3g worst ratio %.3f" % (gap, kappa, worst_ratio))
+    assert worst_ratio <= 2.0          # first-order bound (2 eps = relative size of the Gram change)
+    assert worst_ratio >= 0.1          # and not vacuous: the worst perturbation comes close to it
