@@ -58,10 +58,28 @@ typedef enum {
 typedef enum {
     MPS_FP64 = 0,   /* complex FP64 contractions on FP64 MFMA                  */
     MPS_FP32 = 1,   /* complex FP32 contractions on FP32 MFMA, FP32 environments */
+    MPS_BF16X2 = 2, /* split precision: FP32 operands as two BF16 terms (hi, lo),
+                       three BF16 MFMA products per real product (hh, hl, lh),
+                       FP32 accumulation (relative error about 2^-16),
+                       FP32 environments                                      */
     MPS_BF16X3 = 3  /* split precision: FP32 operands as three BF16 terms, six
                        BF16 MFMA products per real product, FP32 accumulation
                        (about FP32 accuracy), FP32 environments            */
 } mps_precision;
+
+/* Device-memory callbacks (optional, see mps_create).  alloc returns at least
+ * `bytes` bytes of device memory of the state's GPU, aligned to 256 bytes,
+ * usable in stream order on `stream` (a hipStream_t), or NULL on failure;
+ * free releases a pointer alloc returned, in stream order on `stream`.  The
+ * library calls them from the thread that makes the library call (for
+ * apply_layer_dmrg_batched: from its worker threads, so they must be
+ * thread-safe) and frees every block before mps_destroy returns.  `user` is
+ * passed through.  The struct is copied by mps_create. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* stream, void* user);
+    void (*free)(void* ptr, void* stream, void* user);
+    void* user;
+} mps_allocator;
 
 /* One gate.  q1 = -1 for a one-qubit gate.  m holds the matrix as interleaved
  * complex128, row-major with rows = output and columns = input:
@@ -84,12 +102,21 @@ typedef struct {
  *              used for argument checks only.
  *   precision  an mps_precision value.
  *   hip_stream hipStream_t to run on (NULL = the default stream).
+ *   alloc      device-memory callbacks for every buffer the state and its
+ *              calls use (e.g. a framework's caching allocator); NULL =
+ *              hipMallocAsync / hipFreeAsync on the call's stream from the
+ *              device's default memory pool.  Both function pointers must be
+ *              non-NULL (MPS_ERR_ARG otherwise).
  *   out        receives the new state; the caller releases it with
  *              mps_destroy.  The state owns all of its device memory. */
 mps_status mps_create(int n_sites, const uint8_t* init_bits, int max_chi,
-                      int precision, void* hip_stream, mps_state** out);
+                      int precision, void* hip_stream, const mps_allocator* alloc,
+                      mps_state** out);
 
-/* Release a state and all device memory it owns.  NULL is accepted. */
+/* Release a state and all device memory it owns, after its streams have
+ * drained: its buffers (through its allocator), its rocBLAS handle, its second
+ * stream and its events.  Memory the default pool keeps cached is returned to
+ * the device.  NULL is accepted. */
 mps_status mps_destroy(mps_state* state);
 
 /* One compression step (Sec. IV.B with K = 1): replace |psi> by the bond-chi
@@ -224,6 +251,17 @@ mps_status mps_get_tensor(const mps_state* state, int site, double* re_im);
  * total number available. */
 mps_status mps_step_log(const mps_state* state, double* f, double* sum_s2,
                         int* chi_kept, int cap, int* n);
+
+/* How the truncations of this state were diagonalised since it was created:
+ *   counts[0]  persistent multi-workgroup tridiagonal reduction (orders 129..2048);
+ *   counts[1]  single-workgroup tridiagonal reduction (orders 2..128);
+ *   counts[2]  fallbacks: rocSOLVER's dense solver after the persistent reduction
+ *              was refused a cooperative launch or gave up waiting;
+ *   counts[3]  rocSOLVER's dense solver by choice (order above 2048, order 1, or
+ *              MPS_EIGENSOLVER=rocsolver).
+ * counts: 4 host int64.  A truncation whose eigenvalues or kept eigenvectors
+ * are not finite fails the call with MPS_ERR_NUMERIC instead. */
+mps_status mps_eigensolver_counts(const mps_state* state, int64_t* counts);
 
 /* <phi| Z_i Z_j |phi> (or <Z_i> when i == j) in FP64. */
 mps_status mps_expect_zz(const mps_state* state, int i, int j, double* value);

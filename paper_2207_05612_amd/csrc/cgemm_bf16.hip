@@ -1,12 +1,16 @@
 // Split-precision complex GEMM on CDNA4 BF16 matrix cores (gfx950).
 //
 // C (M x N, FP32) = A (M x K) B^T (B stored N x K), planar complex, both
-// operands FP32 with k contiguous.  Every FP32 operand x is split into three
-// BF16 terms x = x_h + x_m + x_l (each the BF16 rounding of what remains), and
-// a real product keeps the six terms x_h y_h + x_h y_m + x_m y_h + x_m y_m +
-// x_h y_l + x_l y_h, accumulated in FP32 by v_mfma_f32_32x32x16_bf16.  The
-// dropped terms are below 2^-24 of the product, so the result carries about
-// FP32 accuracy; a complex product is four such real products.
+// operands FP32 with k contiguous.  Every FP32 operand x is split into S BF16
+// terms x = x_0 + ... + x_{S-1} (each the BF16 rounding of what remains), and a
+// real product keeps the terms x_a y_b with a + b < S, accumulated in FP32 by
+// v_mfma_f32_32x32x16_bf16:
+//   S = 3 (cgemm_bf16x3_nt_kernel): six products hh, hm, mh, mm, hl, lh; the
+//         dropped terms are below 2^-24 of the product (about FP32 accuracy);
+//   S = 2 (cgemm_bf16x2_nt_kernel): three products hh, hl, lh; the dropped
+//         term x_l y_l and the residual of the two-term split are about 2^-16
+//         of the product.
+// A complex product is four such real products.
 //
 // Tiling: 512 threads = 8 wavefronts (4 x 2), wave tile 64 x 64 complex
 // (2 x 2 MFMA tiles of 32 x 32), block tile 256 x 128, BK = 16 (one MFMA k
@@ -14,8 +18,9 @@
 // waits.  The split happens when a k-tile is staged from registers into LDS;
 // LDS holds [split][re|im][k/8][row][8] so that the 8 consecutive k of one
 // MFMA lane are one 16-byte read and the 32 lanes of a row group read
-// consecutive 16-byte words.  Two LDS buffers (144 KiB) overlap the next
-// tile's float4 global loads with the current tile's 96 MFMAs per wave;
+// consecutive 16-byte words.  Two LDS buffers (144 KiB for S = 3) overlap the
+// next tile's float4 global loads with the current tile's 96 (S = 3) or 48
+// (S = 2) MFMAs per wave;
 // fragments are read per split pair to keep each wave under 256 registers.
 // Block ids map to tiles XCD-first, then in groups of 8 tile rows.
 #include <hip/hip_runtime.h>
@@ -62,10 +67,10 @@ constexpr int NT = 512;   // threads per block: 8 wavefronts, 4 (m) x 2 (n)
 template <int ROWS>
 __device__ inline int lds_off(int s, int p, int c, int r) { return ((((s * 2 + p) * 2 + c) * ROWS) + r) * 8; }
 
-template <bool VEC>
-__global__ __launch_bounds__(NT, 1) void cgemm_bf16x3_nt_kernel(SplitArgs g) {
-    __shared__ __attribute__((aligned(16))) unsigned short As[2][3 * 2 * 2 * SBM * 8];
-    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][3 * 2 * 2 * SBN * 8];
+template <int S, bool VEC>
+__device__ __forceinline__ void cgemm_split_body(const SplitArgs& g) {
+    __shared__ __attribute__((aligned(16))) unsigned short As[2][S * 2 * 2 * SBM * 8];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][S * 2 * 2 * SBN * 8];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -143,16 +148,21 @@ __global__ __launch_bounds__(NT, 1) void cgemm_bf16x3_nt_kernel(SplitArgs g) {
         u16x4 h, m, l;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            unsigned short a, b, c;
-            split3(x[e], a, b, c);
-            h[e] = a; m[e] = b; l[e] = c;
+            if (S == 3) {
+                unsigned short a, b, c;
+                split3(x[e], a, b, c);
+                h[e] = a; m[e] = b; l[e] = c;
+            } else {
+                h[e] = bf16_rne(x[e]);
+                m[e] = bf16_rne(x[e] - bf16_to_float(h[e]));
+            }
         }
         const int chunk = kq >> 3, sub = kq & 7;
         const int plane = 2 * rows * 8;   // elements per (split, part) for both chunks
         const int off = ((p * 2 + chunk) * rows + row) * 8 + sub;
         *(u16x4*)&base[off] = h;
         *(u16x4*)&base[off + 2 * plane] = m;
-        *(u16x4*)&base[off + 4 * plane] = l;
+        if (S == 3) *(u16x4*)&base[off + 4 * plane] = l;
     };
     auto store = [&](int buf) {
 #pragma unroll
@@ -178,16 +188,16 @@ __global__ __launch_bounds__(NT, 1) void cgemm_bf16x3_nt_kernel(SplitArgs g) {
     const int lrow = lane & 31;
     const int lchunk = lane >> 5;
     auto compute = [&](int buf) {
-        // kept split pairs: (0,0) (0,1) (0,2) (1,0) (1,1) (2,0), grouped by the A split
+        // kept split pairs (sa, sb) with sa + sb < S, grouped by the A split
 #pragma unroll
-        for (int sa = 0; sa < 3; ++sa) {
+        for (int sa = 0; sa < S; ++sa) {
             bf16x8 fa[2][2];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int p = 0; p < 2; ++p)
                     fa[i][p] = *(const bf16x8*)&As[buf][lds_off<SBM>(sa, p, lchunk, wm0 + i * 32 + lrow)];
-            for (int sb = 0; sb < 3 - sa; ++sb) {
+            for (int sb = 0; sb < S - sa; ++sb) {
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
                     const bf16x8 fbr = *(const bf16x8*)&Bs[buf][lds_off<SBN>(sb, 0, lchunk, wn0 + j * 32 + lrow)];
@@ -249,7 +259,16 @@ __global__ __launch_bounds__(NT, 1) void cgemm_bf16x3_nt_kernel(SplitArgs g) {
             }
 }
 
-static hipError_t launch_split(int M, int N, int K, CView<float> A, CView<float> B, CViewMut<float> C,
+template <bool VEC>
+__global__ __launch_bounds__(NT, 1) void cgemm_bf16x3_nt_kernel(SplitArgs g) {
+    cgemm_split_body<3, VEC>(g);
+}
+template <bool VEC>
+__global__ __launch_bounds__(NT, 1) void cgemm_bf16x2_nt_kernel(SplitArgs g) {
+    cgemm_split_body<2, VEC>(g);
+}
+
+static hipError_t launch_split(int terms, int M, int N, int K, CView<float> A, CView<float> B, CViewMut<float> C,
                                int ksplit, int64_t split_stride, hipStream_t stream) {
     if (M <= 0 || N <= 0) return hipSuccess;
     SplitArgs g;
@@ -271,21 +290,30 @@ static hipError_t launch_split(int M, int N, int K, CView<float> A, CView<float>
     const bool vec = (A.ld % 4 == 0) && (B.ld % 4 == 0) &&
                      ((((uintptr_t)A.re) | ((uintptr_t)A.im) | ((uintptr_t)B.re) | ((uintptr_t)B.im)) & 15) == 0;
     const dim3 grid((unsigned)nblocks, (unsigned)ksplit);
-    if (vec)
-        hipLaunchKernelGGL(cgemm_bf16x3_nt_kernel<true>, grid, dim3(NT), 0, stream, g);
-    else
-        hipLaunchKernelGGL(cgemm_bf16x3_nt_kernel<false>, grid, dim3(NT), 0, stream, g);
+    if (terms == 3) {
+        if (vec)
+            hipLaunchKernelGGL(cgemm_bf16x3_nt_kernel<true>, grid, dim3(NT), 0, stream, g);
+        else
+            hipLaunchKernelGGL(cgemm_bf16x3_nt_kernel<false>, grid, dim3(NT), 0, stream, g);
+    } else if (terms == 2) {
+        if (vec)
+            hipLaunchKernelGGL(cgemm_bf16x2_nt_kernel<true>, grid, dim3(NT), 0, stream, g);
+        else
+            hipLaunchKernelGGL(cgemm_bf16x2_nt_kernel<false>, grid, dim3(NT), 0, stream, g);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t cgemm_bf16x3_nt(int M, int N, int K, CView<float> A, CView<float> B, CViewMut<float> C,
-                           hipStream_t stream) {
-    return launch_split(M, N, K, A, B, C, 1, 0, stream);
+hipError_t cgemm_bf16_nt(int terms, int M, int N, int K, CView<float> A, CView<float> B, CViewMut<float> C,
+                         hipStream_t stream) {
+    return launch_split(terms, M, N, K, A, B, C, 1, 0, stream);
 }
 
-hipError_t cgemm_bf16x3_nt_splitk(int M, int N, int K, CView<float> A, CView<float> B, float* ws_re,
-                                  float* ws_im, int ksplit, hipStream_t stream) {
-    return launch_split(M, N, K, A, B, {ws_re, ws_im, N}, ksplit, (int64_t)M * N, stream);
+hipError_t cgemm_bf16_nt_splitk(int terms, int M, int N, int K, CView<float> A, CView<float> B, float* ws_re,
+                                float* ws_im, int ksplit, hipStream_t stream) {
+    return launch_split(terms, M, N, K, A, B, {ws_re, ws_im, N}, ksplit, (int64_t)M * N, stream);
 }
 
 }  // namespace mpsk

@@ -66,9 +66,22 @@ constexpr double EPS_TRUNC = 1e-12;        // kept: S^2 > EPS_TRUNC * sum S^2
 constexpr double GATE_RANK_CUTOFF = 1e-14; // operator-Schmidt terms kept: sigma > cutoff * sigma_0
 
 // ------------------------------------------------------------ device memory
+// Allocator of the state the current call works on (NULL: hipMallocAsync on the
+// call's stream).  Set by check_state() and mps_create(), reset by run_guarded().
+thread_local const mps_allocator* g_alloc = nullptr;
+
 void* dalloc(size_t bytes, hipStream_t s) {
     if (bytes == 0) bytes = 256;
     void* p = nullptr;
+    if (g_alloc) {
+        p = g_alloc->alloc(bytes, (void*)s, g_alloc->user);
+        if (!p) fail(MPS_ERR_OOM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes");
+        if ((uintptr_t)p % 256 != 0) {
+            g_alloc->free(p, (void*)s, g_alloc->user);
+            fail(MPS_ERR_ARG, "allocator callback returned memory that is not 256-byte aligned");
+        }
+        return p;
+    }
     hipError_t e = hipMallocAsync(&p, bytes, s);
     if (e != hipSuccess || p == nullptr) {
         (void)hipGetLastError();
@@ -76,29 +89,37 @@ void* dalloc(size_t bytes, hipStream_t s) {
     }
     return p;
 }
-void dfree(void* p, hipStream_t s) {
-    if (p) (void)hipFreeAsync(p, s);
+void dfree(void* p, hipStream_t s, const mps_allocator* al) {
+    if (!p) return;
+    if (al)
+        al->free(p, (void*)s, al->user);
+    else
+        (void)hipFreeAsync(p, s);
 }
 
-// Planar complex buffer: re = p, im = p + cap.
+// Planar complex buffer: re = p, im = p + cap.  It is released through the
+// allocator it was obtained from.
 template <typename T>
 struct Planar {
     T* p = nullptr;
     int64_t cap = 0;
+    const mps_allocator* al = nullptr;
     T* re() const { return p; }
     T* im() const { return p + cap; }
     void ensure(int64_t n, hipStream_t s) {
         if (n <= cap && p) return;
-        dfree(p, s);
+        release(s);
         // capacity rounded to 64 elements keeps the imaginary plane 256-byte aligned
         const int64_t c = (std::max<int64_t>(n, 1) + 63) / 64 * 64;
         p = (T*)dalloc(sizeof(T) * 2 * (size_t)c, s);
+        al = g_alloc;
         cap = c;
     }
     void release(hipStream_t s) {
-        dfree(p, s);
+        dfree(p, s, al);
         p = nullptr;
         cap = 0;
+        al = nullptr;
     }
 };
 
@@ -106,16 +127,19 @@ template <typename T>
 struct Raw {
     T* p = nullptr;
     int64_t cap = 0;
+    const mps_allocator* al = nullptr;
     void ensure(int64_t n, hipStream_t s) {
         if (n <= cap && p) return;
-        dfree(p, s);
+        release(s);
         p = (T*)dalloc(sizeof(T) * (size_t)std::max<int64_t>(n, 1), s);
+        al = g_alloc;
         cap = std::max<int64_t>(n, 1);
     }
     void release(hipStream_t s) {
-        dfree(p, s);
+        dfree(p, s, al);
         p = nullptr;
         cap = 0;
+        al = nullptr;
     }
 };
 
@@ -485,6 +509,9 @@ struct mps_state {
     Raw<double> dscal;             // small device scalars
     Raw<double> partial;           // reduction partials
     bool prof = false;
+    bool has_alloc = false;
+    mps_allocator alloc{};         // device-memory callbacks (used when has_alloc)
+    int64_t eig_count[4] = {0, 0, 0, 0};   // see mps_eigensolver_counts
     KStat stats[MPS_KCLASS_COUNT];
     std::vector<PendingTiming> pending;
     std::vector<hipEvent_t> event_pool;
@@ -607,7 +634,11 @@ void gemm(mps_state* st, int cls, int opa, int opb, int64_t M, int64_t N, int64_
     }
 }
 
-// Split-precision (BF16 x 3) complex GEMM, C = A B^T with both operands k-contiguous.
+// BF16 terms per FP32 operand of a split-precision state.
+int split_terms(const mps_state* st) { return st->prec == MPS_BF16X2 ? 2 : 3; }
+bool is_split(int prec) { return prec == MPS_BF16X2 || prec == MPS_BF16X3; }
+
+// Split-precision (BF16 x 2 or x 3) complex GEMM, C = A B^T with both operands k-contiguous.
 void gemm_split(mps_state* st, int cls, int64_t M, int64_t N, int64_t K, const float* ar, const float* ai,
                 int64_t lda, const float* br, const float* bi, int64_t ldb, float* cr, float* ci, int64_t ldc,
                 const Lane* lane = nullptr) {
@@ -620,7 +651,7 @@ void gemm_split(mps_state* st, int cls, int64_t M, int64_t N, int64_t K, const f
         ln.ws->ensure(M * N * ks, ln.s);
         {
             Timer t(st, cls, fl, by, ln.s);
-            HIPCHK(cgemm_bf16x3_nt_splitk((int)M, (int)N, (int)K, {ar, ai, lda}, {br, bi, ldb}, ln.ws->re(),
+            HIPCHK(cgemm_bf16_nt_splitk(split_terms(st), (int)M, (int)N, (int)K, {ar, ai, lda}, {br, bi, ldb}, ln.ws->re(),
                                           ln.ws->im(), splitk_for(M, N, K), ln.s));
             t.done();
         }
@@ -629,7 +660,7 @@ void gemm_split(mps_state* st, int cls, int64_t M, int64_t N, int64_t K, const f
         t.done();
     } else {
         Timer t(st, cls, fl, by, ln.s);
-        HIPCHK(cgemm_bf16x3_nt((int)M, (int)N, (int)K, {ar, ai, lda}, {br, bi, ldb}, {cr, ci, ldc}, ln.s));
+        HIPCHK(cgemm_bf16_nt(split_terms(st), (int)M, (int)N, (int)K, {ar, ai, lda}, {br, bi, ldb}, {cr, ci, ldc}, ln.s));
         t.done();
     }
 }
@@ -778,9 +809,13 @@ void eigh_gram(mps_state* st, EighWork& wk, const double* re, const double* im, 
             t.done();
             if (rs != rocblas_status_success) fail(MPS_ERR_DEVICE, "rocsolver_dstedc failed: status " + std::to_string((int)rs));
             wk.method_used = EIGH_PERSISTENT;
+            st->eig_count[dim <= 128 ? 1 : 0] += 1;
             return;
         }
         t.done();
+        st->eig_count[2] += 1;                       // the persistent reduction was refused or gave up
+    } else {
+        st->eig_count[3] += 1;
     }
     wk.Z.ensure(2 * (int64_t)dim * dim, s);
     {
@@ -808,6 +843,13 @@ void top_eigvecs(mps_state* st, EighWork& wk, int dim, int k, double* out_re, do
     const hipStream_t s = st->stream;
     if (wk.method_used == EIGH_ROCSOLVER) {
         HIPCHK(take_top_eigvecs(wk.Z.p, dim, k, nullptr, out_re, out_im, s));
+        // the dense library solver has returned non-finite eigenvectors for some inputs
+        // (diagonal matrices of order >= 100): check the kept ones
+        double nrm = 0;
+        HIPCHK(norm2<double>(out_re, out_im, (int64_t)dim * k, st->partial.p, st->dscal.p + 2, s));
+        HIPCHK(hipMemcpyAsync(&nrm, st->dscal.p + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (!std::isfinite(nrm)) fail(MPS_ERR_NUMERIC, "eigensolver returned non-finite eigenvectors");
         return;
     }
     HIPCHK(take_top_real_eigvecs(wk.Z.p, dim, k, out_re, out_im, s));
@@ -854,7 +896,7 @@ struct Engine {
     Planar<R> X, T2, TH, UR, T2T;
     Planar<R> XR, T2R[2];             // right blocks, written on the second stream
     Planar<R> MT[2][2];               // per lane: intermediates of multi-layer MPO factors
-    bool split = false;   // BF16 x 3 contractions (R = float only): operands kept k-contiguous
+    bool split = false;   // split-precision BF16 contractions (R = float only): operands kept k-contiguous
     Planar<double> TH64, GR, U64, V64, M64;
     EighWork ew;
     Raw<double> svec, QZ, QG, QT;
@@ -902,6 +944,8 @@ struct Engine {
         HIPCHK(hipMemcpyAsync(&hinfo, ew.info.p, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (hinfo != 0) fail(MPS_ERR_NUMERIC, "eigensolver did not converge (info " + std::to_string(hinfo) + ")");
+        for (int i = 0; i < dim; ++i)
+            if (!std::isfinite(hvals[i])) fail(MPS_ERR_NUMERIC, "eigensolver returned a non-finite eigenvalue");
         double total = 0;
         for (int i = dim - 1; i >= 0; --i) total += hvals[i];
         if (!(total > 0) || !std::isfinite(total)) fail(MPS_ERR_NUMERIC, "local tensor has zero or non-finite norm");
@@ -1350,22 +1394,26 @@ void forward_tensor(const mps_state* st, int k, Planar<double>& dst, hipStream_t
 }
 
 mps_status run_guarded(const std::function<void()>& fn) {
+    mps_status code = MPS_OK;
     try {
         fn();
         g_last_error.clear();
-        return MPS_OK;
     } catch (const MpsFail& e) {
         g_last_error = e.msg;
-        return e.code;
+        code = e.code;
     } catch (const std::exception& e) {
         g_last_error = e.what();
-        return MPS_ERR_DEVICE;
+        code = MPS_ERR_DEVICE;
     }
+    g_alloc = nullptr;
+    return code;
 }
 
+// Argument check of a state; device memory of the call comes from its allocator.
 void check_state(const mps_state* st) {
     if (!st) fail(MPS_ERR_ARG, "state is NULL");
     if (st->invalid) fail(MPS_ERR_STATE, "state was invalidated by an earlier failure");
+    g_alloc = st->has_alloc ? &st->alloc : nullptr;
 }
 
 
@@ -1395,9 +1443,9 @@ void apply_step_impl(mps_state* st, const mps_gate* gates, const int* n_gates, i
     const size_t log_mark = st->log_step_f.size();
     double f = 0;
     try {
-        if (st->prec == MPS_FP32 || st->prec == MPS_BF16X3) {
+        if (st->prec == MPS_FP32 || is_split(st->prec)) {
             Engine<float> e(st, chi);
-            e.split = st->prec == MPS_BF16X3;
+            e.split = is_split(st->prec);
             e.single_site = single_site;
             if (chi_bond) e.chi_bond.assign(chi_bond, chi_bond + st->n + 1);
             f = e.run(gates, n_gates, n_layers, n_sweeps);
@@ -1436,14 +1484,15 @@ extern "C" {
 const char* mps_last_error(void) { return g_last_error.c_str(); }
 
 mps_status mps_create(int n_sites, const uint8_t* init_bits, int max_chi, int precision, void* hip_stream,
-                      mps_state** out) {
+                      const mps_allocator* alloc, mps_state** out) {
     return run_guarded([&] {
         if (!out) fail(MPS_ERR_ARG, "out is NULL");
         *out = nullptr;
         if (n_sites < 1 || n_sites > 4096) fail(MPS_ERR_ARG, "n_sites must be in [1, 4096]");
         if (max_chi < 1) fail(MPS_ERR_ARG, "max_chi must be >= 1");
-        if (precision != MPS_FP64 && precision != MPS_FP32 && precision != MPS_BF16X3)
+        if (precision != MPS_FP64 && precision != MPS_FP32 && !is_split(precision))
             fail(MPS_ERR_ARG, "unknown precision");
+        if (alloc && (!alloc->alloc || !alloc->free)) fail(MPS_ERR_ARG, "allocator callbacks must be non-NULL");
         if (init_bits)
             for (int k = 0; k < n_sites; ++k)
                 if (init_bits[k] > 1) fail(MPS_ERR_ARG, "init_bits must be 0 or 1");
@@ -1454,6 +1503,11 @@ mps_status mps_create(int n_sites, const uint8_t* init_bits, int max_chi, int pr
         st->max_chi = max_chi;
         st->prec = precision;
         st->stream = (hipStream_t)hip_stream;
+        if (alloc) {
+            st->alloc = *alloc;
+            st->has_alloc = true;
+            g_alloc = &st->alloc;
+        }
         if (const char* em = std::getenv("MPS_EIGENSOLVER"))
             st->eigh_method = std::strcmp(em, "rocsolver") == 0 ? EIGH_ROCSOLVER : EIGH_PERSISTENT;
         if (const char* ov = std::getenv("MPS_OVERLAP")) st->overlap_right = std::strcmp(ov, "0") != 0;
@@ -1482,27 +1536,44 @@ mps_status mps_create(int n_sites, const uint8_t* init_bits, int max_chi, int pr
 
 mps_status mps_destroy(mps_state* st) {
     if (!st) return MPS_OK;
+    g_alloc = st->has_alloc ? &st->alloc : nullptr;
     (void)hipStreamSynchronize(st->stream);
+    if (st->stream2) (void)hipStreamSynchronize(st->stream2);
     for (auto& t : st->ten) t.release(st->stream);
     st->dscal.release(st->stream);
     st->partial.release(st->stream);
     st->splitws.release(st->stream);
     st->splitws64.release(st->stream);
     if (st->stream2) {
-        (void)hipStreamSynchronize(st->stream2);
         st->splitws2.release(st->stream2);
         (void)hipStreamSynchronize(st->stream2);
         (void)hipStreamDestroy(st->stream2);
+        st->stream2 = nullptr;
     }
-    for (auto e : st->ev_order)
-        if (e) (void)hipEventDestroy(e);
+    for (auto& e : st->ev_order)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
     for (auto& p : st->pending) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
     }
+    st->pending.clear();
     for (auto e : st->event_pool) (void)hipEventDestroy(e);
+    st->event_pool.clear();
     if (st->blas) rocblas_destroy_handle(st->blas);
+    st->blas = nullptr;
     (void)hipStreamSynchronize(st->stream);
+    if (!st->has_alloc) {
+        // return what the default pool cached for this state's frees to the device
+        int dev = 0;
+        hipMemPool_t pool = nullptr;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool)
+            (void)hipMemPoolTrimTo(pool, 0);
+    }
+    (void)hipGetLastError();
+    g_alloc = nullptr;
     delete st;
     return MPS_OK;
 }
@@ -1782,8 +1853,16 @@ mps_status sample(mps_state* st, int64_t n_samples, uint64_t seed, uint64_t* bit
         if (n_samples < 0 || (n_samples > 0 && !bits)) fail(MPS_ERR_ARG, "bad sample arguments");
         if (n_samples == 0) return;
         if (st->prec == MPS_FP32) sample_impl<float>(st, n_samples, seed, bits);
-        else if (st->prec == MPS_BF16X3) sample_impl<float>(st, n_samples, seed, bits, true);
+        else if (is_split(st->prec)) sample_impl<float>(st, n_samples, seed, bits, true);
         else sample_impl<double>(st, n_samples, seed, bits);
+    });
+}
+
+mps_status mps_eigensolver_counts(const mps_state* st, int64_t* counts) {
+    return run_guarded([&] {
+        if (!st) fail(MPS_ERR_ARG, "state is NULL");
+        if (!counts) fail(MPS_ERR_ARG, "counts is NULL");
+        for (int i = 0; i < 4; ++i) counts[i] = st->eig_count[i];
     });
 }
 
@@ -1892,7 +1971,8 @@ mps_status mps_kernel_stats(const mps_state* st, int cls, int64_t* launches, dou
 namespace {
 template <typename R>
 void selftest_cgemm_impl(int opa, int opb, int M, int N, int K, const double* a, const double* b, double* c,
-                         bool split = false) {
+                         int split_terms_ = 0) {
+    const bool split = split_terms_ > 0;
     hipStream_t s = nullptr;
     const int64_t na = (int64_t)M * K, nb = (int64_t)K * N, nc = (int64_t)M * N;
     std::vector<R> ha(2 * na), hb(2 * nb), hc(2 * nc);
@@ -1910,11 +1990,11 @@ void selftest_cgemm_impl(int opa, int opb, int M, int N, int K, const double* a,
     float* ws = nullptr;
     if (ks > 1) ws = (float*)dalloc(sizeof(float) * 2 * (size_t)nc * ks, s);
     if (split && ks > 1)
-        HIPCHK(cgemm_bf16x3_nt_splitk(M, N, K, {(const float*)da, (const float*)(da + na), lda},
+        HIPCHK(cgemm_bf16_nt_splitk(split_terms_, M, N, K, {(const float*)da, (const float*)(da + na), lda},
                                       {(const float*)db, (const float*)(db + nb), ldb}, ws, ws + nc * ks,
                                       splitk_for(M, N, K), s));
     else if (split)
-        HIPCHK(cgemm_bf16x3_nt(M, N, K, {(const float*)da, (const float*)(da + na), lda},
+        HIPCHK(cgemm_bf16_nt(split_terms_, M, N, K, {(const float*)da, (const float*)(da + na), lda},
                                {(const float*)db, (const float*)(db + nb), ldb}, {(float*)dc, (float*)(dc + nc), N}, s));
     else if (ks > 1)
         HIPCHK(cgemm_f32_splitk(opa, opb, M, N, K, {(const float*)da, (const float*)(da + na), lda},
@@ -1923,11 +2003,11 @@ void selftest_cgemm_impl(int opa, int opb, int M, int N, int K, const double* a,
         HIPCHK(gemm_raw<R>(opa, opb, M, N, K, da, da + na, lda, db, db + nb, ldb, dc, dc + nc, N, s));
     if (ks > 1) {
         HIPCHK(splitk_reduce(ws, ws + nc * ks, ks, M, N, (float*)dc, (float*)(dc + nc), N, s));
-        dfree(ws, s);
+        dfree(ws, s, nullptr);
     }
     HIPCHK(hipMemcpyAsync(hc.data(), dc, sizeof(R) * 2 * nc, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    dfree(da, s); dfree(db, s); dfree(dc, s);
+    dfree(da, s, nullptr); dfree(db, s, nullptr); dfree(dc, s, nullptr);
     HIPCHK(hipStreamSynchronize(s));
     for (int64_t i = 0; i < nc; ++i) { c[2 * i] = hc[i]; c[2 * i + 1] = hc[nc + i]; }
 }
@@ -1997,9 +2077,9 @@ extern "C" mps_status mps_kernel_selftest_cgemm(int precision, int opa, int opb,
         if (opb != OP_N && opb != OP_T && opb != OP_C) fail(MPS_ERR_ARG, "opb must be 0, 1 or 2");
         if ((int64_t)M * K > (1 << 28) || (int64_t)K * N > (1 << 28) || (int64_t)M * N > (1 << 28))
             fail(MPS_ERR_ARG, "self-test operands too large");
-        if (precision == MPS_BF16X3) {
+        if (is_split(precision)) {
             if (opa != OP_N || opb != OP_T) fail(MPS_ERR_ARG, "the split-precision kernel takes opa = 0, opb = 1");
-            selftest_cgemm_impl<float>(opa, opb, M, N, K, a, b, c, true);
+            selftest_cgemm_impl<float>(opa, opb, M, N, K, a, b, c, precision == MPS_BF16X2 ? 2 : 3);
         } else if (precision == MPS_FP32) selftest_cgemm_impl<float>(opa, opb, M, N, K, a, b, c);
         else if (precision == MPS_FP64) selftest_cgemm_impl<double>(opa, opb, M, N, K, a, b, c);
         else fail(MPS_ERR_ARG, "unknown precision");

@@ -81,12 +81,16 @@ __device__ inline void st_coh(double2* p, double2 v) {
     __hip_atomic_store(q + 1, __builtin_bit_cast(unsigned long long, v.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Cross-workgroup protocol.  Every value another workgroup reads is written
-// with a device-coherent store (st_coh) and read with a device-coherent load
-// (ld_coh), so no cache write-back or invalidation is needed: a producer
-// waits until its coherent stores are acknowledged (s_waitcnt), joins its
-// workgroup barrier and then sets the flag; a consumer polls the flag with
-// coherent loads and issues its data loads only after the poll returned.
+// Cross-workgroup protocol (release / acquire at agent scope).  Every value
+// another workgroup reads is written with a device-coherent atomic store
+// (st_coh) and read with a device-coherent atomic load (ld_coh).  A producer's
+// threads issue an agent-scope release fence, join the workgroup barrier, and
+// one thread then stores the flag; a consumer thread polls the flag with
+// relaxed loads and issues an agent-scope acquire fence once it has seen the
+// value, before the workgroup barrier after which its data loads are issued.
+// The fence pair makes every store before the producer's fence visible to every
+// load after the consumer's fence (fence-fence synchronisation of the HIP /
+// C++ memory model), so the protocol does not rest on hardware ordering.
 
 // One thread waits until *flag >= target.  False on abort or time-out.
 __device__ bool wait_geq(int* flag, int target, int* abort_flag) {
@@ -99,13 +103,13 @@ __device__ bool wait_geq(int* flag, int target, int* abort_flag) {
         }
         __builtin_amdgcn_s_sleep(1);
     }
-    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return true;
 }
 
-// After this workgroup's coherent stores are acknowledged, set *flag = val.
+// Release this workgroup's earlier stores, then set *flag = val.
 __device__ void publish(int* flag, int val) {
-    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_store(flag, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

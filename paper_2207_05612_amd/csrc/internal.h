@@ -49,8 +49,8 @@ hipError_t cgemm_f32_splitk(int opa, int opb, int M, int N, int K, CView<float> 
                             float* ws_re, float* ws_im, int ksplit, hipStream_t stream);
 hipError_t splitk_reduce(const float* ws_re, const float* ws_im, int nsplit, int64_t M, int64_t N, float* c_re,
                          float* c_im, int64_t ldc, hipStream_t stream);
-hipError_t cgemm_bf16x3_nt_splitk(int M, int N, int K, CView<float> A, CView<float> B, float* ws_re,
-                                  float* ws_im, int ksplit, hipStream_t stream);
+hipError_t cgemm_bf16_nt_splitk(int terms, int M, int N, int K, CView<float> A, CView<float> B, float* ws_re,
+                                float* ws_im, int ksplit, hipStream_t stream);
 // FP64-accumulating split-K variants (BK = 8), used by the Gram matrices of the truncation
 hipError_t cgemm_f32in_f64_splitk(int opa, int opb, int M, int N, int K, CView<float> A, CView<float> B,
                                   double* ws_re, double* ws_im, int ksplit, int lower_only, hipStream_t stream);
@@ -60,10 +60,11 @@ hipError_t splitk_reduce64(const double* ws_re, const double* ws_im, int nsplit,
                            double* c_im, int64_t ldc, hipStream_t stream);
 
 // Split-precision complex GEMM: C (M x N) = A (M x K) B^T with B stored N x K,
-// FP32 operands split into three BF16 terms, six BF16 MFMA products per real
-// product, FP32 accumulation (about FP32 accuracy).
-hipError_t cgemm_bf16x3_nt(int M, int N, int K, CView<float> A, CView<float> B, CViewMut<float> C,
-                           hipStream_t stream);
+// FP32 operands split into `terms` BF16 terms (3: six BF16 MFMA products per
+// real product, about FP32 accuracy; 2: three products, about 2^-16 relative),
+// FP32 accumulation.
+hipError_t cgemm_bf16_nt(int terms, int M, int N, int K, CView<float> A, CView<float> B, CViewMut<float> C,
+                         hipStream_t stream);
 
 // Structured MPO application on one site.
 //   in  [P][w_in][2 (t)][Q],  out [P][2 (s)][w_out][Q]

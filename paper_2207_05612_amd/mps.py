@@ -5,12 +5,21 @@ converts NumPy arrays to pointers and status codes to exceptions.  Loading
 fails loudly when the library has not been built: there is no fallback.
 
 PyTorch supplies the HIP stream (``torch.cuda.current_stream()``) when it is
-importable and a GPU is visible; otherwise the default stream is used.
+importable and a GPU is visible; otherwise the default stream is used.  With
+``torch_allocator=True`` a state takes its device memory from PyTorch's
+caching allocator (``torch.cuda.caching_allocator_alloc`` / ``_delete``)
+through the ABI's allocator callbacks.
+
+States and statevectors still open when the interpreter exits are destroyed
+by an exit hook registered after PyTorch's own, so it runs first, while the
+HIP runtime is still whole.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -21,7 +30,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpsdmrg.so")
 
 MPS_OK, MPS_ERR_ARG, MPS_ERR_OOM, MPS_ERR_DEVICE, MPS_ERR_NUMERIC, MPS_ERR_STATE = 0, -1, -2, -3, -4, -5
-MPS_FP64, MPS_FP32, MPS_BF16X3 = 0, 1, 3
+MPS_FP64, MPS_FP32, MPS_BF16X2, MPS_BF16X3 = 0, 1, 2, 3
 MPS_UPDATE_TWO_SITE, MPS_UPDATE_SINGLE_SITE = 0, 1
 _UPDATES = {"two-site": MPS_UPDATE_TWO_SITE, "single-site": MPS_UPDATE_SINGLE_SITE}
 KCLASS = {"contract": 0, "mpo": 1, "gram": 2, "eigh": 3, "other": 4, "tridiag": 5}
@@ -34,9 +43,26 @@ EXPORTS = ("mps_create", "mps_destroy", "apply_layer_dmrg", "apply_layer_dmrg_si
            "mps_expect_zz", "mps_set_profiling", "mps_kernel_stats", "mps_kernel_selftest_cgemm",
            "mps_kernel_selftest_eigh", "mps_overlap", "apply_layers_dmrg",
            "sv_create", "sv_destroy", "sv_apply_layer", "sv_amplitudes", "sv_compare_mps",
-           "sv_schmidt_weights", "apply_layers_dmrg_bonds")
+           "sv_schmidt_weights", "apply_layers_dmrg_bonds", "mps_eigensolver_counts")
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class MpsAllocator(ctypes.Structure):
+    """struct mps_allocator of the ABI."""
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
 
 _lib = None
+_live = weakref.WeakSet()        # open MPS / Statevector handles, closed by the exit hook
+
+
+def _close_all() -> None:
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 class MpsError(RuntimeError):
@@ -58,12 +84,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     except ImportError:
         pass
     lib = ctypes.CDLL(path)
+    # registered after PyTorch's exit hooks, so it runs before them
+    atexit.register(_close_all)
     P = ctypes.c_void_p
     i32, i64, u64, dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
     dp = ctypes.POINTER(ctypes.c_double)
     ip = ctypes.POINTER(ctypes.c_int)
     sig = {
-        "mps_create": (i32, [i32, P, i32, i32, P, ctypes.POINTER(P)]),
+        "mps_create": (i32, [i32, P, i32, i32, P, ctypes.POINTER(MpsAllocator), ctypes.POINTER(P)]),
+        "mps_eigensolver_counts": (i32, [P, ctypes.POINTER(i64)]),
         "mps_destroy": (i32, [P]),
         "apply_layer_dmrg": (i32, [P, P, i32, i32, i32, dp]),
         "apply_layer_dmrg_single_site": (i32, [P, P, i32, i32, i32, dp]),
@@ -122,11 +151,33 @@ def current_stream() -> Optional[int]:
     return None
 
 
+def _torch_allocator():
+    """Allocator callbacks onto PyTorch's caching allocator (current device): the ABI
+    struct and the two ctypes callback objects, which must stay alive with it."""
+    import torch
+    dev = torch.cuda.current_device()
+
+    def alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream or 0)
+        except Exception:
+            return None
+
+    def free(ptr, stream, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    fa, ff = ALLOC_FN(alloc), FREE_FN(free)
+    return MpsAllocator(fa, ff, None), (fa, ff)
+
+
 class MPS:
-    """Handle of one on-GPU MPS (owns an ``mps_state*``)."""
+    """Handle of one on-GPU MPS (owns an ``mps_state*``).
+
+    torch_allocator=True: device memory from PyTorch's caching allocator (the
+    ABI's allocator callbacks); otherwise the library's own stream-ordered pool."""
 
     def __init__(self, n: int, bits: Optional[Sequence[int]] = None, max_chi: int = 1024,
-                 precision: int = MPS_FP32, stream: Optional[int] = None):
+                 precision: int = MPS_FP32, stream: Optional[int] = None, torch_allocator: bool = False):
         lib = load_library()
         self.n = n
         self.precision = precision
@@ -134,8 +185,12 @@ class MPS:
         bits_arr = None if bits is None else np.ascontiguousarray(bits, dtype=np.uint8)
         if stream is None:
             stream = current_stream()
+        # the callbacks must outlive the state
+        self._alloc, self._alloc_fns = _torch_allocator() if torch_allocator else (None, None)
         _check(lib.mps_create(n, None if bits_arr is None else bits_arr.ctypes.data, max_chi, precision,
-                              stream, ctypes.byref(self._h)))
+                              stream, ctypes.byref(self._alloc) if self._alloc is not None else None,
+                              ctypes.byref(self._h)))
+        _live.add(self)
 
     def close(self) -> None:
         if self._h:
@@ -237,6 +292,12 @@ class MPS:
         _check(_lib.mps_step_log(self._h, _dptr(f), _dptr(s2), _iptr(k), m, ctypes.byref(n)))
         return f[:m], s2[:m], k[:m]
 
+    def counters(self) -> dict:
+        """Eigensolver paths of the truncations so far (mps_eigensolver_counts)."""
+        c = (ctypes.c_int64 * 4)()
+        _check(_lib.mps_eigensolver_counts(self._h, c))
+        return {"persistent": c[0], "single_workgroup": c[1], "fallback_library": c[2], "library": c[3]}
+
     def expect_zz(self, i: int, j: int) -> float:
         v = ctypes.c_double()
         _check(_lib.mps_expect_zz(self._h, i, j, ctypes.byref(v)))
@@ -291,8 +352,8 @@ def selftest_eigh(a: np.ndarray, method: int = EIGH_PERSISTENT):
 
 
 # free functions with the ABI's names
-def mps_create(n, bits=None, max_chi=1024, precision=MPS_FP32, stream=None) -> MPS:
-    return MPS(n, bits, max_chi, precision, stream)
+def mps_create(n, bits=None, max_chi=1024, precision=MPS_FP32, stream=None, torch_allocator=False) -> MPS:
+    return MPS(n, bits, max_chi, precision, stream, torch_allocator)
 
 
 def apply_layer_dmrg(state: MPS, layer, chi: int, n_sweeps: int) -> float:
@@ -342,6 +403,7 @@ class Statevector:
         if stream is None:
             stream = current_stream()
         _check(lib.sv_create(n, None if bits_arr is None else bits_arr.ctypes.data, stream, ctypes.byref(self._h)))
+        _live.add(self)
 
     def close(self) -> None:
         if self._h:

@@ -17,7 +17,7 @@ HEADER = os.path.join(ROOT, "include", "mps_dmrg.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\b\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)))
 
 
 def test_header_declares_the_abi():
@@ -54,3 +54,32 @@ def test_gate_record_layout():
     assert rec[0]["q1"] == -1 and rec[1]["q0"] == 0 and rec[1]["q1"] == 5
     m = rec[1]["m"][0::2] + 1j * rec[1]["m"][1::2]
     assert np.allclose(m.reshape(4, 4), circuits.fsim(0.3, 0.2))
+
+
+def _prototype(name):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    m = re.search(r"\b%s\s*\((.*?)\)\s*;" % name, text, flags=re.S)
+    assert m, name
+    return [" ".join(a.split()) for a in m.group(1).split(",")]
+
+
+def test_create_takes_allocator_callbacks():
+    args = _prototype("mps_create")
+    assert args == ["int n_sites", "const uint8_t* init_bits", "int max_chi", "int precision",
+                    "void* hip_stream", "const mps_allocator* alloc", "mps_state** out"]
+    # struct mps_allocator: alloc, free, user -- three pointers, as the binding declares it
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{(.*?)\}\s*mps_allocator;", text, flags=re.S).group(1)
+    fields = [f.strip() for f in body.split(";") if f.strip()]
+    assert fields[0].startswith("void* (*alloc)(size_t bytes, void* stream, void* user")
+    assert fields[1].startswith("void (*free)(void* ptr, void* stream, void* user")
+    assert fields[2] == "void* user"
+    assert ctypes.sizeof(mps.MpsAllocator) == 3 * ctypes.sizeof(ctypes.c_void_p)
+    assert [f[0] for f in mps.MpsAllocator._fields_] == ["alloc", "free", "user"]
+
+
+def test_precision_values_match_the_header():
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    vals = dict((k, int(v)) for k, v in re.findall(r"\b(MPS_(?:FP64|FP32|BF16X2|BF16X3))\s*=\s*(\d+)", text))
+    assert vals == {"MPS_FP64": mps.MPS_FP64, "MPS_FP32": mps.MPS_FP32, "MPS_BF16X2": mps.MPS_BF16X2,
+                    "MPS_BF16X3": mps.MPS_BF16X3}

@@ -245,3 +245,43 @@ def test_argument_errors_leave_state_usable():
         st.apply_layer_dmrg(layer, 8, 2)
     ora = dmrg.run_circuit(c, chi=8, n_sweeps=2)
     assert rel_l2(st.statevector(), dmrg.to_statevector(ora)) < 1e-9
+
+
+@pytest.mark.parametrize("prec", [FP64, BF16X3])
+def test_torch_caching_allocator_parity(prec):
+    """A state whose device memory comes from PyTorch's caching allocator (the ABI's allocator
+    callbacks) gives the same layers as the oracle; its blocks are PyTorch's while it lives and
+    are all returned when it is destroyed."""
+    import torch
+    c = circuits.plain_fp64_workload(1)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    st = mps.MPS(c.n, None, max_chi=8, precision=prec, torch_allocator=True)
+    fs = np.array([st.apply_layer_dmrg(layer, 8, 2) for layer in c.layers])
+    assert torch.cuda.memory_allocated() > base          # the tensors of the state live in torch's pool
+    ora = dmrg.run_circuit(c, chi=8, n_sweeps=2)
+    of = np.array(ora.layer_f)
+    assert np.max(np.abs(fs - of) / of) < F_TOL[prec]
+    err = rel_l2(st.statevector(), dmrg.to_statevector(ora))
+    check_amplitudes(prec, err, st, ora, 2, "torch allocator")
+    # the same layers on a state with the library's own pool: identical kernels, identical results
+    ref, fr = run_gpu(c, 8, 2, prec)
+    assert np.array_equal(fs, fr)
+    st.close()
+    ref.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == base
+
+
+def test_eigensolver_counts():
+    """Every truncation is counted once by the path that diagonalised it; orders up to 128 take
+    the single-workgroup reduction, larger ones the persistent one; no fallback happens."""
+    c = circuits.random_circuit(circuits.grid_from_shape(5, 4), 10, seed=3)
+    st, fs = run_gpu(c, 128, 1, FP64)
+    cnt = st.counters()
+    n_trunc = len(c.layers) * (2 * (c.n - 1))          # zip-up (n - 1) + one sweep (n - 1) per layer
+    print(cnt, st.bond_dims())
+    assert sum(cnt.values()) == n_trunc
+    assert cnt["fallback_library"] == 0 and cnt["single_workgroup"] > 0
+    if max(st.bond_dims()) > 64:                        # a Gram matrix of order > 128 was diagonalised
+        assert cnt["persistent"] > 0
