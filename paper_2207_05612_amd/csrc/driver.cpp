@@ -727,11 +727,12 @@ struct EighWork {
     Planar<double> vh, S, T, Y, W, ws;   // reflectors (conjugated rows) and back-transformation scratch
     Raw<char> trws;
     Raw<int> info;
+    Raw<double> nrm;                     // partial sums and result of the eigenvector check
     int method_used = EIGH_ROCSOLVER;
     void release(hipStream_t s) {
         Z.release(s); evals.release(s); evwork.release(s); tau.release(s);
         vh.release(s); S.release(s); T.release(s); Y.release(s); W.release(s); ws.release(s);
-        trws.release(s); info.release(s);
+        trws.release(s); info.release(s); nrm.release(s);
     }
 };
 
@@ -845,9 +846,12 @@ void top_eigvecs(mps_state* st, EighWork& wk, int dim, int k, double* out_re, do
         HIPCHK(take_top_eigvecs(wk.Z.p, dim, k, nullptr, out_re, out_im, s));
         // the dense library solver has returned non-finite eigenvectors for some inputs
         // (diagonal matrices of order >= 100): check the kept ones
+        // (the work buffers are the eigensolver's own: callers such as the self-test pass a
+        // state without reduction buffers)
         double nrm = 0;
-        HIPCHK(norm2<double>(out_re, out_im, (int64_t)dim * k, st->partial.p, st->dscal.p + 2, s));
-        HIPCHK(hipMemcpyAsync(&nrm, st->dscal.p + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+        wk.nrm.ensure(1024 + 1, s);
+        HIPCHK(norm2<double>(out_re, out_im, (int64_t)dim * k, wk.nrm.p, wk.nrm.p + 1024, s));
+        HIPCHK(hipMemcpyAsync(&nrm, wk.nrm.p + 1024, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (!std::isfinite(nrm)) fail(MPS_ERR_NUMERIC, "eigensolver returned non-finite eigenvectors");
         return;

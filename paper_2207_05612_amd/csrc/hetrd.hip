@@ -75,6 +75,10 @@ __device__ inline double2 ld_coh(const double2* p) {
     const unsigned long long y = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return make_double2(__builtin_bit_cast(double, x), __builtin_bit_cast(double, y));
 }
+__device__ inline void st_coh1(double* p, double v) {
+    __hip_atomic_store((unsigned long long*)p, __builtin_bit_cast(unsigned long long, v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ inline void st_coh(double2* p, double2 v) {
     unsigned long long* q = (unsigned long long*)p;
     __hip_atomic_store(q, __builtin_bit_cast(unsigned long long, v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -83,16 +87,20 @@ __device__ inline void st_coh(double2* p, double2 v) {
 
 // Cross-workgroup protocol (release / acquire at agent scope).  Every value
 // another workgroup reads is written with a device-coherent atomic store
-// (st_coh) and read with a device-coherent atomic load (ld_coh).  A producer's
-// threads issue an agent-scope release fence, join the workgroup barrier, and
-// one thread then stores the flag; a consumer thread polls the flag with
-// relaxed loads and issues an agent-scope acquire fence once it has seen the
-// value, before the workgroup barrier after which its data loads are issued.
-// The fence pair makes every store before the producer's fence visible to every
-// load after the consumer's fence (fence-fence synchronisation of the HIP /
-// C++ memory model), so the protocol does not rest on hardware ordering.
+// (st_coh) and read with a device-coherent atomic load (ld_coh).  A producer
+// joins its workgroup barrier; then its first wavefront issues an agent-scope
+// release fence and one thread stores the flag.  A consumer's first wavefront
+// polls the flags with relaxed loads, issues an agent-scope acquire fence once
+// every flag has the value, and the workgroup barrier that follows orders the
+// data loads of every wavefront after it.  The barriers carry the ordering
+// inside a workgroup and the fence pair (fence-fence synchronisation of the
+// HIP / C++ memory model) carries it across workgroups, so the protocol does
+// not rest on hardware ordering.  One fence per workgroup and step: each one
+// costs an L2 write-back (release) or invalidation (acquire).  The reflectors
+// and the tridiagonal entries are written with coherent stores as well, so
+// the L2 holds no dirty lines that a release would have to write back.
 
-// One thread waits until *flag >= target.  False on abort or time-out.
+// One thread waits until *flag >= target (relaxed polls).  False on abort or time-out.
 __device__ bool wait_geq(int* flag, int target, int* abort_flag) {
     int spins = 0;
     while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -103,15 +111,27 @@ __device__ bool wait_geq(int* flag, int target, int* abort_flag) {
         }
         __builtin_amdgcn_s_sleep(1);
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return true;
 }
 
-// Release this workgroup's earlier stores, then set *flag = val.
+// Wavefront 0 waits until flags[0 .. count) all reach target, then acquires; the caller's
+// workgroup barrier follows.  False (in wavefront 0) on abort or time-out.
+__device__ bool wait_all_acquire(int* flags, int count, int target, int* abort_flag) {
+    bool ok = true;
+    if (threadIdx.x < 64) {
+        for (int f = threadIdx.x; f < count && ok; f += 64) ok = wait_geq(flags + f, target, abort_flag);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    return ok;
+}
+
+// After the workgroup barrier, release this workgroup's earlier stores and set *flag = val.
 __device__ void publish(int* flag, int val) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(flag, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (threadIdx.x == 0) __hip_atomic_store(flag, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 __device__ inline double wave_sum(double v) {
@@ -329,20 +349,19 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrArgs g) {
             for (int q = 0; q < TQ; ++q) {
                 const int r = tid + TT * q;
                 if (r < n) {
-                    g.vh_re[(int64_t)i * n + r] = v[q].x;
-                    g.vh_im[(int64_t)i * n + r] = -v[q].y;
+                    st_coh1(&g.vh_re[(int64_t)i * n + r], v[q].x);
+                    st_coh1(&g.vh_im[(int64_t)i * n + r], -v[q].y);
                 }
-                if (r == i) g.d[i] = d_i;
+                if (r == i) st_coh1(&g.d[i], d_i);
             }
             if (tid == 0) {
-                g.e[i] = beta;
-                g.tau[i] = tau;
+                st_coh1(&g.e[i], beta);
+                st_coh(&g.tau[i], tau);
             }
         }
         // ---- wait for every workgroup's y entries and partial y^H v (and the
         //      column published one step earlier)
-        bool ok = true;
-        if (tid < P) ok = wait_geq(g.wg_flag + tid, i + 1, g.abort_flag);
+        const bool ok = wait_all_acquire(g.wg_flag, P, i + 1, g.abort_flag);
         if (__syncthreads_or(!ok)) return;
         // every published value of this step is complete now: issue the loads of y and of
         // the partial y^H v together, so that their latencies overlap
