@@ -23,7 +23,13 @@ from measured errors):
     step (local tensor, environments, intermediate products) and the FP32
     accumulation over long contractions.
 Where the target bound applies (u * sum kappa small), the test asserts the
-target itself.  Every test also reports the worst gap and the MPS-MPS overlap
+target itself.
+
+Per-layer f_delta: 1e-4 relative (the target of the reduced-precision
+paths) for FP32 and split BF16x3.  The two-term split BF16x2 has unit
+roundoff 2^-16, so the same first-order constant gives C_FIRST_ORDER * 2^-16
+= 1.5e-4: it cannot promise the 1e-4 target and is held to that bound (its
+use is the 1e-3 amplitude budget, not the fidelity target).  Every test also reports the worst gap and the MPS-MPS overlap
 error 1 - |<phi_gpu|phi_oracle>|^2, and asserts the overlap error against the
 square of the same bound (for normalised states it is at most the squared
 L2 distance).
@@ -38,6 +44,10 @@ FP64, FP32, BF16X2, BF16X3 = 0, 1, 2, 3
 AMP_TARGET = {FP64: 1e-9, FP32: 1e-5, BF16X2: 1e-3, BF16X3: 1e-3}
 UNIT_ROUNDOFF = {FP64: 2.0 ** -53, FP32: 2.0 ** -24, BF16X3: 2.0 ** -23, BF16X2: 2.0 ** -16}
 C_FIRST_ORDER = 10.0
+# 1 - |<a|b>|^2 of two unit FP64 MPS is computed with an absolute error of a few
+# hundred ulps (a chain of transfer-matrix products, then a cancellation near 1)
+OVERLAP_FLOOR = 1e-13
+F_TARGET = {FP32: 1e-4, BF16X3: 1e-4, BF16X2: C_FIRST_ORDER * UNIT_ROUNDOFF[BF16X2]}
 
 
 def layer_chunks(step_log, layer_sizes):

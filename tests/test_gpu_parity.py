@@ -27,8 +27,9 @@ import parity_bounds as pb
 pytestmark = pytest.mark.gpu
 
 FP64, FP32, BF16X2, BF16X3 = mps.MPS_FP64, mps.MPS_FP32, mps.MPS_BF16X2, mps.MPS_BF16X3
-F_TOL = {FP64: 1e-10, FP32: 1e-4, BF16X2: 1e-4, BF16X3: 1e-4}
+F_TOL = {FP64: 1e-10, **pb.F_TARGET}
 AMP_TOL = pb.AMP_TARGET
+OVERLAP_FLOOR = pb.OVERLAP_FLOOR
 EPS = {FP64: 2.2e-16, FP32: 1.2e-7, BF16X3: 2.4e-7, BF16X2: 3.1e-5}
 
 
@@ -92,7 +93,7 @@ def check_amplitudes(prec, err, st, ora, n_sweeps, label):
     print("%s prec=%d amplitude rel-L2 %.2e (bound %.2e; target %.0e) overlap error %.2e worst gap %.2e "
           "sum kappa %.3g" % (label, prec, err, bound, AMP_TOL[prec], ovl, pb.worst_gap(ora.step_log), ksum))
     assert err < bound
-    assert ovl <= max(bound ** 2, 1e-15)
+    assert ovl <= max(bound ** 2, OVERLAP_FLOOR)
     return bound
 
 
