@@ -484,6 +484,24 @@ def test_closed_amplitude_exact_regime(d1, update):
         assert abs(fwd.log_f) < 1e-12 and abs(bwd.log_f) < 1e-12
 
 
+@pytest.mark.parametrize("d1,d2", [(0, 8), (2, 3), (3, 1), (5, 3)])
+def test_closed_amplitude_middle_part(d1, d2):
+    """The exact middle part of depth d2 (Sec. IV.C, D2): in the exact regime (chi = 64) the
+    amplitude equals the statevector's for every split; with d1 = 0 and d2 = D the two MPS
+    are the product states |0> and |x> and the amplitude is exact at any chi (chi = 1 here),
+    so the sandwich contraction alone is pinned against the brute-force statevector."""
+    from oracle import closed
+    c = circuits.plain_fp64_workload(0)
+    psi = sv.run(c)
+    rng = np.random.default_rng(10 * d1 + d2)
+    chi = 1 if (d1 == 0 and d2 == len(c.layers)) else 64
+    for _ in range(3):
+        bits = rng.integers(0, 2, size=c.n)
+        amp, fwd, bwd = closed.closed_amplitude(c, bits, chi=chi, n_sweeps=2, d1=d1, d2=d2)
+        idx = int("".join(str(int(b)) for b in bits), 2)
+        assert abs(amp - psi[idx]) < 1e-12 * max(1.0, abs(psi[idx])) + 1e-13
+
+
 def test_closed_amplitude_truncated_bounds():
     """With truncation, the closed-mode amplitude is |<bwd|fwd>| <= 1 and its error against the
     exact amplitude is bounded by the infidelity of the two MPS (Cauchy-Schwarz with
