@@ -273,6 +273,20 @@ mps_status mps_expect_zz(const mps_state* state, int i, int j, double* value);
  * on return.  re, im: HOST outputs. */
 mps_status mps_overlap(const mps_state* bra, const mps_state* ket, double* re, double* im);
 
+/* <bra| U_K ... U_1 |ket> with the K = n_layers layers contracted exactly
+ * between the two states: the closed simulation mode's middle part of depth
+ * D2 (Sec. IV.C), between the backward MPS (bra) and the forward MPS (ket).
+ * The layers follow the rules of apply_layers_dmrg (gates of layer 1, then
+ * layer 2, ...; n_gates[l] records each; one-qubit gates act first in each
+ * layer); they form the same MPO as a K-layer compression step, contracted
+ * site by site as E_{k+1} = B_k^H (E_k A_k W_k) in FP64 (nothing truncated).
+ * n_layers = 0 is mps_overlap.  MPS_ERR_ARG when an environment
+ * D_bra x (MPO bond) x D_ket would exceed 2^31 complex values.  Neither state
+ * is modified; the bra's stream is synchronised first and the work runs on the
+ * ket's stream, complete on return.  re, im: HOST outputs. */
+mps_status mps_overlap_layers(const mps_state* bra, mps_state* ket, const mps_gate* gates,
+                              const int* n_gates, int n_layers, double* re, double* im);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /* Kernel classes timed when profiling is on (hipEvents around every launch on

@@ -1,10 +1,12 @@
 """Closed simulation mode (Sec. IV.C): amplitudes <x|U|0> of chosen bitstrings.
 
-The circuit is cut after layer d1.  The forward MPS U_{d1} ... U_1 |0> and the
-backward MPS U_{d1+1}^dagger ... U_D^dagger |x> are both built by the
-library's compression step; the amplitude is their overlap
-<backward|forward> (mps_overlap), with fidelity estimate F~_forward *
-F~_backward.
+The circuit is cut into three parts: the forward MPS U_{d1} ... U_1 |0> and
+the backward MPS U_{d1+d2+1}^dagger ... U_D^dagger |x> are both built by the
+library's compression step, and the middle part of depth d2 (the paper's D2)
+is contracted exactly between them (mps_overlap_layers):
+  <x|U|0> = <backward| U_{d1+d2} ... U_{d1+1} |forward>,
+with fidelity estimate F~_forward * F~_backward.  d2 = 0 is the plain overlap
+(mps_overlap).
 
 A layer of this library applies its one-qubit gates before its two-qubit
 gates, so the daggered layers are regrouped: the first backward layer holds
@@ -13,7 +15,7 @@ one-qubit gates of layer l together with the daggered two-qubit gates of
 layer l - 1, and the last one the daggered one-qubit gates of layer d1 + 1.
 
 This module only composes calls of the C ABI (mps_create with init_bits,
-apply_layer_dmrg / apply_layer_dmrg_single_site, mps_overlap).
+apply_layer_dmrg / apply_layer_dmrg_single_site, mps_overlap_layers).
 """
 from __future__ import annotations
 
@@ -35,33 +37,39 @@ def backward_layers(layers: Sequence) -> List[list]:
     return out
 
 
+def _check_split(circuit, d1: int, d2: int) -> None:
+    if not (0 <= d1 and 0 <= d2 and d1 + d2 <= len(circuit.layers)):
+        raise ValueError("0 <= d1, 0 <= d2 and d1 + d2 <= depth required")
+
+
 def closed_amplitude(circuit, bits, chi: int, n_sweeps: int, d1: int, precision: int = mps.MPS_FP64,
-                     update: str = "two-site"):
-    """(<x|U|0>, forward state, backward state) with the cut after layer d1 (0 <= d1 <= depth).
+                     update: str = "two-site", d2: int = 0):
+    """(<x|U|0>, forward state, backward state): forward MPS of layers [0, d1), exact middle
+    part [d1, d1 + d2), backward MPS of layers [d1 + d2, D).
 
     The caller closes the returned states (MPS.close)."""
-    if not 0 <= d1 <= len(circuit.layers):
-        raise ValueError("0 <= d1 <= depth required")
+    _check_split(circuit, d1, d2)
     bits = np.asarray(bits, dtype=np.uint8)
     fwd = mps.MPS(circuit.n, None, max_chi=chi, precision=precision)
     for layer in circuit.layers[:d1]:
         fwd.apply_layer_dmrg(layer, chi, n_sweeps, update=update)
     bwd = mps.MPS(circuit.n, bits, max_chi=chi, precision=precision)
-    for layer in backward_layers(circuit.layers[d1:]):
+    for layer in backward_layers(circuit.layers[d1 + d2:]):
         bwd.apply_layer_dmrg(layer, chi, n_sweeps, update=update)
-    return mps.overlap(bwd, fwd), fwd, bwd
+    return mps.overlap_layers(bwd, circuit.layers[d1:d1 + d2], fwd), fwd, bwd
 
 
 class ClosedAmplitudes:
     """Amplitudes <x|U|0> of one circuit for many bitstrings: the forward MPS of the
-    first d1 layers is built once, a backward MPS per bitstring."""
+    first d1 layers is built once, a backward MPS per bitstring, the next d2 layers are
+    the exact middle part."""
 
     def __init__(self, circuit, chi: int, n_sweeps: int, d1: int, precision: int = mps.MPS_FP64,
-                 update: str = "two-site"):
-        if not 0 <= d1 <= len(circuit.layers):
-            raise ValueError("0 <= d1 <= depth required")
+                 update: str = "two-site", d2: int = 0):
+        _check_split(circuit, d1, d2)
         self.circuit, self.chi, self.n_sweeps, self.precision, self.update = circuit, chi, n_sweeps, precision, update
-        self.back = backward_layers(circuit.layers[d1:])
+        self.middle = circuit.layers[d1:d1 + d2]
+        self.back = backward_layers(circuit.layers[d1 + d2:])
         self.fwd = mps.MPS(circuit.n, None, max_chi=chi, precision=precision)
         for layer in circuit.layers[:d1]:
             self.fwd.apply_layer_dmrg(layer, chi, n_sweeps, update=update)
@@ -73,7 +81,7 @@ class ClosedAmplitudes:
             for layer in self.back:
                 bwd.apply_layer_dmrg(layer, self.chi, self.n_sweeps, update=self.update)
             self.log_f_backward.append(bwd.fidelity()["log_F_tilde"])
-            return mps.overlap(bwd, self.fwd)
+            return mps.overlap_layers(bwd, self.middle, self.fwd)
         finally:
             bwd.close()
 

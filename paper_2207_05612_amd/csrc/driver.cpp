@@ -1948,6 +1948,57 @@ mps_status mps_overlap(const mps_state* bra_c, const mps_state* ket_c, double* r
     });
 }
 
+mps_status mps_overlap_layers(const mps_state* bra_c, mps_state* ket, const mps_gate* gates, const int* n_gates,
+                              int n_layers, double* re, double* im) {
+    if (n_layers == 0) return mps_overlap(bra_c, ket, re, im);
+    return run_guarded([&] {
+        check_state(bra_c);
+        check_state(ket);
+        if (!re || !im) fail(MPS_ERR_ARG, "NULL output");
+        if (bra_c->n != ket->n) fail(MPS_ERR_ARG, "the states have different numbers of sites");
+        if (n_layers < 0 || n_layers > 64) fail(MPS_ERR_ARG, "n_layers must be in [0, 64]");
+        if (!n_gates) fail(MPS_ERR_ARG, "n_gates is NULL");
+        int64_t total = 0;
+        for (int l = 0; l < n_layers; ++l) {
+            if (n_gates[l] < 0) fail(MPS_ERR_ARG, "negative gate count");
+            total += n_gates[l];
+        }
+        if (total > 0 && !gates) fail(MPS_ERR_ARG, "gates is NULL");
+        const mps_state* bra = bra_c;
+        const int n = ket->n;
+        LayerMpo mpo = build_step_mpo(n, gates, n_gates, n_layers);      // validates the gates
+        for (int c = 0; c <= n; ++c) {
+            const double env = (double)bra->bond[c] * (double)mpo.w[c] * (double)ket->bond[c];
+            if (env > (double)(1LL << 31))
+                fail(MPS_ERR_ARG, "the middle layers are too wide: an environment of " + std::to_string(env) +
+                                      " complex values at bond " + std::to_string(c));
+        }
+        HIPCHK(hipStreamSynchronize(bra->stream));
+        const hipStream_t s = ket->stream;
+        {
+            // the left-environment recursion of the compression step with the bra as the
+            // fitted state: E_{j+1} = B_j^H (E_j A_j W_j), FP64 contractions
+            Engine<double> e(ket, 1);
+            e.mpo = std::move(mpo);
+            e.setup();
+            for (int c = 0; c <= n; ++c) e.cb[c] = bra->bond[c];
+            for (int j = 0; j < n; ++j) {
+                e.left_block(0, j);
+                forward_tensor(bra, j, e.U64, s);
+                e.finish_left(0, j, typename Engine<double>::Trunc{bra->bond[j + 1], 0.0, 0.0, true}, true);
+            }
+            double v[2] = {0, 0};
+            HIPCHK(hipMemcpyAsync(&v[0], e.env[n].re(), sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(&v[1], e.env[n].im(), sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            *re = v[0];
+            *im = v[1];
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        flush_timings(ket);
+    });
+}
+
 mps_status mps_set_profiling(mps_state* st, int on) {
     return run_guarded([&] {
         if (!st) fail(MPS_ERR_ARG, "state is NULL");

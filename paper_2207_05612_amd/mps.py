@@ -43,7 +43,8 @@ EXPORTS = ("mps_create", "mps_destroy", "apply_layer_dmrg", "apply_layer_dmrg_si
            "mps_expect_zz", "mps_set_profiling", "mps_kernel_stats", "mps_kernel_selftest_cgemm",
            "mps_kernel_selftest_eigh", "mps_overlap", "apply_layers_dmrg",
            "sv_create", "sv_destroy", "sv_apply_layer", "sv_amplitudes", "sv_compare_mps",
-           "sv_schmidt_weights", "apply_layers_dmrg_bonds", "mps_eigensolver_counts")
+           "sv_schmidt_weights", "apply_layers_dmrg_bonds", "mps_eigensolver_counts",
+           "mps_overlap_layers")
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -111,6 +112,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mps_kernel_selftest_cgemm": (i32, [i32, i32, i32, i32, i32, i32, dp, dp, dp]),
         "mps_kernel_selftest_eigh": (i32, [i32, dp, i32, dp, dp, ip]),
         "mps_overlap": (i32, [P, P, dp, dp]),
+        "mps_overlap_layers": (i32, [P, P, P, ip, i32, dp, dp]),
         "apply_layers_dmrg": (i32, [P, P, ip, i32, i32, i32, i32, dp]),
         "sv_create": (i32, [i32, P, P, ctypes.POINTER(P)]),
         "sv_destroy": (i32, [P]),
@@ -331,6 +333,19 @@ def overlap(bra: "MPS", ket: "MPS") -> complex:
     """<bra|ket> (see mps_overlap)."""
     re, im = ctypes.c_double(), ctypes.c_double()
     _check(_lib.mps_overlap(bra._h, ket._h, ctypes.byref(re), ctypes.byref(im)))
+    return complex(re.value, im.value)
+
+
+def overlap_layers(bra: "MPS", layers, ket: "MPS") -> complex:
+    """<bra| U_K ... U_1 |ket> with the layers contracted exactly (see mps_overlap_layers)."""
+    recs = [np.ascontiguousarray(l if isinstance(l, np.ndarray) else circuits.pack_layer(l),
+                                 dtype=circuits.GATE_DTYPE) for l in layers]
+    counts = np.ascontiguousarray([len(r) for r in recs], dtype=np.int32)
+    allrec = np.ascontiguousarray(np.concatenate(recs) if recs else np.zeros(0, circuits.GATE_DTYPE),
+                                  dtype=circuits.GATE_DTYPE)
+    re, im = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.mps_overlap_layers(bra._h, ket._h, allrec.ctypes.data if len(allrec) else None, _iptr(counts),
+                                   len(recs), ctypes.byref(re), ctypes.byref(im)))
     return complex(re.value, im.value)
 
 

@@ -7,6 +7,11 @@
   daggered rest from |x>) against the statevector amplitude in the exact
   regime (FP64: 1e-10 relative to the largest amplitude magnitude), and
   against the oracle's closed mode in the truncated regime (FP64: 1e-9).
+* The exact middle part of depth d2 (mps_overlap_layers, Sec. IV.C D2): the
+  statevector amplitude in the exact regime for d2 = 1..3 at several cuts,
+  the whole circuit as the middle part between the product states |0> and
+  <x| (exact at chi = 1), and the oracle's closed mode with d2 = 1..3 in the
+  truncated regime, FP64 and the split precision.
 """
 import numpy as np
 import pytest
@@ -93,6 +98,53 @@ def test_closed_amplitude_truncated_matches_oracle(update):
         assert abs(bwd.fidelity()["log_F_tilde"] - obwd.log_f) < 1e-9
         fwd.close()
         bwd.close()
+
+
+@pytest.mark.parametrize("d1,d2", [(0, 1), (2, 2), (3, 3), (5, 3), (0, 8)])
+def test_closed_amplitude_middle_part_exact(d1, d2):
+    """Exact regime (chi = 64 = 2^(n/2)), and d1 = 0, d2 = D at chi = 1 (both MPS are product
+    states; the whole circuit is the exact middle part): the statevector amplitude."""
+    c = circuits.plain_fp64_workload(0)
+    psi = sv.run(c)
+    scale = np.abs(psi).max()
+    chi = 1 if d2 == len(c.layers) else 64
+    rng = np.random.default_rng(10 * d1 + d2)
+    for _ in range(2):
+        bits = rng.integers(0, 2, size=c.n)
+        amp, fwd, bwd = closed.closed_amplitude(c, bits, chi=chi, n_sweeps=2, d1=d1, d2=d2)
+        assert abs(amp - psi[index_of(bits)]) < 1e-10 * scale, (amp, psi[index_of(bits)])
+        fwd.close()
+        bwd.close()
+
+
+@pytest.mark.parametrize("prec", [FP64, mps.MPS_BF16X3])
+@pytest.mark.parametrize("d2", [1, 2, 3])
+def test_closed_amplitude_middle_part_truncated(d2, prec):
+    """16 qubits, chi = 8, cut after layer 3 with d2 middle layers, against the oracle's closed
+    mode with the same split (its middle part is the dense MPO of the layers); FP64 to 1e-9,
+    split precision to 1e-3 relative (the amplitude budget of that path)."""
+    c = circuits.random_circuit(circuits.grid_from_shape(4, 4), 8, seed=5)
+    rng = np.random.default_rng(20 + d2)
+    for _ in range(2):
+        bits = rng.integers(0, 2, size=c.n)
+        amp, fwd, bwd = closed.closed_amplitude(c, bits, chi=8, n_sweeps=2, d1=3, d2=d2, precision=prec)
+        want, _, _ = oclosed.closed_amplitude(c, bits, chi=8, n_sweeps=2, d1=3, d2=d2)
+        print("d2=%d prec=%d amp %.4e%+.4ej oracle %.4e%+.4ej" % (d2, prec, amp.real, amp.imag, want.real, want.imag))
+        tol = 1e-9 if prec == FP64 else 1e-3
+        assert abs(amp - want) < tol * max(abs(want), 1e-3)
+        fwd.close()
+        bwd.close()
+
+
+def test_overlap_layers_errors():
+    c = circuits.plain_fp64_workload(0)
+    a = mps.MPS(c.n, None, max_chi=4, precision=FP64)
+    b = mps.MPS(c.n, None, max_chi=4, precision=FP64)
+    with pytest.raises(mps.MpsError) as e:
+        mps.overlap_layers(a, [[(0, 1, np.eye(4)), (1, 2, np.eye(4))]], b)     # overlapping gates
+    assert e.value.code == mps.MPS_ERR_ARG
+    assert abs(mps.overlap_layers(a, [], b) - 1.0) < 1e-14
+    assert abs(mps.overlap_layers(a, [[(0, -1, circuits.SQRT_X)]], b) - circuits.SQRT_X[0, 0]) < 1e-14
 
 
 def test_metropolis_chain_matches_oracle():
