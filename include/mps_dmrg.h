@@ -349,6 +349,31 @@ mps_status mps_kernel_selftest_cgemm(int precision, int opa, int opb, int M, int
  * MPS_EIGENSOLVER = rocsolver | persistent, default persistent). */
 mps_status mps_kernel_selftest_eigh(int n, const double* a, int method, double* w, double* z, int* used);
 
+/* The complex GEMM of mps_kernel_selftest_cgemm on DEVICE operands, for
+ * callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation.  It calls no
+ * allocator.  The split-K partial sums that long contractions need live in a
+ * library-owned static device array of 64 MiB per GPU (held until the process
+ * ends); products whose partial sums exceed it (2 M N chunks FP32 values,
+ * chunks = the library's split of K) fail with MPS_ERR_ARG before any work.
+ *   precision  MPS_FP64 (double operands) or MPS_FP32 / MPS_BF16X2 /
+ *              MPS_BF16X3 (float operands); the split precisions take
+ *              opa = 0, opb = 1 only.
+ *   opa, opb, M, N, K  as for mps_kernel_selftest_cgemm.
+ *   a_re .. c_im  DEVICE pointers to planar (separate real and imaginary)
+ *              row-major matrices with leading dimensions lda, ldb, ldc (in
+ *              elements); c is overwritten.  The caller owns all of them.
+ *   hip_stream stream the work is queued on (NULL = default stream); the call
+ *              returns without waiting.
+ * All calls on one GPU share its scratch array: calls that overlap in time on
+ * that GPU (different streams or threads) race and give wrong results; calls
+ * on one stream are ordered and safe.  Results equal those of
+ * mps_kernel_selftest_cgemm on the same operands (same kernels, same split). */
+mps_status mps_cgemm_noalloc(int precision, int opa, int opb, int M, int N, int K,
+                             const void* a_re, const void* a_im, int64_t lda,
+                             const void* b_re, const void* b_im, int64_t ldb,
+                             void* c_re, void* c_im, int64_t ldc, void* hip_stream);
+
 /* ---- The exact state, for measuring the simulation (Sec. VI, VII) ---------
  * The brute-force statevector U|0> (the perfect state of eq:F-sup) held in
  * device memory: FP64 planar, 2^n amplitudes, chain site q is bit n-1-q of

@@ -30,6 +30,7 @@
 #include <thread>
 #include <array>
 #include <functional>
+#include <mutex>
 #include <cmath>
 #include <complex>
 #include <cstdlib>
@@ -2138,6 +2139,86 @@ extern "C" mps_status mps_kernel_selftest_cgemm(int precision, int opa, int opb,
         } else if (precision == MPS_FP32) selftest_cgemm_impl<float>(opa, opb, M, N, K, a, b, c);
         else if (precision == MPS_FP64) selftest_cgemm_impl<double>(opa, opb, M, N, K, a, b, c);
         else fail(MPS_ERR_ARG, "unknown precision");
+    });
+}
+
+// ============================================== allocation-free GEMM ====
+// Split-K partial sums of mps_cgemm_noalloc live in this file-scope device
+// array (one copy per GPU, held until the process ends).  Host code never
+// passes its name to a kernel: the address is taken once per device with
+// hipGetSymbolAddress and kept in g_scratch_ptr.
+constexpr size_t SCRATCH_FLOATS = (size_t)16 << 20;            // 64 MiB
+static __device__ __align__(256) float scratch[SCRATCH_FLOATS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[MAX_DEVICES] = {};
+
+// The scratch array of the current device (its address is resolved on first use).
+float* scratch_of_current_device() {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) fail(MPS_ERR_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            fail(MPS_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = (float*)ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" mps_status mps_cgemm_noalloc(int precision, int opa, int opb, int M, int N, int K, const void* a_re,
+                                        const void* a_im, int64_t lda, const void* b_re, const void* b_im,
+                                        int64_t ldb, void* c_re, void* c_im, int64_t ldc, void* hip_stream) {
+    return run_guarded([&] {
+        if (M < 1 || N < 1 || K < 1) fail(MPS_ERR_ARG, "M, N and K must be >= 1");
+        if (!a_re || !a_im || !b_re || !b_im || !c_re || !c_im) fail(MPS_ERR_ARG, "NULL operand");
+        if (opa != OP_N && opa != OP_C) fail(MPS_ERR_ARG, "opa must be 0 (N) or 2 (C)");
+        if (opb != OP_N && opb != OP_T && opb != OP_C) fail(MPS_ERR_ARG, "opb must be 0, 1 or 2");
+        if (lda < (opa == OP_N ? K : M) || ldb < (opb == OP_N ? N : K) || ldc < N)
+            fail(MPS_ERR_ARG, "leading dimension smaller than the row length");
+        if (precision != MPS_FP64 && precision != MPS_FP32 && !is_split(precision))
+            fail(MPS_ERR_ARG, "unknown precision");
+        if (is_split(precision) && (opa != OP_N || opb != OP_T))
+            fail(MPS_ERR_ARG, "the split-precision kernel takes opa = 0, opb = 1");
+        const hipStream_t s = (hipStream_t)hip_stream;
+        if (precision == MPS_FP64) {
+            HIPCHK(cgemm_f64(opa, opb, M, N, K, {(const double*)a_re, (const double*)a_im, lda},
+                             {(const double*)b_re, (const double*)b_im, ldb}, {(double*)c_re, (double*)c_im, ldc}, s));
+            return;
+        }
+        // the split-K policy of the compression step and of mps_kernel_selftest_cgemm
+        const int req = splitk_for(M, N, K);
+        const int ks = splitk_chunks(K, req, 16);
+        const CView<float> A{(const float*)a_re, (const float*)a_im, lda};
+        const CView<float> B{(const float*)b_re, (const float*)b_im, ldb};
+        const int terms = precision == MPS_BF16X2 ? 2 : 3;
+        if (ks <= 1) {
+            const CViewMut<float> C{(float*)c_re, (float*)c_im, ldc};
+            if (is_split(precision))
+                HIPCHK(cgemm_bf16_nt(terms, M, N, K, A, B, C, s));
+            else
+                HIPCHK(cgemm_f32(opa, opb, M, N, K, A, B, C, s));
+            return;
+        }
+        const size_t need = 2 * (size_t)M * (size_t)N * (size_t)ks;
+        if (need > SCRATCH_FLOATS)
+            fail(MPS_ERR_ARG, "split-K partial sums need " + std::to_string(need * sizeof(float)) +
+                                  " bytes, more than the " + std::to_string(SCRATCH_FLOATS * sizeof(float)) +
+                                  "-byte scratch array");
+        float* ws = scratch_of_current_device();
+        float* ws_re = ws;
+        float* ws_im = ws + (size_t)M * N * ks;
+        if (is_split(precision))
+            HIPCHK(cgemm_bf16_nt_splitk(terms, M, N, K, A, B, ws_re, ws_im, req, s));
+        else
+            HIPCHK(cgemm_f32_splitk(opa, opb, M, N, K, A, B, ws_re, ws_im, req, s));
+        HIPCHK(splitk_reduce(ws_re, ws_im, ks, M, N, (float*)c_re, (float*)c_im, ldc, s));
     });
 }
 

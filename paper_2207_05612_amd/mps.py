@@ -43,7 +43,7 @@ EXPORTS = ("mps_create", "mps_destroy", "apply_layer_dmrg", "apply_layer_dmrg_si
            "mps_expect_zz", "mps_set_profiling", "mps_kernel_stats", "mps_kernel_selftest_cgemm",
            "mps_kernel_selftest_eigh", "mps_overlap", "apply_layers_dmrg",
            "sv_create", "sv_destroy", "sv_apply_layer", "sv_amplitudes", "sv_compare_mps",
-           "sv_schmidt_weights", "apply_layers_dmrg_bonds", "mps_eigensolver_counts",
+           "sv_schmidt_weights", "apply_layers_dmrg_bonds", "mps_eigensolver_counts", "mps_cgemm_noalloc",
            "mps_overlap_layers")
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -94,6 +94,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     sig = {
         "mps_create": (i32, [i32, P, i32, i32, P, ctypes.POINTER(MpsAllocator), ctypes.POINTER(P)]),
         "mps_eigensolver_counts": (i32, [P, ctypes.POINTER(i64)]),
+        "mps_cgemm_noalloc": (i32, [i32, i32, i32, i32, i32, i32, P, P, i64, P, P, i64, P, P, i64, P]),
         "mps_destroy": (i32, [P]),
         "apply_layer_dmrg": (i32, [P, P, i32, i32, i32, dp]),
         "apply_layer_dmrg_single_site": (i32, [P, P, i32, i32, i32, dp]),
@@ -327,6 +328,17 @@ def selftest_cgemm(precision: int, opa: int, opb: int, a: np.ndarray, b: np.ndar
     _check(lib.mps_kernel_selftest_cgemm(precision, opa, opb, M, N, K, _dptr(a.view(np.float64)),
                                          _dptr(b.view(np.float64)), _dptr(c.view(np.float64))))
     return c
+
+
+def cgemm_noalloc(precision: int, opa: int, opb: int, M: int, N: int, K: int, a, lda: int, b, ldb: int, c,
+                  ldc: int, stream: Optional[int] = None) -> None:
+    """mps_cgemm_noalloc on device planar operands: a, b, c are (re, im) pairs of device
+    pointers (ints, e.g. torch tensors' data_ptr()); queued on `stream`, not awaited."""
+    lib = load_library()
+    if stream is None:
+        stream = current_stream()
+    _check(lib.mps_cgemm_noalloc(precision, opa, opb, M, N, K, a[0], a[1], lda, b[0], b[1], ldb, c[0], c[1], ldc,
+                                 stream))
 
 
 def overlap(bra: "MPS", ket: "MPS") -> complex:
