@@ -100,26 +100,34 @@ __device__ inline void st_coh(double2* p, double2 v) {
 // and the tridiagonal entries are written with coherent stores as well, so
 // the L2 holds no dirty lines that a release would have to write back.
 
-// One thread waits until *flag >= target (relaxed polls).  False on abort or time-out.
-__device__ bool wait_geq(int* flag, int target, int* abort_flag) {
-    int spins = 0;
-    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-        if (++spins > SPIN_LIMIT) {
-            __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-    return true;
-}
-
-// Wavefront 0 waits until flags[0 .. count) all reach target, then acquires; the caller's
-// workgroup barrier follows.  False (in wavefront 0) on abort or time-out.
+// Wavefront 0 waits until flags[0 .. count) all reach target (count <= 256), then
+// acquires; the caller's workgroup barrier follows.  Each lane polls flags lane,
+// lane + 64, lane + 128 and lane + 192 with independent loads, so one poll round costs
+// one memory round trip.  False (in wavefront 0) on abort or time-out.
 __device__ bool wait_all_acquire(int* flags, int count, int target, int* abort_flag) {
     bool ok = true;
     if (threadIdx.x < 64) {
-        for (int f = threadIdx.x; f < count && ok; f += 64) ok = wait_geq(flags + f, target, abort_flag);
+        const int lane = threadIdx.x;
+        int spins = 0;
+        while (true) {
+            bool done = true;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int f = lane + 64 * k;
+                if (f < count) done &= __hip_atomic_load(flags + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
+            }
+            if (done) break;
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = false;
+                break;
+            }
+            if (++spins > SPIN_LIMIT) {
+                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     return ok;
@@ -194,7 +202,9 @@ __device__ inline int sum16_index(int lane) {
 // A[r, c_j] -= v[r] conj(w_cj) + w[r] conj(v_cj) over the trailing rows
 #define UPDATE_COL(j)                                                  \
     do {                                                               \
-        const double2 wc_ = wcol[j], vc_ = vcol[j];                    \
+        const double2 vc_ = vcol[buf][j];                              \
+        const double2 ty_ = cmul(tau, ycol[buf][j]);                   \
+        const double2 wc_ = make_double2(ty_.x + alw * vc_.x, ty_.y + alw * vc_.y); \
         _Pragma("unroll") for (int q = 0; q < TQ; ++q) {               \
             const int r = tid + TT * q;                                \
             if (r < i + 1 || r >= n) continue;                         \
@@ -204,12 +214,15 @@ __device__ inline int sum16_index(int lane) {
         }                                                              \
     } while (0)
 
+// The small shared values of a step are double-buffered by the parity of the step: a
+// step's three workgroup barriers (after the partial sums, in the publication, after the
+// wait) keep every wavefront within one step of the others, so a buffer is rewritten only
+// after every read of it in the step before the previous one.
 __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrArgs g) {
     __shared__ double2 alds[TC - TCR][TMAXN];
-    __shared__ double red[NWAVE][2 * TC + 1];
-    __shared__ double bc[2 * TC + 1];
-    __shared__ double2 vcol[TC], wcol[TC], ycol[TC], xcol[TC], a1col[TC];
-    __shared__ double2 alpha_s;
+    __shared__ double red[2][NWAVE][2 * TC + 1];
+    __shared__ double2 vcol[2][TC], ycol[2][TC], xcol[2][TC], a1col[2][TC];
+    __shared__ double2 alpha_s[2];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wg = blockIdx.x, P = g.P, n = g.n;
@@ -238,8 +251,8 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrArgs g) {
         x[q] = r < n ? g.a[r] : make_double2(0.0, 0.0);
     }
     if (tid < TC) {
-        xcol[tid] = make_double2(0.0, 0.0);
-        a1col[tid] = make_double2(0.0, 0.0);
+        xcol[0][tid] = xcol[1][tid] = make_double2(0.0, 0.0);
+        a1col[0][tid] = a1col[1][tid] = make_double2(0.0, 0.0);
     }
     __syncthreads();
 
@@ -250,11 +263,11 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrArgs g) {
         for (int q = 0; q < TQ; ++q) {
             const int r = tid + TT * q;
             if (r == i + 1) {
-                alpha_s = x[q];
+                alpha_s[buf] = x[q];
 #pragma unroll
-                for (int j = 0; j < TC; ++j) a1col[j] = A_GET(j, q, r);
+                for (int j = 0; j < TC; ++j) a1col[buf][j] = A_GET(j, q, r);
             }
-            if (r < n && r >= wg && (r - wg) % P == 0) xcol[(r - wg) / P] = x[q];
+            if (r < n && r >= wg && (r - wg) % P == 0) xcol[buf][(r - wg) / P] = x[q];
         }
         // ---- one reduction: |x[i+2:]|^2 and z_c = sum_{r >= i+2} conj(A[r, c]) x[r]
         double part = 0.0;
@@ -280,20 +293,17 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrArgs g) {
         }
         {
             const double zs = wave_sum16(zp, lane);
-            if ((lane & 3) == 0) red[wave][sum16_index(lane)] = zs;
+            if ((lane & 3) == 0) red[buf][wave][sum16_index(lane)] = zs;
         }
         part = wave_sum(part);
-        if (lane == 0) red[wave][2 * TC] = part;
+        if (lane == 0) red[buf][wave][2 * TC] = part;
         __syncthreads();
-        if (tid <= 2 * TC) {
-            double sum = 0.0;
-            for (int w = 0; w < NWAVE; ++w) sum += red[w][tid];
-            bc[tid] = sum;
-        }
-        __syncthreads();
-        // ---- reflector: H^H x = (beta, 0, ...), v = (1, x[i+2:] / (alpha - beta))
-        const double xnorm2 = bc[2 * TC];
-        const double2 alpha = alpha_s;
+        // ---- reflector: H^H x = (beta, 0, ...), v = (1, x[i+2:] / (alpha - beta));
+        //      every thread sums the wavefronts' partial |x|^2 itself
+        double xnorm2 = 0.0;
+#pragma unroll
+        for (int w = 0; w < NWAVE; ++w) xnorm2 += red[buf][w][2 * TC];
+        const double2 alpha = alpha_s[buf];
         const double anorm2 = alpha.x * alpha.x + alpha.y * alpha.y + xnorm2;
         // tau = 0 (H = I) when x is already (real alpha, 0, ...) or negligible
         const bool reflect = !(xnorm2 == 0.0 && alpha.y == 0.0) && anorm2 > 1e-300;
@@ -317,30 +327,42 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrArgs g) {
             else if (r >= i + 2 && r < n)
                 v[q] = cmul(x[q], scale);
         }
-        if (tid < TC) {
-            const int c = wg + P * tid;
-            double2 vc = make_double2(0.0, 0.0), yc = make_double2(0.0, 0.0);
-            if (c >= i + 1 && c < n) {
-                vc = c == i + 1 ? make_double2(1.0, 0.0) : cmul(xcol[tid], scale);
-                // y_c = conj(A[i+1, c]) + scale z_c
-                const double2 a1 = a1col[tid];
-                yc = cadd(make_double2(a1.x, -a1.y), cmul(scale, make_double2(bc[2 * tid], bc[2 * tid + 1])));
-                st_coh(&g.ybuf[(int64_t)buf * n + c], yc);
+        if (wave == 0) {
+            // lanes 0 .. TC-1: y and v of the owned columns, and this workgroup's share of y^H v
+            double2 pdt = make_double2(0.0, 0.0);
+            if (tid < TC) {
+                const int c = wg + P * tid;
+                double2 vc = make_double2(0.0, 0.0), yc = make_double2(0.0, 0.0);
+                if (c >= i + 1 && c < n) {
+                    double zr = 0.0, zi = 0.0;
+#pragma unroll
+                    for (int w = 0; w < NWAVE; ++w) {
+                        zr += red[buf][w][2 * tid];
+                        zi += red[buf][w][2 * tid + 1];
+                    }
+                    vc = c == i + 1 ? make_double2(1.0, 0.0) : cmul(xcol[buf][tid], scale);
+                    // y_c = conj(A[i+1, c]) + scale z_c
+                    const double2 a1 = a1col[buf][tid];
+                    yc = cadd(make_double2(a1.x, -a1.y), cmul(scale, make_double2(zr, zi)));
+                    st_coh(&g.ybuf[(int64_t)buf * n + c], yc);
+                }
+                vcol[buf][tid] = vc;
+                ycol[buf][tid] = yc;
+                pdt = cjmul(yc, vc);
             }
-            vcol[tid] = vc;
-            ycol[tid] = yc;
+            static_assert(TC == 8, "the y^H v share sums lanes 0..7");
+#pragma unroll
+            for (int o = 4; o > 0; o >>= 1) {
+                pdt.x += __shfl_xor(pdt.x, o);
+                pdt.y += __shfl_xor(pdt.y, o);
+            }
+            if (tid == 0) st_coh(&g.pdot[(int64_t)buf * P + wg], pdt);
         }
         // d_i before x is reused
         double d_i = 0.0;
 #pragma unroll
         for (int q = 0; q < TQ; ++q)
             if (tid + TT * q == i) d_i = x[q].x;
-        __syncthreads();
-        if (tid == 0) {
-            double2 pd = make_double2(0.0, 0.0);
-            for (int j = 0; j < TC; ++j) pd = cadd(pd, cjmul(ycol[j], vcol[j]));
-            st_coh(&g.pdot[(int64_t)buf * P + wg], pd);
-        }
         publish(g.wg_flag + wg, i + 1);
         // the owner of column i records d_i, e_i, tau_i and the reflector; issued after
         // the flag so that the publication does not wait for these stores
@@ -372,18 +394,12 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrArgs g) {
             yq[q] = (r >= i + 1 && r < n) ? ld_coh(&g.ybuf[(int64_t)buf * n + r]) : make_double2(0.0, 0.0);
         }
         const double2 y1 = ld_coh(&g.ybuf[(int64_t)buf * n + i + 1]);
-        double pdr = tid < P ? ld_coh(&g.pdot[(int64_t)buf * P + tid]).x : 0.0;
+        // every wavefront sums all P shares of y^H v itself (no barrier)
+        double pdr = 0.0;
+        for (int k = lane; k < P; k += 64) pdr += ld_coh(&g.pdot[(int64_t)buf * P + k]).x;
         pdr = wave_sum(pdr);
-        if (lane == 0) red[wave][0] = pdr;
-        __syncthreads();
-        if (tid == 0) {
-            double sum = 0.0;
-            for (int w = 0; w < NWAVE; ++w) sum += red[w][0];
-            bc[0] = sum;
-        }
-        __syncthreads();
         // w = tau y + alpha_w v, alpha_w = -|tau|^2 (y^H v) / 2
-        const double alw = -0.5 * (tau.x * tau.x + tau.y * tau.y) * bc[0];
+        const double alw = -0.5 * (tau.x * tau.x + tau.y * tau.y) * pdr;
         double2 w[TQ];
 #pragma unroll
         for (int q = 0; q < TQ; ++q) {
@@ -394,14 +410,9 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrArgs g) {
                 w[q] = make_double2(ty.x + alw * v[q].x, ty.y + alw * v[q].y);
             }
         }
-        if (tid < TC) {
-            const double2 ty = cmul(tau, ycol[tid]);
-            wcol[tid] = make_double2(ty.x + alw * vcol[tid].x, ty.y + alw * vcol[tid].y);
-        }
         // w at row i+1 (v there is 1): the scalar of the next column's update
         const double2 ty1 = cmul(tau, y1);
         const double2 w1 = make_double2(ty1.x + alw, ty1.y);
-        __syncthreads();   // wcol visible to every wave before the update
         // ---- rank-2 update of the owned columns; column i+2 first, then published
         const int j2 = (i + 2 < n && wg == (i + 2) % P) ? (i + 2) / P : -1;
         if (j2 >= 0) {
@@ -436,7 +447,6 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrArgs g) {
                 x[q] = make_double2(cv.x - t1.x - w[q].x, cv.y - t1.y - w[q].y);
             }
         }
-        __syncthreads();
     }
     // last diagonal entry: column n-1 after step n-2
     if (wg == 0) {
