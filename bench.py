@@ -65,8 +65,12 @@ def parse(argv=None):
     p.add_argument("--fp64-steps", type=int, default=8,
                    help="timed layers also run with FP64 contractions (from the first timed layer; 0 = skip)")
     p.add_argument("--cpu-baseline", type=int, default=1)
-    p.add_argument("--samples", type=int, default=65536,
-                   help="bitstrings sampled from the final MPS of the timed run (0 = skip)")
+    p.add_argument("--samples", type=int, default=1000000,
+                   help="bitstrings sampled from the final MPS of the timed run, timed, then scored by "
+                        "linear XEB against the same MPS's probabilities (0 = skip)")
+    p.add_argument("--xeb-fp64", type=int, default=0,
+                   help="also build the all-FP64 MPS over the same layers and score the samples with its "
+                        "probabilities (1 = yes; about 20 more layer applications)")
     p.add_argument("--single-site", type=int, default=0,
                    help="also time the single-site update (split and FP64) on the same layers (1 = yes)")
     p.add_argument("--multilayer-chi", type=int, default=0,
@@ -75,6 +79,9 @@ def parse(argv=None):
                    help="closed-mode amplitudes timed on the 54-qubit circuit at chi = 64 (0 = skip)")
     p.add_argument("--statevector", type=int, default=0,
                    help="qubits of an exact-statevector leg (28, 32 or 33; 0 = skip)")
+    p.add_argument("--batched", type=int, default=0,
+                   help="instances of the 64-instance ragged batch (n 20..40, depth 8..20, chi 32..512) run "
+                        "through apply_layer_dmrg_batched, split precision (0 = skip)")
     p.add_argument("--progress", action="store_true", help="print one line per layer to stderr")
     p.add_argument("--calibrate-copy-mib", type=int, default=0,
                    help="fill, then sum, a device buffer of this many MiB (HBM counter calibration)")
@@ -112,9 +119,10 @@ def log(progress, msg):
 
 
 def run_layers(mps, circuit, precision, chi, sweeps, warmup, steps, torch, progress=False, samples=0,
-               update="two-site", tag=""):
+               update="two-site", tag="", keep=False):
     """Warm up on layers [0, warmup), then time layers [warmup, warmup + steps) one call each.
-    Returns per-layer seconds, f_delta, per-layer kernel statistics and the final state's data."""
+    Returns per-layer seconds, f_delta, per-layer kernel statistics and the final state's data
+    (and the state itself when keep is set; the caller closes it)."""
     st = mps.MPS(circuit.n, None, max_chi=chi, precision=precision)
     for d in range(warmup):
         f = st.apply_layer_dmrg(circuit.layers[d], chi, sweeps, update=update)
@@ -154,9 +162,24 @@ def run_layers(mps, circuit, precision, chi, sweeps, warmup, steps, torch, progr
         sampling = {"samples": samples, "seconds": ts, "samples_per_s": samples / ts,
                     "algorithmic_tflops": flops / ts / 1e12, "max_bond": max(bonds)}
         log(progress, "%ssampled %d bitstrings in %.2f s" % (tag, samples, ts))
-    st.close()
-    return {"secs": secs, "f": fs, "per_layer": per_layer, "stats": stats, "bonds": bonds, "fid": fid,
-            "sampling": sampling, "counters": counters, "bonds_per_layer": bonds_per_layer}
+    out = {"secs": secs, "f": fs, "per_layer": per_layer, "stats": stats, "bonds": bonds, "fid": fid,
+           "sampling": sampling, "counters": counters, "bonds_per_layer": bonds_per_layer}
+    if keep:
+        out["state"] = st
+    else:
+        st.close()
+    return out
+
+
+def xeb_leg(analysis, sampler, reference, n_samples, torch, label):
+    """eq:FB-estim over n_samples bitstrings drawn from `sampler`, scored with the
+    probabilities of `reference` (FP64 amplitude evaluation in the library)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    est, sd, _ = analysis.linear_xeb(sampler, reference, n_samples, seed=12345)
+    torch.cuda.synchronize()
+    return {"samples": n_samples, "F_B": est, "F_B_standard_error": sd, "reference": label,
+            "seconds": time.perf_counter() - t0}
 
 
 def tflops(stat):
@@ -346,6 +369,35 @@ def closed_leg(circuits, torch, n_amp):
             "F_tilde_forward": f_fwd, "abs_amplitudes": [abs(v) for v in vals]}
 
 
+def batched_leg(mps, circuits, torch, count, sweeps, progress):
+    """The first `count` instances of circuits.batched_instances(64), each on its own stream,
+    one apply_layer_dmrg_batched call per layer over the instances still active; reported as
+    instance-layers per second (a first untimed layer warms the kernels up)."""
+    insts = circuits.batched_instances(64)[:count]
+    streams = [torch.cuda.Stream() for _ in insts]
+    states = [mps.MPS(c.n, None, max_chi=chi, precision=mps.MPS_BF16X3, stream=s.cuda_stream)
+              for (c, chi), s in zip(insts, streams)]
+    mps.apply_layer_dmrg_batched(states, [c.layers[0] for c, _ in insts], [chi for _, chi in insts], sweeps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    for d in range(1, max(len(c.layers) for c, _ in insts)):
+        act = [i for i, (c, _) in enumerate(insts) if d < len(c.layers)]
+        mps.apply_layer_dmrg_batched([states[i] for i in act], [insts[i][0].layers[d] for i in act],
+                                     [insts[i][1] for i in act], sweeps)
+        done += len(act)
+        log(progress, "batched layer %d: %d instances" % (d, len(act)))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    eps = [st.fidelity()["eps_tilde"] for st in states]
+    for st in states:
+        st.close()
+    return {"instances": count, "instance_layers": done, "seconds": dt, "instance_layers_per_s": done / dt,
+            "precision": "bf16x3", "n_sweeps": sweeps, "mean_eps_tilde": float(sum(eps) / len(eps)),
+            "workload": "circuits.batched_instances(64)[:%d] (n 20..40, depth 8..20, chi 32..512, widths 4..6, "
+                        "Haar), layers 1.. timed" % count}
+
+
 def statevector_leg(mps, circuits, torch, n_qubits):
     """Gate passes of the exact statevector (HBM-bound: every pass reads and writes all 2^n
     FP64 complex amplitudes) on a Sycamore-layout circuit of n_qubits."""
@@ -413,7 +465,8 @@ def main():
     steps = max(1, min(args.steps, DEPTH - warmup))
     prec_name = args.precision
     prec = getattr(mps, "MPS_" + prec_name.upper())
-    run = run_layers(mps, c, prec, args.chi, args.sweeps, warmup, steps, torch, args.progress, args.samples)
+    run = run_layers(mps, c, prec, args.chi, args.sweeps, warmup, steps, torch, args.progress, args.samples,
+                     keep=args.samples > 0)
     dt = sum(run["secs"])
     value = steps / dt
     stats = run["stats"]
@@ -479,7 +532,20 @@ def main():
             sum(320.0 * min(b, args.chi) ** 3 for bonds in run["bonds_per_layer"] for b in bonds[1:-1])
             * (1 + args.sweeps) / (trunc_ms * 1e-3) / 1e12 if trunc_ms > 0 else 0.0)
     if run["sampling"]:
+        from paper_2207_05612_amd import analysis
         out["sampling"] = run["sampling"]
+        st = run.pop("state")
+        log(args.progress, "xeb against the sampled MPS")
+        out["sampling"]["xeb_self"] = xeb_leg(analysis, st, st, args.samples, torch,
+                                              "the sampled MPS itself (2^N sum_x p(x)^2 - 1)")
+        if args.xeb_fp64:
+            ref = run_layers(mps, c, mps.MPS_FP64, args.chi, args.sweeps, warmup, steps, torch, args.progress,
+                             tag="xeb fp64 ", keep=True)["state"]
+            out["sampling"]["xeb_fp64"] = xeb_leg(analysis, st, ref, args.samples, torch,
+                                                  "the all-FP64 path's MPS over the same layers (the oracle's "
+                                                  "arithmetic on the GPU; proxy for the oracle MPS)")
+            ref.close()
+        st.close()
     if args.fp64_steps and prec_name != "fp64":
         n64 = min(args.fp64_steps, steps)
         r64 = run_layers(mps, c, mps.MPS_FP64, args.chi, args.sweeps, warmup, n64, torch, args.progress,
@@ -511,6 +577,8 @@ def main():
         out["closed"] = closed_leg(circuits, torch, args.closed_amplitudes)
     if args.statevector:
         out["statevector"] = statevector_leg(mps, circuits, torch, args.statevector)
+    if args.batched:
+        out["batched"] = batched_leg(mps, circuits, torch, args.batched, args.sweeps, args.progress)
     if args.cpu_baseline:
         log(args.progress, "cpu baseline")
         out["cpu_baseline"] = cpu_baseline(args.chi, c.n, args.sweeps, classes, run["bonds_per_layer"])

@@ -37,6 +37,19 @@ def chaotic_optimum_error(chi: int, n_qubits: int, depth: int) -> float:
     return -math.expm1(2.0 * log_f / (n_qubits * depth))
 
 
+def linear_xeb(sampler, reference, n_samples: int, seed: int):
+    """Linear cross-entropy (eq:FB-estim): F_B ~ 2^N <P(x)> - 1 over bitstrings x drawn from
+    the MPS `sampler` (exact sequential sampling), P(x) = |<x|reference>|^2 the probabilities of
+    the MPS `reference` (the exact state's when it is the exact state; a proxy otherwise).
+    Returns (estimate, standard error, bitstrings)."""
+    bits = sampler.sample(n_samples, seed)
+    p = np.abs(reference.amplitudes(bits)) ** 2
+    scale = 2.0 ** sampler.n
+    est = float(scale * np.mean(p) - 1.0)
+    sd = float(scale * np.std(p) / math.sqrt(n_samples))
+    return est, sd, bits
+
+
 def error_rate(fid: float, n_2q: int) -> float:
     """eq:epsilon: 1 - F^(1/N_2g) (0 before any two-qubit gate)."""
     if n_2q <= 0:

@@ -1751,31 +1751,35 @@ mps_status mps_amplitude(const mps_state* st_c, int n_strings, const uint8_t* bi
         const hipStream_t s = st->stream;
         int maxD = 1;
         for (int c = 0; c <= n; ++c) maxD = std::max(maxD, st->bond[c]);
-        const int64_t S = n_strings;
+        // strings are evaluated in chunks that keep the two row buffers under ~1.5 GiB
+        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n_strings, ((int64_t)1 << 26) / maxD));
         Planar<double> v, u, a;
-        v.ensure(S * maxD, s);
-        u.ensure(S * 2 * maxD, s);
+        v.ensure(chunk * maxD, s);
+        u.ensure(chunk * 2 * maxD, s);
         Raw<uint8_t> bdev;
-        bdev.ensure(S, s);
-        std::vector<uint8_t> col(S);
-        HIPCHK(fill_planar<double>(v.re(), v.im(), S, 1.0, s));
-        for (int k = 0; k < n; ++k) {
-            forward_tensor(st, k, a);
-            const int64_t Dk = st->bond[k], Dn = st->bond[k + 1];
-            gemm<double>(st, MPS_KCLASS_OTHER, OP_N, OP_N, S, 2 * Dn, Dk, v.re(), v.im(), Dk, a.re(), a.im(), 2 * Dn,
-                         u.re(), u.im(), 2 * Dn);
-            for (int64_t r = 0; r < S; ++r) col[r] = bits[r * n + k];
-            HIPCHK(hipMemcpyAsync(bdev.p, col.data(), S, hipMemcpyHostToDevice, s));
-            HIPCHK(select_rows<double>(u.re(), u.im(), S, (int)Dn, 0, bdev.p, 0, 0, k, v.re(), v.im(), nullptr, s));
+        bdev.ensure(chunk, s);
+        std::vector<uint8_t> col(chunk);
+        std::vector<double> h(2 * chunk);
+        for (int64_t s0 = 0; s0 < n_strings; s0 += chunk) {
+            const int64_t S = std::min<int64_t>(chunk, n_strings - s0);
+            HIPCHK(fill_planar<double>(v.re(), v.im(), S, 1.0, s));
+            for (int k = 0; k < n; ++k) {
+                forward_tensor(st, k, a);
+                const int64_t Dk = st->bond[k], Dn = st->bond[k + 1];
+                gemm<double>(st, MPS_KCLASS_OTHER, OP_N, OP_N, S, 2 * Dn, Dk, v.re(), v.im(), Dk, a.re(), a.im(),
+                             2 * Dn, u.re(), u.im(), 2 * Dn);
+                for (int64_t r = 0; r < S; ++r) col[r] = bits[(s0 + r) * n + k];
+                HIPCHK(hipMemcpyAsync(bdev.p, col.data(), S, hipMemcpyHostToDevice, s));
+                HIPCHK(select_rows<double>(u.re(), u.im(), S, (int)Dn, 0, bdev.p, 0, 0, k, v.re(), v.im(), nullptr, s));
+                HIPCHK(hipStreamSynchronize(s));
+            }
+            HIPCHK(hipMemcpyAsync(h.data(), v.re(), sizeof(double) * S, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(h.data() + S, v.im(), sizeof(double) * S, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-        }
-        std::vector<double> h(2 * S);
-        HIPCHK(hipMemcpyAsync(h.data(), v.re(), sizeof(double) * S, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(h.data() + S, v.im(), sizeof(double) * S, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        for (int64_t r = 0; r < S; ++r) {
-            re_im[2 * r] = h[r];
-            re_im[2 * r + 1] = h[S + r];
+            for (int64_t r = 0; r < S; ++r) {
+                re_im[2 * (s0 + r)] = h[r];
+                re_im[2 * (s0 + r) + 1] = h[S + r];
+            }
         }
         v.release(s); u.release(s); a.release(s); bdev.release(s);
         flush_timings(st);

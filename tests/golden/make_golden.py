@@ -40,6 +40,9 @@ CASES = {
     "sycamore54_chi32_seed0_d6": dict(kind="syc54", seed=0, chi=32, sweeps=2, depth=6),
     # the same workload, first 10 layers at chi 256 (the bonds saturate from layer 4 on)
     "sycamore54_chi256_seed0_d10": dict(kind="syc54", seed=0, chi=256, sweeps=2, depth=10),
+    # ragged batch (circuits.batched_instances(64)): the instances with chi <= 128 that the
+    # oracle finishes in minutes, full depth
+    **{"batched64_inst%d" % i: dict(kind="batched64", index=i, sweeps=2) for i in (1, 8, 9, 10, 17)},
     # QAOA MaxCut on a random 3-regular graph of 54 nodes, p = 4, the first 8 of the seeded
     # (gamma, beta) sets, chi 64, 2 sweeps, every brick layer of the SWAP network
     "qaoa54_p4_chi64_sets8": dict(kind="qaoa54", seed=0, chi=64, sweeps=2, p=4, sets=8),
@@ -47,6 +50,8 @@ CASES = {
 
 
 def circuit_for(case):
+    if case["kind"] == "batched64":
+        return circuits.batched_instances(64)[case["index"]][0]
     if case["kind"] == "grid36":
         return circuits.grid36_workload(case["seed"])
     if case["kind"] == "syc54":
@@ -91,6 +96,8 @@ def make(name):
     if case["kind"] == "qaoa54":
         return make_qaoa(name, case)
     c = circuit_for(case)
+    if case["kind"] == "batched64":
+        case = dict(case, chi=circuits.batched_instances(64)[case["index"]][1], depth=len(c.layers))
     t0 = time.time()
     st = dmrg.run_circuit(c, chi=case["chi"], n_sweeps=case["sweeps"], depth=case["depth"])
     bits = bitstrings(c.n)

@@ -42,11 +42,15 @@ FP64, FP32, BF16X2, BF16X3 = mps.MPS_FP64, mps.MPS_FP32, mps.MPS_BF16X2, mps.MPS
 
 def golden_cases(kind=None):
     names = sorted(os.path.basename(p)[:-5] for p in glob.glob(os.path.join(GOLDEN, "*.json")))
-    return [nm for nm in names if (kind is None and not nm.startswith("qaoa")) or (kind and nm.startswith(kind))]
+    if kind is None:
+        return [nm for nm in names if nm.startswith(("grid36", "sycamore54"))]
+    return [nm for nm in names if nm.startswith(kind)]
 
 
 def circuit_of(rec):
     case = rec["case"]
+    if case["kind"] == "batched64":
+        return circuits.batched_instances(64)[case["index"]][0]
     if case["kind"] == "grid36":
         return circuits.grid36_workload(case["seed"])
     return circuits.sycamore_like_54_workload(case["seed"])
@@ -121,6 +125,43 @@ def test_batched_matches_single_and_oracle():
         amp = states[i].amplitudes(bits)
         want = np.array([dmrg.amplitude(ora, b) for b in bits])
         assert np.linalg.norm(amp - want) / np.linalg.norm(want) < 1e-8
+
+
+@pytest.mark.parametrize("prec", [FP64, BF16X3])
+def test_batched_config4_subset_matches_golden(prec):
+    """The instances of the 64-instance ragged batch (circuits.batched_instances) whose oracle
+    runs are stored under tests/golden (n 21..37, chi 32..128, depth 8..19), run together
+    through apply_layer_dmrg_batched, one call per layer with the instances still active:
+    per-layer f_delta against the oracle within 1e-9 (FP64) / 1e-4 (split), log F~ and N_2g."""
+    import torch
+    names = golden_cases("batched64")
+    if not names:
+        pytest.skip("no batched golden cases written")
+    recs = [json.load(open(os.path.join(GOLDEN, nm + ".json"))) for nm in names]
+    insts = circuits.batched_instances(64)
+    cs = [insts[r["case"]["index"]][0] for r in recs]
+    chis = [insts[r["case"]["index"]][1] for r in recs]
+    assert chis == [r["case"]["chi"] for r in recs]
+    streams = [torch.cuda.Stream() for _ in cs]
+    states = [mps.MPS(c.n, None, max_chi=chi, precision=prec, stream=s.cuda_stream)
+              for c, chi, s in zip(cs, chis, streams)]
+    fs = [[] for _ in cs]
+    for d in range(max(len(c.layers) for c in cs)):
+        act = [i for i, c in enumerate(cs) if d < len(c.layers)]
+        f = mps.apply_layer_dmrg_batched([states[i] for i in act], [cs[i].layers[d] for i in act],
+                                         [chis[i] for i in act], 2)
+        for k, i in enumerate(act):
+            fs[i].append(f[k])
+    tol = 1e-9 if prec == FP64 else pb.F_TARGET[prec]
+    for i, (r, st) in enumerate(zip(recs, states)):
+        want = np.array(r["layer_f"])
+        rel = np.max(np.abs(np.array(fs[i]) - want) / want)
+        print("%s prec=%d max rel f_delta err %.2e" % (names[i], prec, rel))
+        assert rel < tol
+        fid = st.fidelity()
+        assert fid["n_2q"] == r["n_2q"]
+        assert abs(fid["log_F_tilde"] - r["log_f_tilde"]) < tol * len(want)
+        st.close()
 
 
 def test_batched_argument_errors_leave_states_unchanged():

@@ -215,3 +215,24 @@ def test_depth_curve_matches_the_oracle():
         assert abs(rec["F_B_estimate"] - rec["F_B"]) < 5 * rec["F_B_estimate_sd"] + 1e-12
     print("depth F F~ F_B F_SVD:", [(r["depth"], round(r["F"], 4), round(r["F_tilde"], 4), round(r["F_B"], 4),
                                      round(r["F_SVD"], 4)) for r in recs])
+
+
+def test_linear_xeb_of_split_samples_against_oracle_probabilities():
+    """The bench's XEB leg at 20 qubits: bitstrings sampled from the split-precision MPS, scored
+    with the probabilities of the FP64 path's MPS (analysis.linear_xeb), against the exact value
+    2^N sum_x Q(x) P(x) - 1 with Q from the split MPS's statevector and P from the oracle's MPS
+    (eq:FB-sup / eq:FB-estim), within 5 standard errors."""
+    from paper_2207_05612_amd import analysis as gan
+    c = circuits.random_circuit(circuits.grid_from_shape(5, 4), 8, seed=4)
+    split = mps.MPS(c.n, None, max_chi=16, precision=mps.MPS_BF16X3)
+    ref = mps.MPS(c.n, None, max_chi=16, precision=FP64)
+    for layer in c.layers:
+        split.apply_layer_dmrg(layer, 16, 2)
+        ref.apply_layer_dmrg(layer, 16, 2)
+    ora = dmrg.run_circuit(c, chi=16, n_sweeps=2)
+    want = analysis.xeb_exact(dmrg.to_statevector(ora), split.statevector())
+    est, sd, bits = gan.linear_xeb(split, ref, 200000, seed=7)
+    print("XEB estimate %.5f +- %.5f, exact against the oracle MPS %.5f" % (est, sd, want))
+    assert abs(est - want) < 5 * sd
+    split.close()
+    ref.close()
