@@ -199,6 +199,11 @@ mps_status apply_layers_dmrg_bonds(mps_state* state, const mps_gate* gates, cons
  *   gates    batch host pointers; gates[i] holds n_gates[i] records.
  *   chi      batch bond dimensions, 1 <= chi[i] <= max_chi of state i.
  *   f_layers batch outputs (may be NULL): f_delta of each instance.
+ * The persistent tridiagonal reductions of the instances' truncations (orders
+ * 129..2048) that the threads reach within about 1 ms of each other run in one
+ * shared cooperative launch (up to 8 instances, 256 workgroups in total):
+ * the reduction is latency-bound and an order-n matrix occupies only n / 8
+ * workgroups, so concurrent instances fill the chip together.
  * Arguments of all instances are checked before any device work
  * (MPS_ERR_ARG leaves every state unchanged).  If an instance fails, the
  * first failing instance's status is returned with its message; that state
@@ -206,6 +211,11 @@ mps_status apply_layers_dmrg_bonds(mps_state* state, const mps_gate* gates, cons
 mps_status apply_layer_dmrg_batched(mps_state* const* states, int batch,
                                     const mps_gate* const* gates, const int* n_gates,
                                     const int* chi, int n_sweeps, double* f_layers);
+
+/* Shared tridiagonal-reduction launches of apply_layer_dmrg_batched since the
+ * library was loaded (*launches) and the reductions they carried
+ * (*reductions); either pointer may be NULL. */
+mps_status mps_batch_stats(int64_t* launches, int64_t* reductions);
 
 /* The fidelity estimate F~ = prod_delta f_delta (eq:Ftilde-sup), its natural
  * logarithm, the number of layers applied and the number of two-qubit gates

@@ -29,6 +29,8 @@
 #include <atomic>
 #include <thread>
 #include <array>
+#include <chrono>
+#include <condition_variable>
 #include <functional>
 #include <mutex>
 #include <cmath>
@@ -720,6 +722,107 @@ void gram_product(mps_state* st, int opa, int opb, int dim, int64_t K, const TIn
     }
 }
 
+// ===================================== batched tridiagonal reductions ====
+// Inside apply_layer_dmrg_batched, instances run on several host threads and
+// streams.  The persistent tridiagonal reduction of an order-n truncation is
+// latency-bound and occupies n / 8 workgroups, one per compute unit, in a
+// cooperative launch that no other cooperative launch can overlap; so the
+// reductions that the threads reach at about the same time are gathered and
+// run in one cooperative launch (at most hetrd_batch_max() instances and 256
+// workgroups).  The first thread to arrive leads: it waits until every worker
+// thread of the call has submitted, the launch is full, or a window of 1 ms has
+// passed, then makes its stream wait for the others' ready events, launches on
+// its stream, and records each member's done event there; every member's stream
+// then waits on its done event.
+struct TridiagBatcher {
+    struct Item {
+        TrRequest req;
+        hipStream_t s;
+        hipEvent_t ready, done;
+        int P;
+        bool launched = false;
+        hipError_t err = hipSuccess;
+    };
+    std::mutex mu;
+    std::condition_variable cv;
+    std::vector<Item*> pending;
+    int active = 0;                                   // worker threads that may still submit
+    std::chrono::microseconds window{1000};
+    int64_t launches = 0, reductions = 0;
+
+    void worker_done() {
+        std::lock_guard<std::mutex> lk(mu);
+        --active;
+        cv.notify_all();
+    }
+
+    // Launch a prefix of the pending items that fits (the front one always does).  Lock held.
+    void launch_front() {
+        std::vector<Item*> take, rest;
+        int sumP = 0;
+        for (Item* p : pending) {
+            if ((int)take.size() < hetrd_batch_max() && sumP + p->P <= 256) {
+                take.push_back(p);
+                sumP += p->P;
+            } else {
+                rest.push_back(p);
+            }
+        }
+        pending.swap(rest);
+        const hipStream_t ls = take[0]->s;
+        hipError_t err = hipSuccess;
+        for (Item* p : take)
+            if (err == hipSuccess && p->s != ls) err = hipStreamWaitEvent(ls, p->ready, 0);
+        std::vector<TrRequest> reqs;
+        for (Item* p : take) reqs.push_back(p->req);
+        if (err == hipSuccess) err = hetrd_persistent_multi(reqs.data(), (int)reqs.size(), ls);
+        if (err != hipSuccess) (void)hipGetLastError();
+        for (Item* p : take) {
+            if (err == hipSuccess) {
+                const hipError_t e2 = hipEventRecord(p->done, ls);
+                p->err = e2;
+            } else {
+                p->err = err;
+            }
+            p->launched = true;
+        }
+        ++launches;
+        reductions += (int64_t)take.size();
+        cv.notify_all();
+    }
+
+    hipError_t run(Item& it) {
+        std::unique_lock<std::mutex> lk(mu);
+        pending.push_back(&it);
+        cv.notify_all();
+        const auto t0 = std::chrono::steady_clock::now();
+        while (!it.launched) {
+            if (pending.front() == &it) {
+                int sumP = 0;
+                for (Item* p : pending) sumP += p->P;
+                const bool full = sumP >= 256 || (int)pending.size() >= hetrd_batch_max();
+                const bool all_here = (int)pending.size() >= active;
+                if (full || all_here || std::chrono::steady_clock::now() - t0 >= window) {
+                    launch_front();
+                    break;
+                }
+                cv.wait_until(lk, t0 + window);
+            } else {
+                cv.wait(lk);
+            }
+        }
+        return it.err;
+    }
+};
+
+// The batcher of the batched call this thread works for (NULL outside such calls).
+thread_local TridiagBatcher* g_batcher = nullptr;
+
+// Shared launches and the reductions they carried, over all batched calls (mps_batch_stats).
+struct BatchStats {
+    std::atomic<int64_t> launches{0}, reductions{0};
+} g_batch_stats;
+
 // ================================================== FP64 eigensolver ====
 enum { EIGH_ROCSOLVER = 0, EIGH_PERSISTENT = 1 };
 
@@ -793,8 +896,25 @@ void eigh_gram(mps_state* st, EighWork& wk, const double* re, const double* im, 
         int aborted = 1;
         {
             Timer tr(st, MPS_KCLASS_TRIDIAG, 16.0 / 3.0 * dim * (double)dim * dim, 16.0 * dim * (double)dim);
-            const hipError_t le = hetrd_persistent(wk.Z.p, dim, wk.evals.p, wk.evwork.p, wk.tau.p, wk.vh.re(),
-                                                   wk.vh.im(), wk.trws.p, wsb, &abort_dev, s);
+            hipError_t le;
+            if (g_batcher && hetrd_workgroups(dim) > 1) {
+                // gathered with the reductions of the other instances of the batched call
+                TridiagBatcher::Item it;
+                it.req = TrRequest{wk.Z.p, dim, wk.evals.p, wk.evwork.p, wk.tau.p, wk.vh.re(), wk.vh.im(),
+                                   wk.trws.p, wsb, &abort_dev};
+                it.s = s;
+                it.P = hetrd_workgroups(dim);
+                it.ready = get_event(st);
+                it.done = get_event(st);
+                HIPCHK(hipEventRecord(it.ready, s));
+                le = g_batcher->run(it);
+                if (le == hipSuccess) le = hipStreamWaitEvent(s, it.done, 0);
+                st->event_pool.push_back(it.ready);
+                st->event_pool.push_back(it.done);
+            } else {
+                le = hetrd_persistent(wk.Z.p, dim, wk.evals.p, wk.evwork.p, wk.tau.p, wk.vh.re(), wk.vh.im(),
+                                      wk.trws.p, wsb, &abort_dev, s);
+            }
             tr.done();
             if (le == hipSuccess) {
                 HIPCHK(hipMemcpyAsync(&aborted, abort_dev, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1629,22 +1749,30 @@ mps_status apply_layer_dmrg_batched(mps_state* const* states, int batch, const m
             (void)build_layer_mpo(states[i]->n, gates[i], n_gates[i]);
         }
         if (n_sweeps < 0) fail(MPS_ERR_ARG, "n_sweeps must be >= 0");
-        // one host thread per concurrently driven instance; each instance runs on its own stream
+        // one host thread per concurrently driven instance; each instance runs on its own
+        // stream, and their persistent tridiagonal reductions are gathered into shared launches
         const int n_threads = std::max(1, std::min(batch, 8));
         std::vector<mps_status> status(batch, MPS_OK);
         std::vector<std::string> msg(batch);
         std::vector<std::thread> pool;
         std::atomic<int> next(0);
+        TridiagBatcher batcher;
+        batcher.active = n_threads;
         for (int t = 0; t < n_threads; ++t)
             pool.emplace_back([&] {
+                g_batcher = &batcher;
                 for (int i = next.fetch_add(1); i < batch; i = next.fetch_add(1)) {
                     double f = 0;
                     status[i] = run_guarded([&] { apply_layer_impl(states[i], gates[i], n_gates[i], chi[i], n_sweeps, &f); });
                     if (status[i] != MPS_OK) msg[i] = g_last_error;
                     if (f_layers) f_layers[i] = f;
                 }
+                g_batcher = nullptr;
+                batcher.worker_done();
             });
         for (auto& th : pool) th.join();
+        g_batch_stats.launches += batcher.launches;
+        g_batch_stats.reductions += batcher.reductions;
         for (int i = 0; i < batch; ++i)
             if (status[i] != MPS_OK) fail(status[i], "instance " + std::to_string(i) + ": " + msg[i]);
     });
@@ -1864,6 +1992,13 @@ mps_status sample(mps_state* st, int64_t n_samples, uint64_t seed, uint64_t* bit
         if (st->prec == MPS_FP32) sample_impl<float>(st, n_samples, seed, bits);
         else if (is_split(st->prec)) sample_impl<float>(st, n_samples, seed, bits, true);
         else sample_impl<double>(st, n_samples, seed, bits);
+    });
+}
+
+mps_status mps_batch_stats(int64_t* launches, int64_t* reductions) {
+    return run_guarded([&] {
+        if (launches) *launches = g_batch_stats.launches.load();
+        if (reductions) *reductions = g_batch_stats.reductions.load();
     });
 }
 

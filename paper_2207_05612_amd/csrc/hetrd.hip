@@ -47,6 +47,7 @@ constexpr int TCR = 4;             // columns kept in registers (the rest in LDS
 constexpr int TMAXN = TT * TQ;     // 2048
 constexpr int NWAVE = TT / 64;
 constexpr int SPIN_LIMIT = 1 << 21;
+constexpr int TR_MAXB = 8;         // instances per launch
 
 struct TrArgs {
     const double2* a;    // n x n column-major, full Hermitian (not modified)
@@ -218,14 +219,26 @@ __device__ inline int sum16_index(int lane) {
 // step's three workgroup barriers (after the partial sums, in the publication, after the
 // wait) keep every wavefront within one step of the others, so a buffer is rewritten only
 // after every read of it in the step before the previous one.
-__global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrArgs g) {
+// Several independent reductions may share one cooperative launch (the reduction is
+// latency-bound; an order-n matrix occupies only n / 8 workgroups): instance i owns the
+// workgroups [first[i], first[i + 1]) and its own workspace and flags.
+struct TrBatch {
+    TrArgs a[TR_MAXB];
+    int first[TR_MAXB + 1];
+    int count;
+};
+
+__global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrBatch batch) {
     __shared__ double2 alds[TC - TCR][TMAXN];
     __shared__ double red[2][NWAVE][2 * TC + 1];
     __shared__ double2 vcol[2][TC], ycol[2][TC], xcol[2][TC], a1col[2][TC];
     __shared__ double2 alpha_s[2];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wg = blockIdx.x, P = g.P, n = g.n;
+    int inst = 0;
+    while (inst + 1 < batch.count && (int)blockIdx.x >= batch.first[inst + 1]) ++inst;
+    const TrArgs g = batch.a[inst];
+    const int wg = (int)blockIdx.x - batch.first[inst], P = g.P, n = g.n;
     const int64_t lda = g.lda;
     double2 areg[TCR][TQ];
     double2 x[TQ];          // column i at this thread's rows
@@ -702,37 +715,60 @@ hipError_t hermitian_full_colmajor(const double* re, const double* im, int n, do
     return hipGetLastError();
 }
 
-hipError_t hetrd_persistent(const double* a_z, int n, double* d, double* e, double* tau_z, double* vh_re,
-                            double* vh_im, void* ws, size_t ws_bytes, int** abort_flag, hipStream_t stream) {
-    if (n < 2 || n > TMAXN) return hipErrorInvalidValue;
-    if (ws_bytes < hetrd_workspace_bytes(n)) return hipErrorInvalidValue;
-    TrArgs g;
-    g.a = (const double2*)a_z;
-    g.vh_re = vh_re;
-    g.vh_im = vh_im;
-    g.n = n;
-    g.lda = n;
-    g.P = (n + TC - 1) / TC;
-    g.d = d;
-    g.e = e;
-    g.tau = (double2*)tau_z;
-    char* p = (char*)ws;
+namespace {
+// Arguments of one reduction over its workspace; clears its flags on `stream`.
+hipError_t prepare(const TrRequest& r, TrArgs& g, hipStream_t stream) {
+    if (r.n < 2 || r.n > TMAXN) return hipErrorInvalidValue;
+    if (r.ws_bytes < hetrd_workspace_bytes(r.n)) return hipErrorInvalidValue;
+    g.a = (const double2*)r.a_z;
+    g.vh_re = r.vh_re;
+    g.vh_im = r.vh_im;
+    g.n = r.n;
+    g.lda = r.n;
+    g.P = (r.n + TC - 1) / TC;
+    g.d = r.d;
+    g.e = r.e;
+    g.tau = (double2*)r.tau_z;
+    char* p = (char*)r.ws;
     g.colbuf = (double2*)p;
-    g.ybuf = g.colbuf + 2 * (size_t)n;
-    g.pdot = g.ybuf + 2 * (size_t)n;
+    g.ybuf = g.colbuf + 2 * (size_t)r.n;
+    g.pdot = g.ybuf + 2 * (size_t)r.n;
     int* flags = (int*)(g.pdot + 2 * (size_t)g.P);
     g.col_flag = flags;
     g.abort_flag = flags + 1;
     g.wg_flag = flags + 2;
-    *abort_flag = g.abort_flag;
-    hipError_t err = hipMemsetAsync(flags, 0, sizeof(int) * (size_t)(g.P + 2), stream);
-    if (err != hipSuccess) return err;
-    if (n <= SN) {
-        hipLaunchKernelGGL(hetrd_small_kernel, dim3(1), dim3(ST), 0, stream, g);
-        return hipGetLastError();
+    if (r.abort_flag) *r.abort_flag = g.abort_flag;
+    return hipMemsetAsync(flags, 0, sizeof(int) * (size_t)(g.P + 2), stream);
+}
+}  // namespace
+
+int hetrd_batch_max() { return TR_MAXB; }
+int hetrd_workgroups(int n) { return n <= SN ? 1 : (n + TC - 1) / TC; }
+
+hipError_t hetrd_persistent_multi(const TrRequest* reqs, int count, hipStream_t stream) {
+    if (count < 1 || count > TR_MAXB) return hipErrorInvalidValue;
+    TrBatch b;
+    b.count = count;
+    b.first[0] = 0;
+    for (int i = 0; i < count; ++i) {
+        if (reqs[i].n <= SN) return hipErrorInvalidValue;   // small orders use the one-workgroup kernel
+        const hipError_t err = prepare(reqs[i], b.a[i], stream);
+        if (err != hipSuccess) return err;
+        b.first[i + 1] = b.first[i] + b.a[i].P;
     }
-    void* args[] = {&g};
-    return hipLaunchCooperativeKernel((const void*)hetrd_kernel, dim3(g.P), dim3(TT), args, 0, stream);
+    void* args[] = {&b};
+    return hipLaunchCooperativeKernel((const void*)hetrd_kernel, dim3(b.first[count]), dim3(TT), args, 0, stream);
+}
+
+hipError_t hetrd_persistent(const double* a_z, int n, double* d, double* e, double* tau_z, double* vh_re,
+                            double* vh_im, void* ws, size_t ws_bytes, int** abort_flag, hipStream_t stream) {
+    const TrRequest r{a_z, n, d, e, tau_z, vh_re, vh_im, ws, ws_bytes, abort_flag};
+    if (n > SN) return hetrd_persistent_multi(&r, 1, stream);
+    TrArgs g;
+    const hipError_t err = prepare(r, g, stream);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(hetrd_small_kernel, dim3(1), dim3(ST), 0, stream, g);
+    return hipGetLastError();
 }
 
 }  // namespace mpsk

@@ -178,6 +178,25 @@ hipError_t hermitian_full_colmajor(const double* re, const double* im, int n, do
 // is non-zero when the kernel gave up waiting (results then invalid).
 hipError_t hetrd_persistent(const double* a_z, int n, double* d, double* e, double* tau_z, double* vh_re,
                             double* vh_im, void* ws, size_t ws_bytes, int** abort_flag, hipStream_t stream);
+// One reduction's arguments (as for hetrd_persistent).
+struct TrRequest {
+    const double* a_z;
+    int n;
+    double* d;
+    double* e;
+    double* tau_z;
+    double* vh_re;
+    double* vh_im;
+    void* ws;
+    size_t ws_bytes;
+    int** abort_flag;
+};
+// Up to hetrd_batch_max() reductions of order > 128 in one cooperative launch on `stream`
+// (instance i on hetrd_workgroups(n_i) workgroups; at most 256 in total); each instance
+// keeps its own workspace, flags and abort flag.
+int hetrd_batch_max();
+int hetrd_workgroups(int n);
+hipError_t hetrd_persistent_multi(const TrRequest* reqs, int count, hipStream_t stream);
 // T factors (wy_block() x wy_block(), planar row-major, block b at
 // b wy_block()^2) of the compact WY forms of nblk blocks of wy_block()
 // reflectors, from S_b = V_b^H V_b (same layout) and tau (interleaved,

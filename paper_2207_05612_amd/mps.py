@@ -44,7 +44,7 @@ EXPORTS = ("mps_create", "mps_destroy", "apply_layer_dmrg", "apply_layer_dmrg_si
            "mps_kernel_selftest_eigh", "mps_overlap", "apply_layers_dmrg",
            "sv_create", "sv_destroy", "sv_apply_layer", "sv_amplitudes", "sv_compare_mps",
            "sv_schmidt_weights", "apply_layers_dmrg_bonds", "mps_eigensolver_counts", "mps_cgemm_noalloc",
-           "mps_overlap_layers")
+           "mps_overlap_layers", "mps_batch_stats")
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -114,6 +114,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mps_kernel_selftest_eigh": (i32, [i32, dp, i32, dp, dp, ip]),
         "mps_overlap": (i32, [P, P, dp, dp]),
         "mps_overlap_layers": (i32, [P, P, P, ip, i32, dp, dp]),
+        "mps_batch_stats": (i32, [ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "apply_layers_dmrg": (i32, [P, P, ip, i32, i32, i32, i32, dp]),
         "sv_create": (i32, [i32, P, P, ctypes.POINTER(P)]),
         "sv_destroy": (i32, [P]),
@@ -404,6 +405,14 @@ def apply_layer_dmrg_batched(states: Sequence[MPS], layers, chis: Sequence[int],
     f = np.zeros(b)
     _check(lib.apply_layer_dmrg_batched(hs, b, gp, _iptr(ng), _iptr(ch), n_sweeps, _dptr(f)))
     return f
+
+
+def batch_stats():
+    """(shared tridiagonal-reduction launches, reductions they carried) of the batched calls."""
+    lib = load_library()
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.mps_batch_stats(ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def fidelity(state: MPS):

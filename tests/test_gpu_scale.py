@@ -164,6 +164,32 @@ def test_batched_config4_subset_matches_golden(prec):
         st.close()
 
 
+def test_batched_shared_tridiagonal_launches():
+    """Eight 20-qubit instances at chi 128 (Gram orders up to 256: persistent reductions of 32
+    workgroups each) through the batched call: their reductions share cooperative launches
+    (fewer launches than reductions), and every instance equals the same layers applied on its
+    own, bit for bit (an instance's workgroups compute the same whatever shares the launch)."""
+    import torch
+    insts = [circuits.random_circuit(circuits.grid_from_shape(5, 4), 7, seed=200 + i) for i in range(8)]
+    streams = [torch.cuda.Stream() for _ in insts]
+    states = [mps.MPS(c.n, None, max_chi=128, precision=FP64, stream=s.cuda_stream) for c, s in zip(insts, streams)]
+    l0, r0 = mps.batch_stats()
+    fb = np.array([mps.apply_layer_dmrg_batched(states, [c.layers[d] for c in insts], [128] * len(insts), 2)
+                   for d in range(7)]).T
+    l1, r1 = mps.batch_stats()
+    print("shared launches %d carrying %d reductions" % (l1 - l0, r1 - r0), [max(st.bond_dims()) for st in states])
+    assert r1 - r0 > 0 and l1 - l0 < r1 - r0
+    for i, c in enumerate(insts):
+        single = mps.MPS(c.n, None, max_chi=128, precision=FP64)
+        fs = np.array([single.apply_layer_dmrg(layer, 128, 2) for layer in c.layers])
+        assert np.array_equal(fs, fb[i])
+        bits = bitstrings(c.n, 8, seed=i)
+        assert np.array_equal(single.amplitudes(bits), states[i].amplitudes(bits))
+        assert states[i].counters()["fallback_library"] == 0
+        single.close()
+        states[i].close()
+
+
 def test_batched_argument_errors_leave_states_unchanged():
     a = mps.MPS(6, None, max_chi=4, precision=FP64)
     b = mps.MPS(6, None, max_chi=4, precision=FP64)
