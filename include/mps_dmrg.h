@@ -347,8 +347,9 @@ mps_status mps_kernel_selftest_cgemm(int precision, int opa, int opb, int M, int
  * local tensor) once on host data.  a: n x n Hermitian, HOST, interleaved
  * complex128, row-major (only the lower triangle, row >= column, is read).
  * method 0: rocSOLVER's dense solver; method 1: the persistent tridiagonal
- * reduction kernel (n <= 2048, else method 0 is used) followed by
- * rocSOLVER's tridiagonal divide and conquer and back-transformation.
+ * reduction kernel (n <= 2048, else method 0 is used) followed by the
+ * library's tridiagonal divide and conquer (mps_kernel_selftest_stedc) and
+ * the back-transformation.
  * Outputs (HOST): w[n] eigenvalues in ascending order; z[n * n] interleaved
  * complex128, column j at z[2 (i + j n)] is the eigenvector of w[j];
  * *used (may be NULL) the method that actually ran (method 1 falls back to
@@ -358,6 +359,20 @@ mps_status mps_kernel_selftest_cgemm(int precision, int opa, int opb, int M, int
  * Gram matrix (choose the method with the environment variable
  * MPS_EIGENSOLVER = rocsolver | persistent, default persistent). */
 mps_status mps_kernel_selftest_eigh(int n, const double* a, int method, double* w, double* z, int* used);
+
+/* The tridiagonal eigensolver of the truncation's method 1, once on host
+ * data: divide and conquer on the real symmetric tridiagonal matrix with
+ * diagonal d[n] and off-diagonal e[n - 1] (HOST; e may be NULL when n = 1),
+ * 1 <= n <= 2048.  The matrix splits into two halves plus a rank-one term,
+ * the halves are solved recursively and each merge solves the secular
+ * equation of the rank-one update, with deflation of negligible or nearly
+ * coincident terms and eigenvectors from the recomputed update vector, so
+ * that they are orthogonal to working accuracy.  It stands in for a
+ * library tridiagonal solver in Sec. VI.A's truncated SVD (all eigenvalues
+ * for the discarded weight, the vectors of the kept ones).  Outputs (HOST):
+ * w[n] eigenvalues ascending; z[n * n] real, column-major, column j the
+ * eigenvector of w[j].  For kernel-level parity tests. */
+mps_status mps_kernel_selftest_stedc(int n, const double* d, const double* e, double* w, double* z);
 
 /* The complex GEMM of mps_kernel_selftest_cgemm on DEVICE operands, for
  * callers that cannot allocate device memory: code under HIP graph capture,

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB_NAME = "libmpsdmrg.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
-SOURCES = ["cgemm.hip", "cgemm_bf16.hip", "tensor_ops.hip", "hetrd.hip", "statevector.hip", "driver.cpp"]
+SOURCES = ["cgemm.hip", "cgemm_bf16.hip", "tensor_ops.hip", "hetrd.hip", "tridiag_dc.hip", "statevector.hip", "driver.cpp"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

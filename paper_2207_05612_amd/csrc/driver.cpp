@@ -829,14 +829,14 @@ enum { EIGH_ROCSOLVER = 0, EIGH_PERSISTENT = 1 };
 struct EighWork {
     Raw<double> Z, evals, evwork, tau;   // Z: eigenvectors (complex for the library solver, real of T otherwise)
     Planar<double> vh, S, T, Y, W, ws;   // reflectors (conjugated rows) and back-transformation scratch
-    Raw<char> trws;
+    Raw<char> trws, dcws;                // tridiagonal reduction and divide-and-conquer workspaces
     Raw<int> info;
     Raw<double> nrm;                     // partial sums and result of the eigenvector check
     int method_used = EIGH_ROCSOLVER;
     void release(hipStream_t s) {
         Z.release(s); evals.release(s); evwork.release(s); tau.release(s);
         vh.release(s); S.release(s); T.release(s); Y.release(s); W.release(s); ws.release(s);
-        trws.release(s); info.release(s); nrm.release(s);
+        trws.release(s); dcws.release(s); info.release(s); nrm.release(s);
     }
 };
 
@@ -860,9 +860,10 @@ void gemm64_long_k(mps_state* st, EighWork& wk, int opa, int opb, int M, int N, 
 // triangle (row >= column) of the row-major planar array (re, im).  On
 // return wk.evals holds the eigenvalues in ascending order; top_eigvecs()
 // then forms the eigenvectors of the largest ones.
-// EIGH_PERSISTENT: tridiagonal reduction by the persistent kernel, rocSOLVER's
-// divide and conquer on the real tridiagonal matrix, and (in top_eigvecs) the
-// blocked back-transformation by the reflectors on the kept columns only.
+// EIGH_PERSISTENT: tridiagonal reduction by the persistent kernel, the
+// library's own divide and conquer on the real tridiagonal matrix
+// (stedc_dc), and (in top_eigvecs) the blocked back-transformation by the
+// reflectors on the kept columns only.
 // It falls back to rocSOLVER's dense solver when the cooperative launch is
 // refused or gives up waiting.
 // after_reduce (may be null) is called once the reduction no longer needs
@@ -926,10 +927,11 @@ void eigh_gram(mps_state* st, EighWork& wk, const double* re, const double* im, 
         Timer t(st, MPS_KCLASS_EIGH, 0, 0);
         if (!aborted) {
             if (after_reduce) (*after_reduce)();
-            rocblas_status rs = rocsolver_dstedc(st->blas, rocblas_evect_tridiagonal, dim, wk.evals.p, wk.evwork.p,
-                                                 wk.Z.p, dim, wk.info.p);
+            const size_t dcb = stedc_dc_workspace_bytes(dim);
+            wk.dcws.ensure((int64_t)dcb, s);
+            HIPCHK(stedc_dc(dim, wk.evals.p, wk.evwork.p, wk.Z.p, dim, wk.dcws.p, dcb, s));
+            HIPCHK(hipMemsetAsync(wk.info.p, 0, sizeof(int), s));
             t.done();
-            if (rs != rocblas_status_success) fail(MPS_ERR_DEVICE, "rocsolver_dstedc failed: status " + std::to_string((int)rs));
             wk.method_used = EIGH_PERSISTENT;
             st->eig_count[dim <= 128 ? 1 : 0] += 1;
             return;
@@ -2261,6 +2263,33 @@ extern "C" mps_status mps_kernel_selftest_eigh(int n, const double* a, int metho
         if (n < 1 || n > 8192 || !a || !w || !z) fail(MPS_ERR_ARG, "bad eigensolver self-test arguments");
         if (method != EIGH_ROCSOLVER && method != EIGH_PERSISTENT) fail(MPS_ERR_ARG, "method must be 0 or 1");
         selftest_eigh_impl(n, a, method, w, z, used);
+    });
+}
+
+extern "C" mps_status mps_kernel_selftest_stedc(int n, const double* d, const double* e, double* w, double* z) {
+    return run_guarded([&] {
+        if (n < 1 || n > stedc_dc_max_n() || !d || (n > 1 && !e) || !w || !z)
+            fail(MPS_ERR_ARG, "bad tridiagonal self-test arguments");
+        Raw<double> dd, ee, zz;
+        Raw<char> ws;
+        try {
+            const size_t wsb = stedc_dc_workspace_bytes(n);
+            dd.ensure(n, nullptr);
+            ee.ensure(std::max(1, n - 1), nullptr);
+            zz.ensure((int64_t)n * n, nullptr);
+            ws.ensure((int64_t)wsb, nullptr);
+            HIPCHK(hipMemcpyAsync(dd.p, d, sizeof(double) * n, hipMemcpyHostToDevice, nullptr));
+            if (n > 1) HIPCHK(hipMemcpyAsync(ee.p, e, sizeof(double) * (n - 1), hipMemcpyHostToDevice, nullptr));
+            HIPCHK(stedc_dc(n, dd.p, ee.p, zz.p, n, ws.p, wsb, nullptr));
+            HIPCHK(hipMemcpyAsync(w, dd.p, sizeof(double) * n, hipMemcpyDeviceToHost, nullptr));
+            HIPCHK(hipMemcpyAsync(z, zz.p, sizeof(double) * n * n, hipMemcpyDeviceToHost, nullptr));
+            HIPCHK(hipStreamSynchronize(nullptr));
+        } catch (...) {
+            (void)hipStreamSynchronize(nullptr);
+            dd.release(nullptr); ee.release(nullptr); zz.release(nullptr); ws.release(nullptr);
+            throw;
+        }
+        dd.release(nullptr); ee.release(nullptr); zz.release(nullptr); ws.release(nullptr);
     });
 }
 

@@ -201,6 +201,16 @@ hipError_t hetrd_persistent_multi(const TrRequest* reqs, int count, hipStream_t 
 // b wy_block()^2) of the compact WY forms of nblk blocks of wy_block()
 // reflectors, from S_b = V_b^H V_b (same layout) and tau (interleaved,
 // nblk wy_block() entries; tau = 0 marks an identity reflector).
+// Divide-and-conquer eigen-decomposition of the real symmetric tridiagonal
+// matrix (d, e) of order n <= stedc_dc_max_n(), all on the device: d is
+// replaced by the eigenvalues in ascending order and z (column-major, leading
+// dimension ldz) receives the orthonormal eigenvectors; e is not modified.
+// ws: stedc_dc_workspace_bytes(n) bytes of device memory.
+int stedc_dc_max_n();
+size_t stedc_dc_workspace_bytes(int n);
+hipError_t stedc_dc(int n, double* d, const double* e, double* z, int ldz, void* ws, size_t ws_bytes,
+                    hipStream_t stream);
+
 int wy_block();
 hipError_t wy_t_factors(const double* s_re, const double* s_im, int nblk, const double* tau_z, double* t_re,
                         double* t_im, hipStream_t stream);

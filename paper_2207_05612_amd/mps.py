@@ -44,7 +44,7 @@ EXPORTS = ("mps_create", "mps_destroy", "apply_layer_dmrg", "apply_layer_dmrg_si
            "mps_kernel_selftest_eigh", "mps_overlap", "apply_layers_dmrg",
            "sv_create", "sv_destroy", "sv_apply_layer", "sv_amplitudes", "sv_compare_mps",
            "sv_schmidt_weights", "apply_layers_dmrg_bonds", "mps_eigensolver_counts", "mps_cgemm_noalloc",
-           "mps_overlap_layers", "mps_batch_stats")
+           "mps_overlap_layers", "mps_batch_stats", "mps_kernel_selftest_stedc")
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -112,6 +112,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mps_kernel_stats": (i32, [P, i32, ctypes.POINTER(i64), dp, dp, dp]),
         "mps_kernel_selftest_cgemm": (i32, [i32, i32, i32, i32, i32, i32, dp, dp, dp]),
         "mps_kernel_selftest_eigh": (i32, [i32, dp, i32, dp, dp, ip]),
+        "mps_kernel_selftest_stedc": (i32, [i32, dp, dp, dp, dp]),
         "mps_overlap": (i32, [P, P, dp, dp]),
         "mps_overlap_layers": (i32, [P, P, P, ip, i32, dp, dp]),
         "mps_batch_stats": (i32, [ctypes.POINTER(i64), ctypes.POINTER(i64)]),
@@ -377,6 +378,21 @@ def selftest_eigh(a: np.ndarray, method: int = EIGH_PERSISTENT):
     _check(lib.mps_kernel_selftest_eigh(n, _dptr(a.view(np.float64)), method, _dptr(w),
                                         _dptr(z.view(np.float64)), ctypes.byref(used)))
     return w, np.ascontiguousarray(z.T), used.value
+
+
+def selftest_stedc(d: np.ndarray, e: np.ndarray):
+    """Eigenvalues (ascending) and eigenvectors (columns) of the real symmetric tridiagonal
+    matrix (d, e) through the library's divide and conquer (see mps_kernel_selftest_stedc)."""
+    lib = load_library()
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    n = d.shape[0]
+    if e.shape[0] != max(n - 1, 0):
+        raise ValueError("e must have n - 1 entries")
+    w = np.zeros(n)
+    z = np.zeros((n, n))                           # filled column-major: z.T[j] is eigenvector j
+    _check(lib.mps_kernel_selftest_stedc(n, _dptr(d), _dptr(e) if n > 1 else None, _dptr(w), _dptr(z)))
+    return w, np.ascontiguousarray(z.T)
 
 
 # free functions with the ABI's names
