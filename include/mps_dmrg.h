@@ -262,6 +262,18 @@ mps_status mps_get_tensor(const mps_state* state, int site, double* re_im);
 mps_status mps_step_log(const mps_state* state, double* f, double* sum_s2,
                         int* chi_kept, int cap, int* n);
 
+/* Conditioning of the truncations, one entry per applied step (call of
+ * apply_layer_dmrg, apply_layers_dmrg, ... or one instance's layer in the
+ * batched call), oldest first: the smallest separation
+ * (lambda_k - lambda_{k+1}) / lambda_1 of the Gram eigenvalues (squared
+ * singular values, Sec. VI.A) over the step's truncations where chi limited
+ * the kept count (more than chi eigenvalues above the relative threshold
+ * 1e-12); HUGE_VAL when chi limited none.  A separation near
+ * rounding marks a cut inside a (nearly) degenerate set of singular values,
+ * where the kept subspace is not unique.  At most `cap` entries are written;
+ * *n receives the total. */
+mps_status mps_cut_separations(const mps_state* state, double* sep, int cap, int* n);
+
 /* How the truncations of this state were diagonalised since it was created:
  *   counts[0]  persistent multi-workgroup tridiagonal reduction (orders 129..2048);
  *   counts[1]  single-workgroup tridiagonal reduction (orders 2..128);

@@ -497,6 +497,10 @@ struct mps_state {
     int64_t n_2q = 0;
     std::vector<double> log_step_f, log_step_s2;
     std::vector<int> log_step_chi;
+    // per applied step: the smallest separation (lambda_k - lambda_k+1) / lambda_1 of the Gram
+    // eigenvalues at a cut where chi limited the kept count (inf: no such cut)
+    std::vector<double> log_step_sep;
+    double cur_min_sep = HUGE_VAL;
     bool invalid = false;
     rocblas_handle blas = nullptr;
     // scratch
@@ -1082,6 +1086,8 @@ struct Engine {
         const int k = std::max(1, std::min(chi_, keep));
         double f = 0;
         for (int i = 0; i < k; ++i) f += hvals[dim - 1 - i];
+        if (keep > chi_ && hvals[dim - 1] > 0)          // the cut at chi discarded weight above the threshold
+            st->cur_min_sep = std::min(st->cur_min_sep, (hvals[dim - k] - hvals[dim - 1 - k]) / hvals[dim - 1]);
         return Trunc{k, f, total, true};
     }
 
@@ -1568,6 +1574,7 @@ void apply_step_impl(mps_state* st, const mps_gate* gates, const int* n_gates, i
     // argument validation happens in the MPO build, before any device work
     (void)build_step_mpo(st->n, gates, n_gates, n_layers);
     const size_t log_mark = st->log_step_f.size();
+    st->cur_min_sep = HUGE_VAL;
     double f = 0;
     try {
         if (st->prec == MPS_FP32 || is_split(st->prec)) {
@@ -1594,6 +1601,7 @@ void apply_step_impl(mps_state* st, const mps_gate* gates, const int* n_gates, i
     }
     flush_timings(st);
     st->log_f += std::log(f);
+    st->log_step_sep.push_back(st->cur_min_sep);
     st->n_layers += n_layers;
     if (f_layer) *f_layer = f;
 }
@@ -1828,6 +1836,16 @@ mps_status mps_step_log(const mps_state* st, double* f, double* sum_s2, int* chi
             if (sum_s2) sum_s2[i] = st->log_step_s2[i];
             if (chi_kept) chi_kept[i] = st->log_step_chi[i];
         }
+    });
+}
+
+mps_status mps_cut_separations(const mps_state* st, double* sep, int cap, int* n) {
+    return run_guarded([&] {
+        if (!st) fail(MPS_ERR_ARG, "state is NULL");
+        const int total = (int)st->log_step_sep.size();
+        if (n) *n = total;
+        for (int i = 0; i < std::min(cap, total); ++i)
+            if (sep) sep[i] = st->log_step_sep[i];
     });
 }
 

@@ -48,6 +48,8 @@ constexpr int TMAXN = TT * TQ;     // 2048
 constexpr int NWAVE = TT / 64;
 constexpr int SPIN_LIMIT = 1 << 21;
 constexpr int TR_MAXB = 8;         // instances per launch
+constexpr int HG = 8;              // groups of the two-level wait (workgroups wg = g mod HG)
+constexpr int GF_STRIDE = 16;      // ints between group flags
 
 struct TrArgs {
     const double2* a;    // n x n column-major, full Hermitian (not modified)
@@ -62,6 +64,7 @@ struct TrArgs {
     double2* pdot;       // 2 x P: per-workgroup partial y^H v
     int* col_flag;       // number of published columns
     int* wg_flag;        // P: steps completed by each workgroup
+    int* grp_flag;       // HG group flags, 64 bytes apart: steps completed by every member
     int* abort_flag;
 };
 
@@ -75,6 +78,10 @@ __device__ inline double2 ld_coh(const double2* p) {
     const unsigned long long x = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned long long y = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return make_double2(__builtin_bit_cast(double, x), __builtin_bit_cast(double, y));
+}
+__device__ inline double ld_coh1(const double* p) {
+    return __builtin_bit_cast(double, __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT));
 }
 __device__ inline void st_coh1(double* p, double v) {
     __hip_atomic_store((unsigned long long*)p, __builtin_bit_cast(unsigned long long, v), __ATOMIC_RELAXED,
@@ -91,48 +98,16 @@ __device__ inline void st_coh(double2* p, double2 v) {
 // (st_coh) and read with a device-coherent atomic load (ld_coh).  A producer
 // joins its workgroup barrier; then its first wavefront issues an agent-scope
 // release fence and one thread stores the flag.  A consumer's first wavefront
-// polls the flags with relaxed loads, issues an agent-scope acquire fence once
-// every flag has the value, and the workgroup barrier that follows orders the
-// data loads of every wavefront after it.  The barriers carry the ordering
-// inside a workgroup and the fence pair (fence-fence synchronisation of the
-// HIP / C++ memory model) carries it across workgroups, so the protocol does
-// not rest on hardware ordering.  One fence per workgroup and step: each one
+// waits (wait_groups_acquire, below) with relaxed loads, issues an agent-scope
+// acquire fence once every producer has the value, and the workgroup barrier
+// that follows orders the data loads of every wavefront after it.  The
+// barriers carry the ordering inside a workgroup and the fence pair
+// (fence-fence synchronisation of the HIP / C++ memory model) carries it
+// across workgroups, so the protocol does not rest on hardware ordering.
+// One fence of each kind per workgroup and step (two more in a leader): each one
 // costs an L2 write-back (release) or invalidation (acquire).  The reflectors
 // and the tridiagonal entries are written with coherent stores as well, so
 // the L2 holds no dirty lines that a release would have to write back.
-
-// Wavefront 0 waits until flags[0 .. count) all reach target (count <= 256), then
-// acquires; the caller's workgroup barrier follows.  Each lane polls flags lane,
-// lane + 64, lane + 128 and lane + 192 with independent loads, so one poll round costs
-// one memory round trip.  False (in wavefront 0) on abort or time-out.
-__device__ bool wait_all_acquire(int* flags, int count, int target, int* abort_flag) {
-    bool ok = true;
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
-        int spins = 0;
-        while (true) {
-            bool done = true;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int f = lane + 64 * k;
-                if (f < count) done &= __hip_atomic_load(flags + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
-            }
-            if (done) break;
-            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                ok = false;
-                break;
-            }
-            if (++spins > SPIN_LIMIT) {
-                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = false;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    return ok;
-}
 
 // After the workgroup barrier, release this workgroup's earlier stores and set *flag = val.
 __device__ void publish(int* flag, int val) {
@@ -141,6 +116,57 @@ __device__ void publish(int* flag, int val) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (threadIdx.x == 0) __hip_atomic_store(flag, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+}
+
+// Two-level wait.  With every workgroup polling all P flags, the polling of
+// 256 workgroups contends for the same few cache lines; here the workgroups
+// form HG groups (wg mod HG) and the first workgroup of each group (wg < HG)
+// leads it: its first wavefront waits for the flags of its members, acquires,
+// releases and sets the group's flag; every workgroup then waits for the HG
+// group flags and acquires.  The release -> acquire -> release -> acquire
+// chain through the leader makes every member's stores visible to every
+// workgroup (happens-before is transitive), so the protocol stays the
+// fence-fence synchronisation described above.  Every wait is bounded: on
+// time-out the abort flag is raised; on abort (own or seen) it returns false
+// in wavefront 0.
+__device__ bool wait_groups_acquire(int* flags, int* grp_flags, int count, int wg, int target, int* abort_flag) {
+    bool ok = true;
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        int spins = 0;
+        auto bail = [&]() {
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return true;
+            if (++spins > SPIN_LIMIT) {
+                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return true;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            return false;
+        };
+        if (wg < HG) {
+            // members wg, wg + HG, ... (at most 256 / HG = 32 of them: one per lane)
+            while (true) {
+                const int m = wg + HG * lane;
+                const bool done = m >= count ||
+                                  __hip_atomic_load(flags + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
+                if (__all(done)) break;
+                if (bail()) { ok = false; break; }
+            }
+            if (ok) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                if (lane == 0) __hip_atomic_store(grp_flags + GF_STRIDE * wg, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        while (ok) {
+            const bool done = lane >= HG || lane >= count ||
+                              __hip_atomic_load(grp_flags + GF_STRIDE * lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
+            if (__all(done)) break;
+            if (bail()) { ok = false; break; }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    return ok;
 }
 
 __device__ inline double wave_sum(double v) {
@@ -396,7 +422,7 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrBatch batch) {
         }
         // ---- wait for every workgroup's y entries and partial y^H v (and the
         //      column published one step earlier)
-        const bool ok = wait_all_acquire(g.wg_flag, P, i + 1, g.abort_flag);
+        const bool ok = wait_groups_acquire(g.wg_flag, g.grp_flag, P, wg, i + 1, g.abort_flag);
         if (__syncthreads_or(!ok)) return;
         // every published value of this step is complete now: issue the loads of y and of
         // the partial y^H v together, so that their latencies overlap
@@ -407,10 +433,27 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrBatch batch) {
             yq[q] = (r >= i + 1 && r < n) ? ld_coh(&g.ybuf[(int64_t)buf * n + r]) : make_double2(0.0, 0.0);
         }
         const double2 y1 = ld_coh(&g.ybuf[(int64_t)buf * n + i + 1]);
-        // every wavefront sums all P shares of y^H v itself (no barrier)
-        double pdr = 0.0;
-        for (int k = lane; k < P; k += 64) pdr += ld_coh(&g.pdot[(int64_t)buf * P + k]).x;
-        pdr = wave_sum(pdr);
+        // every wavefront sums all P (<= 256) shares of y^H v itself (no barrier); the loads
+        // are issued together with those of y and of the next column
+        double pd[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = lane + 64 * q;
+            pd[q] = k < P ? ld_coh1(&g.pdot[(int64_t)buf * P + k].x) : 0.0;
+        }
+        // next column x_{i+1} = A[:, i+1] as updated by steps 0 .. i-1: published by its owner
+        // in step i-1, before that owner's flag of step i
+        double2 cv[TQ];
+        {
+            const double2* src = g.colbuf + (int64_t)((i + 1) & 1) * n;
+#pragma unroll
+            for (int q = 0; q < TQ; ++q) {
+                const int r = tid + TT * q;
+                cv[q] = make_double2(0.0, 0.0);
+                if (r >= i + 1 && r < n) cv[q] = (i == 0) ? g.a[r + lda] : ld_coh(&src[r]);
+            }
+        }
+        const double pdr = wave_sum(pd[0] + pd[1] + pd[2] + pd[3]);
         // w = tau y + alpha_w v, alpha_w = -|tau|^2 (y^H v) / 2
         const double alw = -0.5 * (tau.x * tau.x + tau.y * tau.y) * pdr;
         double2 w[TQ];
@@ -447,18 +490,11 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrBatch batch) {
             if (j == j2 || c < i + 1 || c >= n) continue;
             UPDATE_COL(j);
         }
-        // ---- next column: x_{i+1} = A[:, i+1] (after step i-1, loaded into x above)
-        //      - v conj(w_{i+1}) - w
-        {
-            const double2* src = g.colbuf + (int64_t)((i + 1) & 1) * n;
+        // ---- next column: x_{i+1} = A[:, i+1] (after step i-1, loaded above) - v conj(w_{i+1}) - w
 #pragma unroll
-            for (int q = 0; q < TQ; ++q) {
-                const int r = tid + TT * q;
-                double2 cv = make_double2(0.0, 0.0);
-                if (r >= i + 1 && r < n) cv = (i == 0) ? g.a[r + lda] : ld_coh(&src[r]);
-                const double2 t1 = cjmul(w1, v[q]);
-                x[q] = make_double2(cv.x - t1.x - w[q].x, cv.y - t1.y - w[q].y);
-            }
+        for (int q = 0; q < TQ; ++q) {
+            const double2 t1 = cjmul(w1, v[q]);
+            x[q] = make_double2(cv[q].x - t1.x - w[q].x, cv[q].y - t1.y - w[q].y);
         }
     }
     // last diagonal entry: column n-1 after step n-2
@@ -706,7 +742,7 @@ int hetrd_max_n() { return TMAXN; }
 
 size_t hetrd_workspace_bytes(int n) {
     const int P = (n + TC - 1) / TC;
-    return sizeof(double2) * (4 * (size_t)n + 2 * (size_t)P) + sizeof(int) * (size_t)(P + 2) + 256;
+    return sizeof(double2) * (4 * (size_t)n + 2 * (size_t)P) + sizeof(int) * (size_t)(P + 2 + HG * GF_STRIDE) + 256;
 }
 
 hipError_t hermitian_full_colmajor(const double* re, const double* im, int n, double* out_z, hipStream_t stream) {
@@ -737,8 +773,9 @@ hipError_t prepare(const TrRequest& r, TrArgs& g, hipStream_t stream) {
     g.col_flag = flags;
     g.abort_flag = flags + 1;
     g.wg_flag = flags + 2;
+    g.grp_flag = flags + 2 + g.P;
     if (r.abort_flag) *r.abort_flag = g.abort_flag;
-    return hipMemsetAsync(flags, 0, sizeof(int) * (size_t)(g.P + 2), stream);
+    return hipMemsetAsync(flags, 0, sizeof(int) * (size_t)(g.P + 2 + HG * GF_STRIDE), stream);
 }
 }  // namespace
 

@@ -44,7 +44,8 @@ EXPORTS = ("mps_create", "mps_destroy", "apply_layer_dmrg", "apply_layer_dmrg_si
            "mps_kernel_selftest_eigh", "mps_overlap", "apply_layers_dmrg",
            "sv_create", "sv_destroy", "sv_apply_layer", "sv_amplitudes", "sv_compare_mps",
            "sv_schmidt_weights", "apply_layers_dmrg_bonds", "mps_eigensolver_counts", "mps_cgemm_noalloc",
-           "mps_overlap_layers", "mps_batch_stats", "mps_kernel_selftest_stedc")
+           "mps_overlap_layers", "mps_batch_stats", "mps_kernel_selftest_stedc",
+           "mps_cut_separations")
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -107,6 +108,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mps_bond_dims": (i32, [P, ip]),
         "mps_get_tensor": (i32, [P, i32, dp]),
         "mps_step_log": (i32, [P, dp, dp, ip, i32, ip]),
+        "mps_cut_separations": (i32, [P, dp, i32, ip]),
         "mps_expect_zz": (i32, [P, i32, i32, dp]),
         "mps_set_profiling": (i32, [P, i32]),
         "mps_kernel_stats": (i32, [P, i32, ctypes.POINTER(i64), dp, dp, dp]),
@@ -296,6 +298,16 @@ class MPS:
         k = np.zeros(max(m, 1), dtype=np.int32)
         _check(_lib.mps_step_log(self._h, _dptr(f), _dptr(s2), _iptr(k), m, ctypes.byref(n)))
         return f[:m], s2[:m], k[:m]
+
+    def cut_separations(self):
+        """Per applied step, the smallest (lambda_k - lambda_k+1) / lambda_1 at a cut where chi
+        limited the kept count (inf where it limited none); see mps_cut_separations."""
+        n = ctypes.c_int()
+        _check(_lib.mps_cut_separations(self._h, None, 0, ctypes.byref(n)))
+        m = n.value
+        out = np.zeros(max(m, 1))
+        _check(_lib.mps_cut_separations(self._h, _dptr(out), m, ctypes.byref(n)))
+        return out[:m]
 
     def counters(self) -> dict:
         """Eigensolver paths of the truncations so far (mps_eigensolver_counts)."""

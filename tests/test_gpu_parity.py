@@ -109,6 +109,9 @@ def test_exact_regime_plain_workload(prec):
     assert fid["n_2q"] == c.n_2q == 34
     ora = dmrg.run_circuit(c, chi=64, n_sweeps=2)
     assert st.bond_dims() == ora.bond_dims()
+    # the zip-up truncates its intermediate bonds (chi w) to chi even here; every cut is resolved
+    sep = st.cut_separations()
+    assert sep.shape == (len(c.layers),) and np.all(sep > 0)
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32, BF16X2, BF16X3])
@@ -130,6 +133,8 @@ def test_truncated_parity_plain_workload(prec, chi):
         assert st.bond_dims() == ora.bond_dims()
     gf = st.fidelity()
     assert abs(gf["log_F_tilde"] - ora.log_f) < F_TOL[prec] * 10 * len(c.layers)
+    sep = st.cut_separations()          # truncation at chi happens: some separation is finite
+    assert sep.shape == (len(c.layers),) and np.all(sep >= 0) and np.isfinite(sep).any()
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32, BF16X2, BF16X3])
