@@ -85,9 +85,9 @@ def test_golden_parity(name, prec):
         assert st.bond_dims() == rec["bond_dims"]
         assert amp_err < 1e-7
     else:
-        assert rel.max() < pb.F_TARGET[prec]
         sizes = pb.two_site_layer_sizes(c.n, sweeps, depth)
         conds = list(zip(rec["step_gap"], [math.inf if k is None else k for k in rec["step_kappa"]]))
+        assert rel.max() < pb.f_bound(prec, amp_err)
         ksum = pb.sum_layer_kappa(conds, sizes)
         bound = pb.amp_bound(prec, ksum)
         print("%s prec=%d amplitude bound %.2e (target %.0e) worst gap %.2e sum kappa %.3g"
