@@ -7,15 +7,17 @@
 // a matrix-vector product with the trailing block; issued as a few kernels
 // per step it is launch-latency bound.  Here one cooperative launch does all
 // steps:
-//   * workgroup g owns the columns g, g + P, g + 2P, ... (at most 8 of them),
-//     four in registers and four in LDS, for the whole reduction, so the
-//     trailing block is never re-read from memory;
+//   * workgroup g owns the columns 8g .. 8g + 7, four in registers and four
+//     in LDS, for the whole reduction, so the trailing block is never re-read
+//     from memory; a workgroup whose columns are all reduced leaves, so the
+//     number of workgroups that exchange data shrinks from n / 8 to one
+//     (the cost of an exchange grows with the number of participants);
 //   * every workgroup holds column i (as updated by steps 0 .. i-1) in its
 //     registers and forms the reflector (v, tau) from it redundantly;
 //   * it computes y = A v for its own columns (the matrix is Hermitian, so
 //     y_c is the dot product of column c with v), publishes y_c and its share
-//     of y^H v, and waits for all workgroups (one flag each, the only wait of
-//     the step);
+//     of y^H v, and waits for the other workgroups that still hold columns
+//     (the only wait of the step);
 //   * it applies the rank-2 update A -= v w^H + w v^H,
 //     w = tau y - (|tau|^2 y^H v / 2) v, to its columns, and rebuilds column
 //     i+1 for the next step from the copy of it that the column's owner
@@ -98,7 +100,7 @@ __device__ inline void st_coh(double2* p, double2 v) {
 // (st_coh) and read with a device-coherent atomic load (ld_coh).  A producer
 // joins its workgroup barrier; then its first wavefront issues an agent-scope
 // release fence and one thread stores the flag.  A consumer's first wavefront
-// waits (wait_groups_acquire, below) with relaxed loads, issues an agent-scope
+// waits (wait_step_acquire, below) with relaxed loads, issues an agent-scope
 // acquire fence once every producer has the value, and the workgroup barrier
 // that follows orders the data loads of every wavefront after it.  The
 // barriers carry the ordering inside a workgroup and the fence pair
@@ -118,18 +120,21 @@ __device__ void publish(int* flag, int val) {
     }
 }
 
-// Two-level wait.  With every workgroup polling all P flags, the polling of
-// 256 workgroups contends for the same few cache lines; here the workgroups
-// form HG groups (wg mod HG) and the first workgroup of each group (wg < HG)
-// leads it: its first wavefront waits for the flags of its members, acquires,
-// releases and sets the group's flag; every workgroup then waits for the HG
-// group flags and acquires.  The release -> acquire -> release -> acquire
+// Wait of step i.  The participants are the workgroups g0 .. count - 1 (those that
+// still hold an unreduced column).  With many participants, polling all their
+// flags from every workgroup contends for the same few cache lines; then they
+// form HG groups (g mod HG) and the first participant of each group leads it:
+// its first wavefront waits for the flags of its members, acquires, releases
+// and sets the group's flag; every participant then waits for the flags of the
+// non-empty groups and acquires.  The release -> acquire -> release -> acquire
 // chain through the leader makes every member's stores visible to every
-// workgroup (happens-before is transitive), so the protocol stays the
-// fence-fence synchronisation described above.  Every wait is bounded: on
-// time-out the abort flag is raised; on abort (own or seen) it returns false
-// in wavefront 0.
-__device__ bool wait_groups_acquire(int* flags, int* grp_flags, int count, int wg, int target, int* abort_flag) {
+// participant (happens-before is transitive), so the protocol stays the
+// fence-fence synchronisation described above.  With at most FLAT_MAX
+// participants every one polls all their flags directly.  Every wait is
+// bounded: on time-out the abort flag is raised; on abort (own or seen) it
+// returns false in wavefront 0.
+constexpr int FLAT_MAX = 32;
+__device__ bool wait_step_acquire(int* flags, int* grp_flags, int g0, int count, int wg, int target, int* abort_flag) {
     bool ok = true;
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
@@ -143,26 +148,40 @@ __device__ bool wait_groups_acquire(int* flags, int* grp_flags, int count, int w
             __builtin_amdgcn_s_sleep(1);
             return false;
         };
-        if (wg < HG) {
-            // members wg, wg + HG, ... (at most 256 / HG = 32 of them: one per lane)
+        if (count - g0 <= FLAT_MAX) {
             while (true) {
-                const int m = wg + HG * lane;
+                const int m = g0 + lane;
                 const bool done = m >= count ||
                                   __hip_atomic_load(flags + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
                 if (__all(done)) break;
                 if (bail()) { ok = false; break; }
             }
-            if (ok) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                if (lane == 0) __hip_atomic_store(grp_flags + GF_STRIDE * wg, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            if (wg < g0 + HG) {
+                // members wg, wg + HG, ... (at most 256 / HG = 32 of them: one per lane)
+                while (true) {
+                    const int m = wg + HG * lane;
+                    const bool done = m >= count ||
+                                      __hip_atomic_load(flags + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
+                    if (__all(done)) break;
+                    if (bail()) { ok = false; break; }
+                }
+                if (ok) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    if (lane == 0)
+                        __hip_atomic_store(grp_flags + GF_STRIDE * (wg % HG), target, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
-        }
-        while (ok) {
-            const bool done = lane >= HG || lane >= count ||
-                              __hip_atomic_load(grp_flags + GF_STRIDE * lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
-            if (__all(done)) break;
-            if (bail()) { ok = false; break; }
+            while (ok) {
+                // group lane % HG is led by g0 + lane (count - g0 > HG: every group has members)
+                const bool done = lane >= HG ||
+                                  __hip_atomic_load(grp_flags + GF_STRIDE * ((g0 + lane) % HG), __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT) >= target;
+                if (__all(done)) break;
+                if (bail()) { ok = false; break; }
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
@@ -272,7 +291,7 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrBatch batch) {
     // load the owned columns and column 0
 #pragma unroll
     for (int j = 0; j < TC; ++j) {
-        const int c = wg + P * j;
+        const int c = wg * TC + j;
 #pragma unroll
         for (int q = 0; q < TQ; ++q) {
             const int r = tid + TT * q;
@@ -295,7 +314,12 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrBatch batch) {
     }
     __syncthreads();
 
+    const int c_first = wg * TC, c_last = min(n, c_first + TC) - 1;   // owned columns
     for (int i = 0; i + 1 < n; ++i) {
+        // this workgroup leaves once all its columns are reduced (no column >= i + 1); the
+        // participants of step i are the workgroups g0 .. P - 1
+        if (c_last < i + 1) break;
+        const int g0 = (i + 1) / TC;
         const int buf = i & 1;
         // ---- broadcasts from row i+1 and from the rows of the owned columns
 #pragma unroll
@@ -306,7 +330,7 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrBatch batch) {
 #pragma unroll
                 for (int j = 0; j < TC; ++j) a1col[buf][j] = A_GET(j, q, r);
             }
-            if (r < n && r >= wg && (r - wg) % P == 0) xcol[buf][(r - wg) / P] = x[q];
+            if (r >= c_first && r <= c_last) xcol[buf][r - c_first] = x[q];
         }
         // ---- one reduction: |x[i+2:]|^2 and z_c = sum_{r >= i+2} conj(A[r, c]) x[r]
         double part = 0.0;
@@ -319,7 +343,7 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrBatch batch) {
 #pragma unroll
         for (int j = 0; j < TC; ++j) {
             double2 sacc = make_double2(0.0, 0.0);
-            const int c = wg + P * j;
+            const int c = c_first + j;
             if (c >= i + 1 && c < n) {
 #pragma unroll
                 for (int q = 0; q < TQ; ++q) {
@@ -370,7 +394,7 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrBatch batch) {
             // lanes 0 .. TC-1: y and v of the owned columns, and this workgroup's share of y^H v
             double2 pdt = make_double2(0.0, 0.0);
             if (tid < TC) {
-                const int c = wg + P * tid;
+                const int c = c_first + tid;
                 double2 vc = make_double2(0.0, 0.0), yc = make_double2(0.0, 0.0);
                 if (c >= i + 1 && c < n) {
                     double zr = 0.0, zi = 0.0;
@@ -403,9 +427,9 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrBatch batch) {
         for (int q = 0; q < TQ; ++q)
             if (tid + TT * q == i) d_i = x[q].x;
         publish(g.wg_flag + wg, i + 1);
-        // the owner of column i records d_i, e_i, tau_i and the reflector; issued after
-        // the flag so that the publication does not wait for these stores
-        if (wg == i % P) {
+        // the first participant (the owner of column i + 1) records d_i, e_i, tau_i and the
+        // reflector; issued after the flag so that the publication does not wait for them
+        if (wg == g0) {
 #pragma unroll
             for (int q = 0; q < TQ; ++q) {
                 const int r = tid + TT * q;
@@ -422,7 +446,7 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrBatch batch) {
         }
         // ---- wait for every workgroup's y entries and partial y^H v (and the
         //      column published one step earlier)
-        const bool ok = wait_groups_acquire(g.wg_flag, g.grp_flag, P, wg, i + 1, g.abort_flag);
+        const bool ok = wait_step_acquire(g.wg_flag, g.grp_flag, g0, P, wg, i + 1, g.abort_flag);
         if (__syncthreads_or(!ok)) return;
         // every published value of this step is complete now: issue the loads of y and of
         // the partial y^H v together, so that their latencies overlap
@@ -433,12 +457,12 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrBatch batch) {
             yq[q] = (r >= i + 1 && r < n) ? ld_coh(&g.ybuf[(int64_t)buf * n + r]) : make_double2(0.0, 0.0);
         }
         const double2 y1 = ld_coh(&g.ybuf[(int64_t)buf * n + i + 1]);
-        // every wavefront sums all P (<= 256) shares of y^H v itself (no barrier); the loads
-        // are issued together with those of y and of the next column
+        // every wavefront sums the participants' (<= 256) shares of y^H v itself (no barrier);
+        // the loads are issued together with those of y and of the next column
         double pd[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int k = lane + 64 * q;
+            const int k = g0 + lane + 64 * q;
             pd[q] = k < P ? ld_coh1(&g.pdot[(int64_t)buf * P + k].x) : 0.0;
         }
         // next column x_{i+1} = A[:, i+1] as updated by steps 0 .. i-1: published by its owner
@@ -470,7 +494,7 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrBatch batch) {
         const double2 ty1 = cmul(tau, y1);
         const double2 w1 = make_double2(ty1.x + alw, ty1.y);
         // ---- rank-2 update of the owned columns; column i+2 first, then published
-        const int j2 = (i + 2 < n && wg == (i + 2) % P) ? (i + 2) / P : -1;
+        const int j2 = (i + 2 < n && wg == (i + 2) / TC) ? (i + 2) % TC : -1;
         if (j2 >= 0) {
 #pragma unroll
             for (int j = 0; j < TC; ++j) {
@@ -486,7 +510,7 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrBatch batch) {
         }
 #pragma unroll
         for (int j = 0; j < TC; ++j) {
-            const int c = wg + P * j;
+            const int c = c_first + j;
             if (j == j2 || c < i + 1 || c >= n) continue;
             UPDATE_COL(j);
         }
@@ -497,8 +521,8 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrBatch batch) {
             x[q] = make_double2(cv[q].x - t1.x - w[q].x, cv[q].y - t1.y - w[q].y);
         }
     }
-    // last diagonal entry: column n-1 after step n-2
-    if (wg == 0) {
+    // last diagonal entry: column n-1 after step n-2 (its owner takes part in every step)
+    if (wg == (n - 1) / TC) {
 #pragma unroll
         for (int q = 0; q < TQ; ++q)
             if (tid + TT * q == n - 1) g.d[n - 1] = x[q].x;
