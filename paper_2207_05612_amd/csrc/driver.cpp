@@ -612,6 +612,17 @@ int splitk_for(int64_t M, int64_t N, int64_t K) {
     return (int)std::max<int64_t>(1, ks);
 }
 
+// The same for the split-precision kernel: 256 x 128 output tiles and one
+// workgroup per compute unit, so an output of fewer than 256 tiles is split
+// until it fills the 256 units (chunks of at least 512 terms).
+int splitk_for_split(int64_t M, int64_t N, int64_t K) {
+    int64_t ks = 1;
+    if (K >= 8192) ks = std::min<int64_t>(64, K / 4096);
+    const int64_t tiles = ((M + 255) / 256) * ((N + 127) / 128);
+    if (tiles < 256 && K >= 1024) ks = std::max<int64_t>(ks, std::min<int64_t>((256 + tiles - 1) / tiles, K / 512));
+    return (int)std::max<int64_t>(1, ks);
+}
+
 // Each launch is timed on its own; the split-K reduction counts as OTHER.
 template <typename R>
 void gemm(mps_state* st, int cls, int opa, int opb, int64_t M, int64_t N, int64_t K, const R* ar,
@@ -653,13 +664,13 @@ void gemm_split(mps_state* st, int cls, int64_t M, int64_t N, int64_t K, const f
     const Lane ln = lane ? *lane : main_lane(st);
     const double fl = 8.0 * (double)M * (double)N * (double)K;
     const double by = 8.0 * ((double)M * K + (double)K * N + (double)M * N);
-    const int ks = splitk_chunks((int)K, splitk_for(M, N, K), 16);
+    const int ks = splitk_chunks((int)K, splitk_for_split(M, N, K), 16);
     if (ks > 1) {
         ln.ws->ensure(M * N * ks, ln.s);
         {
             Timer t(st, cls, fl, by, ln.s);
             HIPCHK(cgemm_bf16_nt_splitk(split_terms(st), (int)M, (int)N, (int)K, {ar, ai, lda}, {br, bi, ldb}, ln.ws->re(),
-                                          ln.ws->im(), splitk_for(M, N, K), ln.s));
+                                          ln.ws->im(), splitk_for_split(M, N, K), ln.s));
             t.done();
         }
         Timer t(st, MPS_KCLASS_OTHER, 0, 8.0 * (double)M * N * (ks + 1), ln.s);
@@ -1029,6 +1040,7 @@ struct Engine {
     Planar<R> MT[2][2];               // per lane: intermediates of multi-layer MPO factors
     bool split = false;   // split-precision BF16 contractions (R = float only): operands kept k-contiguous
     Planar<double> TH64, GR, U64, V64, M64;
+    Planar<double> LX, LY, LQ, LR, LP, LT, LU;   // factors of a low-rank two-site truncation
     EighWork ew;
     Raw<double> svec, QZ, QG, QT;
     Raw<int> QI;
@@ -1049,6 +1061,7 @@ struct Engine {
             for (auto& e : psi[o]) e.release(s);
         X.release(s); T2.release(s); TH.release(s); UR.release(s); T2T.release(s);
         TH64.release(s); GR.release(s); U64.release(s); V64.release(s); M64.release(s);
+        LX.release(s); LY.release(s); LQ.release(s); LR.release(s); LP.release(s); LT.release(s); LU.release(s);
         ew.release(s); svec.release(s); QZ.release(s); QG.release(s); QT.release(s); QI.release(s);
         for (auto& p : phi) p.release(s);
     }
@@ -1165,6 +1178,45 @@ struct Engine {
         }
         HIPCHK(hipStreamSynchronize(s));  // host vectors above must outlive their copies
         tr.caseA = false;
+        return tr;
+    }
+
+    // Truncation of Theta = X Y^T (X: rows x r, Y: cols x r, planar row-major, working
+    // precision, r < rows and r < cols), without forming Theta: the Gram matrix
+    // Theta Theta^H = X (Y^T conj(Y)) X^H has rank <= r, and with X = Q R (Q orthonormal,
+    // rows x r) its non-zero eigen-pairs are those of the order-r Hermitian matrix
+    // H = R conj(Y^H Y) R^H = R (Y^H Y)^T R^H, whose eigenvectors Q maps back.  The kept
+    // values, the total weight (trace H = |Theta|^2) and U64 are those truncate() returns,
+    // up to rounding; the eigen-decomposition has order r instead of min(rows, cols).
+    Trunc truncate_lowrank(const R* x_re, const R* x_im, const R* y_re, const R* y_im, int64_t rows, int64_t cols,
+                           int64_t r, int bond) {
+        const int chi = chi_at(bond);
+        LX.ensure(rows * r, s);
+        LY.ensure(cols * r, s);
+        HIPCHK((convert_planar<R, double>(x_re, x_im, rows * r, LX.re(), LX.im(), s)));
+        HIPCHK((convert_planar<R, double>(y_re, y_im, cols * r, LY.re(), LY.im(), s)));
+        const int64_t kq = qr_orth(rows, r, LX.re(), LX.im());        // Q (rows x r) in U64
+        std::swap(U64, LQ);
+        LR.ensure(kq * r, s);
+        LP.ensure(r * r, s);
+        LT.ensure(kq * r, s);
+        GR.ensure(kq * kq, s);
+        gemm<double>(st, MPS_KCLASS_GRAM, OP_C, OP_N, kq, r, rows, LQ.re(), LQ.im(), kq, LX.re(), LX.im(), r,
+                     LR.re(), LR.im(), r);                                   // R = Q^H X
+        gemm<double>(st, MPS_KCLASS_GRAM, OP_C, OP_N, r, r, cols, LY.re(), LY.im(), r, LY.re(), LY.im(), r,
+                     LP.re(), LP.im(), r);                                   // P = Y^H Y
+        gemm<double>(st, MPS_KCLASS_GRAM, OP_N, OP_T, kq, r, r, LR.re(), LR.im(), r, LP.re(), LP.im(), r,
+                     LT.re(), LT.im(), r);                                   // R P^T
+        gemm<double>(st, MPS_KCLASS_GRAM, OP_N, OP_C, kq, kq, r, LT.re(), LT.im(), r, LR.re(), LR.im(), r,
+                     GR.re(), GR.im(), kq);                                  // H = R P^T R^H
+        eigh((int)kq);
+        Trunc tr = select((int)kq, chi);
+        LU.ensure(kq * tr.k, s);
+        top_eigvecs(st, ew, (int)kq, tr.k, LU.re(), LU.im());
+        U64.ensure(rows * tr.k, s);
+        gemm<double>(st, MPS_KCLASS_EIGH, OP_N, OP_N, rows, tr.k, kq, LQ.re(), LQ.im(), kq, LU.re(), LU.im(), tr.k,
+                     U64.re(), U64.im(), tr.k);                              // U = Q U_H
+        tr.caseA = true;
         return tr;
     }
 
@@ -1394,16 +1446,22 @@ struct Engine {
             const int64_t cL = cb[bL], cR = cb[bR], wM = mpo.w[bM];
             const int64_t DM = st->bond[bM];
             const int64_t rows = 2 * cL, cols = 2 * cR, K = wM * DM;
-            TH.ensure(rows * cols, s);
-            TH64.ensure(rows * cols, s);
             const Planar<R>& rb = T2R[j & 1];
             HIPCHK(hipStreamWaitEvent(s, ev_right[j & 1], 0));
-            if (split)
-                gemm_split(st, MPS_KCLASS_CONTRACT, rows, cols, K, (const float*)T2.re(), (const float*)T2.im(), K,
-                           (const float*)rb.re(), (const float*)rb.im(), K, (float*)TH.re(), (float*)TH.im(), cols);
-            else
-                gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_T, rows, cols, K, T2.re(), T2.im(), K, rb.re(), rb.im(), K,
-                        TH.re(), TH.im(), cols);
+            // Theta = T2 rb^T has rank <= K: when K < rows, cols (a bond that no gate of the layer
+            // crosses, wM = 1, below saturation of the outer bonds) the truncation works on the
+            // factors and Theta is never formed (the last pair needs Theta for its right factor)
+            const bool lowrank = !last && K < rows && K < cols;
+            if (!lowrank) {
+                TH.ensure(rows * cols, s);
+                TH64.ensure(rows * cols, s);
+                if (split)
+                    gemm_split(st, MPS_KCLASS_CONTRACT, rows, cols, K, (const float*)T2.re(), (const float*)T2.im(), K,
+                               (const float*)rb.re(), (const float*)rb.im(), K, (float*)TH.re(), (float*)TH.im(), cols);
+                else
+                    gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_T, rows, cols, K, T2.re(), T2.im(), K, rb.re(), rb.im(),
+                            K, TH.re(), TH.im(), cols);
+            }
             // The right block of the next pair is queued on the second stream once
             // this pair's tridiagonal reduction (a whole-device cooperative launch)
             // has finished, so it overlaps the rest of the truncation.
@@ -1418,8 +1476,13 @@ struct Engine {
                 HIPCHK(hipEventRecord(ev_right[(j + 1) & 1], st->stream2));
             };
             after_reduce = &queue_right;
-            HIPCHK((convert_planar<R, double>(TH.re(), TH.im(), rows * cols, TH64.re(), TH64.im(), s)));
-            Trunc tr = truncate(TH.re(), TH.im(), rows, cols, last, TH64.re(), TH64.im(), bM);
+            Trunc tr;
+            if (lowrank) {
+                tr = truncate_lowrank(T2.re(), T2.im(), rb.re(), rb.im(), rows, cols, K, bM);
+            } else {
+                HIPCHK((convert_planar<R, double>(TH.re(), TH.im(), rows * cols, TH64.re(), TH64.im(), s)));
+                tr = truncate(TH.re(), TH.im(), rows, cols, last, TH64.re(), TH64.im(), bM);
+            }
             after_reduce = nullptr;
             queue_right();          // no-op when the truncation already queued it
             f = tr.f;
@@ -2201,19 +2264,19 @@ void selftest_cgemm_impl(int opa, int opb, int M, int N, int K, const double* a,
     const int64_t lda = (opa == OP_N) ? K : M;
     const int64_t ldb = (opb == OP_N) ? N : K;
     // the same split-K policy as the compression step (FP32 and split-precision kernels)
-    const int ks = sizeof(R) == 4 ? splitk_chunks(K, splitk_for(M, N, K), 16) : 1;
+    const int req = split ? splitk_for_split(M, N, K) : splitk_for(M, N, K);
+    const int ks = sizeof(R) == 4 ? splitk_chunks(K, req, 16) : 1;
     float* ws = nullptr;
     if (ks > 1) ws = (float*)dalloc(sizeof(float) * 2 * (size_t)nc * ks, s);
     if (split && ks > 1)
         HIPCHK(cgemm_bf16_nt_splitk(split_terms_, M, N, K, {(const float*)da, (const float*)(da + na), lda},
-                                      {(const float*)db, (const float*)(db + nb), ldb}, ws, ws + nc * ks,
-                                      splitk_for(M, N, K), s));
+                                      {(const float*)db, (const float*)(db + nb), ldb}, ws, ws + nc * ks, req, s));
     else if (split)
         HIPCHK(cgemm_bf16_nt(split_terms_, M, N, K, {(const float*)da, (const float*)(da + na), lda},
                                {(const float*)db, (const float*)(db + nb), ldb}, {(float*)dc, (float*)(dc + nc), N}, s));
     else if (ks > 1)
         HIPCHK(cgemm_f32_splitk(opa, opb, M, N, K, {(const float*)da, (const float*)(da + na), lda},
-                                {(const float*)db, (const float*)(db + nb), ldb}, ws, ws + nc * ks, splitk_for(M, N, K), s));
+                                {(const float*)db, (const float*)(db + nb), ldb}, ws, ws + nc * ks, req, s));
     else
         HIPCHK(gemm_raw<R>(opa, opb, M, N, K, da, da + na, lda, db, db + nb, ldb, dc, dc + nc, N, s));
     if (ks > 1) {
@@ -2379,7 +2442,7 @@ extern "C" mps_status mps_cgemm_noalloc(int precision, int opa, int opb, int M, 
             return;
         }
         // the split-K policy of the compression step and of mps_kernel_selftest_cgemm
-        const int req = splitk_for(M, N, K);
+        const int req = is_split(precision) ? splitk_for_split(M, N, K) : splitk_for(M, N, K);
         const int ks = splitk_chunks(K, req, 16);
         const CView<float> A{(const float*)a_re, (const float*)a_im, lda};
         const CView<float> B{(const float*)b_re, (const float*)b_im, ldb};
