@@ -188,15 +188,43 @@ __device__ bool wait_step_acquire(int* flags, int* grp_flags, int g0, int count,
     return ok;
 }
 
+// The value of lane ^ M.  Partners within a row of 16 lanes (M <= 8) move through DPP
+// (quad permutations; row shifts left / right by M, selected by bit M of the lane), which
+// stays in the VALU; the row-crossing ones (16, 32) through the LDS crossbar.
+template <int CTRL>
+__device__ inline double dpp_mov(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int M>
+__device__ inline double xor_lane(double v, int lane) {
+    if constexpr (M == 1) return dpp_mov<0xB1>(v);                    // quad_perm [1, 0, 3, 2]
+    else if constexpr (M == 2) return dpp_mov<0x4E>(v);               // quad_perm [2, 3, 0, 1]
+    else if constexpr (M == 4 || M == 8) {
+        const double up = dpp_mov<0x100 + M>(v);                         // row_shl: from lane + M
+        const double dn = dpp_mov<0x110 + M>(v);                         // row_shr: from lane - M
+        return (lane & M) ? dn : up;
+    } else {
+        return __shfl_xor(v, M);
+    }
+}
+
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63;
+    v += xor_lane<32>(v, lane);
+    v += xor_lane<16>(v, lane);
+    v += xor_lane<8>(v, lane);
+    v += xor_lane<4>(v, lane);
+    v += xor_lane<2>(v, lane);
+    v += xor_lane<1>(v, lane);
     return v;
 }
 
 // Sums of 16 values over the 64 lanes of a wave by reduce-scatter: at the
 // exchange with lane ^ 32, ^ 16, ^ 8, ^ 4 each lane keeps half of its values
-// and adds the partner's copy of that half (8 + 4 + 2 + 1 shuffles), then two
+// and adds the partner's copy of that half (8 + 4 + 2 + 1 exchanges), then two
 // plain steps finish.  On return every lane holds the total of value
 // index (lane >> 2) & 15 in bit-reversed order; see sum16_index().
 __device__ inline double wave_sum16(double (&v)[16], int lane) {
@@ -204,28 +232,28 @@ __device__ inline double wave_sum16(double (&v)[16], int lane) {
     for (int k = 0; k < 8; ++k) {
         const bool hi = lane & 32;
         const double keep = hi ? v[8 + k] : v[k], give = hi ? v[k] : v[8 + k];
-        v[k] = keep + __shfl_xor(give, 32);
+        v[k] = keep + xor_lane<32>(give, lane);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const bool hi = lane & 16;
         const double keep = hi ? v[4 + k] : v[k], give = hi ? v[k] : v[4 + k];
-        v[k] = keep + __shfl_xor(give, 16);
+        v[k] = keep + xor_lane<16>(give, lane);
     }
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const bool hi = lane & 8;
         const double keep = hi ? v[2 + k] : v[k], give = hi ? v[k] : v[2 + k];
-        v[k] = keep + __shfl_xor(give, 8);
+        v[k] = keep + xor_lane<8>(give, lane);
     }
     {
         const bool hi = lane & 4;
         const double keep = hi ? v[1] : v[0], give = hi ? v[0] : v[1];
-        v[0] = keep + __shfl_xor(give, 4);
+        v[0] = keep + xor_lane<4>(give, lane);
     }
     double r = v[0];
-    r += __shfl_xor(r, 2);
-    r += __shfl_xor(r, 1);
+    r += xor_lane<2>(r, lane);
+    r += xor_lane<1>(r, lane);
     return r;
 }
 // Index (0..15) of the value whose total wave_sum16 leaves in this lane.
@@ -414,11 +442,12 @@ __global__ __launch_bounds__(TT, 1) void hetrd_kernel(TrBatch batch) {
                 pdt = cjmul(yc, vc);
             }
             static_assert(TC == 8, "the y^H v share sums lanes 0..7");
-#pragma unroll
-            for (int o = 4; o > 0; o >>= 1) {
-                pdt.x += __shfl_xor(pdt.x, o);
-                pdt.y += __shfl_xor(pdt.y, o);
-            }
+            pdt.x += xor_lane<4>(pdt.x, lane);
+            pdt.y += xor_lane<4>(pdt.y, lane);
+            pdt.x += xor_lane<2>(pdt.x, lane);
+            pdt.y += xor_lane<2>(pdt.y, lane);
+            pdt.x += xor_lane<1>(pdt.x, lane);
+            pdt.y += xor_lane<1>(pdt.y, lane);
             if (tid == 0) st_coh(&g.pdot[(int64_t)buf * P + wg], pdt);
         }
         // d_i before x is reused
