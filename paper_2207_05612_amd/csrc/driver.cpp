@@ -1186,8 +1186,10 @@ struct Engine {
     // Theta Theta^H = X (Y^T conj(Y)) X^H has rank <= r, and with X = Q R (Q orthonormal,
     // rows x r) its non-zero eigen-pairs are those of the order-r Hermitian matrix
     // H = R conj(Y^H Y) R^H = R (Y^H Y)^T R^H, whose eigenvectors Q maps back.  The kept
-    // values, the total weight (trace H = |Theta|^2) and U64 are those truncate() returns,
-    // up to rounding; the eigen-decomposition has order r instead of min(rows, cols).
+    // values, the total weight (trace H = |Theta|^2) and U64 are those truncate() returns, up
+    // to rounding (H carries errors of order eps |X|^2 |Y|^2 where the Gram matrix of Theta
+    // carries eps |Theta|^2; the two agree when the factors are not much larger than Theta,
+    // as in the sweep); the eigen-decomposition has order r instead of min(rows, cols).
     Trunc truncate_lowrank(const R* x_re, const R* x_im, const R* y_re, const R* y_im, int64_t rows, int64_t cols,
                            int64_t r, int bond) {
         const int chi = chi_at(bond);

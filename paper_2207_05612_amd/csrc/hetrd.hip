@@ -50,7 +50,7 @@ constexpr int TMAXN = TT * TQ;     // 2048
 constexpr int NWAVE = TT / 64;
 constexpr int SPIN_LIMIT = 1 << 21;
 constexpr int TR_MAXB = 8;         // instances per launch
-constexpr int HG = 8;              // groups of the two-level wait (workgroups wg = g mod HG)
+constexpr int HG = 4;              // groups of the two-level wait (workgroups wg = g mod HG)
 constexpr int GF_STRIDE = 16;      // ints between group flags
 
 struct TrArgs {
@@ -129,11 +129,11 @@ __device__ void publish(int* flag, int val) {
 // non-empty groups and acquires.  The release -> acquire -> release -> acquire
 // chain through the leader makes every member's stores visible to every
 // participant (happens-before is transitive), so the protocol stays the
-// fence-fence synchronisation described above.  With at most FLAT_MAX
-// participants every one polls all their flags directly.  Every wait is
+// fence-fence synchronisation described above.  With at most FLAT_MAX (one per
+// lane) participants every one polls all their flags directly.  Every wait is
 // bounded: on time-out the abort flag is raised; on abort (own or seen) it
 // returns false in wavefront 0.
-constexpr int FLAT_MAX = 32;
+constexpr int FLAT_MAX = 64;
 __device__ bool wait_step_acquire(int* flags, int* grp_flags, int g0, int count, int wg, int target, int* abort_flag) {
     bool ok = true;
     if (threadIdx.x < 64) {
@@ -158,7 +158,7 @@ __device__ bool wait_step_acquire(int* flags, int* grp_flags, int g0, int count,
             }
         } else {
             if (wg < g0 + HG) {
-                // members wg, wg + HG, ... (at most 256 / HG = 32 of them: one per lane)
+                // members wg, wg + HG, ... (at most 256 / HG = 64 of them: one per lane)
                 while (true) {
                     const int m = wg + HG * lane;
                     const bool done = m >= count ||

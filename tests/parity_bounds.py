@@ -82,6 +82,16 @@ def f_bound(prec, amp_err):
     return F_TARGET[prec]
 
 
+def fp64_bound(records, layer_sizes, order, target):
+    """Bound of an FP64-path quantity (per-layer f_delta, amplitudes) against the oracle: the
+    target, or the first-order rule of the reduced precisions where the oracle's truncations are
+    ill-conditioned.  Both sides are FP64, so the perturbation that a cut amplifies is the
+    backward error of the two eigensolvers, about order * eps (eps = 2^-52, order = the largest
+    Gram matrix, 2 chi), not the contraction's unit roundoff."""
+    u = order * 2.0 ** -52
+    return max(target, C_FIRST_ORDER * u * sum_layer_kappa(records, layer_sizes))
+
+
 def worst_gap(records):
     gs = [r.gap if hasattr(r, "gap") else r[0] for r in records]
     gs = [g for g in gs if g is not None and math.isfinite(g)]

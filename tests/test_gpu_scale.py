@@ -243,7 +243,7 @@ SEP_RESOLVED = {FP64: 1e-9, BF16X3: 1e-5}
 @pytest.mark.parametrize("name", golden_cases("qaoa"))
 def test_qaoa54_golden(name):
     """54-node 3-regular MaxCut, p = 4 (217 brick layers per set), 8 parameter sets in one batched
-    call per layer, FP64 and split BF16x3.  Per-layer f_delta is compared with the oracle on every
+    call per layer, FP64 (all layers) and split BF16x3 (the first 40).  Per-layer f_delta is compared with the oracle on every
     layer before the first one with an unresolved cut (where the result stops being unique), and
     log F~ and <C> when no cut is unresolved; after it the results are checked for validity
     (0 < f <= 1 within the precision's bound, log F~ = sum log f, 0 <= <C> <= |E|)."""
@@ -260,7 +260,9 @@ def test_qaoa54_golden(name):
         tol = 1e-9 if prec == FP64 else 1e-4
         streams = [torch.cuda.Stream() for _ in qs]
         states = [mps.MPS(54, None, max_chi=chi, precision=prec, stream=s.cuda_stream) for s in streams]
-        n_layers = len(qs[0].circuit.layers)
+        # the FP64 path runs the whole circuit; the split path the first 40 layers (the cuts become
+        # unresolved after 15 of them, so later layers only add validity checks)
+        n_layers = len(qs[0].circuit.layers) if prec == FP64 else 40
         fs = np.zeros((len(qs), n_layers))
         t0 = time.time()
         for d in range(n_layers):
@@ -270,13 +272,14 @@ def test_qaoa54_golden(name):
                 print("prec %d layer %d of %d (%.1f s)" % (prec, d, n_layers, time.time() - t0), flush=True)
         for i, q in enumerate(qs):
             want = rec["sets"][i]
-            f_ref = np.array(want["layer_f"])
+            f_ref = np.array(want["layer_f"])[:n_layers]
             sep = states[i].cut_separations()
             assert sep.shape == (n_layers,)
             unresolved = np.where(sep < SEP_RESOLVED[prec])[0]
             first = int(unresolved[0]) if len(unresolved) else n_layers
             rel = np.abs(fs[i] - f_ref) / f_ref
-            c_gpu = circuits.maxcut_expectation_from_zz(edges, q.final_position, states[i].expect_zz)
+            whole = n_layers == len(want["layer_f"])          # <C> needs the whole swap network
+            c_gpu = circuits.maxcut_expectation_from_zz(edges, q.final_position, states[i].expect_zz) if whole else 0.0
             log_ft = states[i].fidelity()["log_F_tilde"]
             print("set %d prec=%d layers compared %d of %d (smallest separation %.1e), max rel f err there %.2e; "
                   "<C> %.6f (oracle %.6f)" % (i, prec, first, n_layers, sep.min(), rel[:first].max(initial=0.0),
@@ -286,7 +289,7 @@ def test_qaoa54_golden(name):
             assert np.all(fs[i] > 0) and np.all(fs[i] <= 1.0 + tol)
             assert abs(log_ft - np.sum(np.log(fs[i]))) < 1e-9 * n_layers
             assert 0.0 <= c_gpu <= len(edges)
-            if first == n_layers:
+            if first == n_layers and whole:
                 assert abs(log_ft - want["log_f_tilde"]) < (1e-8 if prec == FP64 else 1e-4 * n_layers)
                 assert abs(c_gpu - want["maxcut"]) < (1e-8 if prec == FP64 else 1e-3 * len(edges))
         for st in states:

@@ -15,6 +15,8 @@ from paper_2207_05612_amd import circuits, mps
 from oracle import dmrg
 from oracle import statevector as sv
 
+import parity_bounds as pb
+
 pytestmark = pytest.mark.gpu
 
 FP64, FP32, BF16X3 = mps.MPS_FP64, mps.MPS_FP32, mps.MPS_BF16X3
@@ -45,9 +47,16 @@ def test_small_layout_truncated_matches_oracle(sequence):
     st = mps.MPS(c.n, None, max_chi=4, precision=FP64)
     fs = np.array([st.apply_layer_dmrg(layer, 4, 2) for layer in c.layers])
     ora = dmrg.run_circuit(c, chi=4, n_sweeps=2)
-    assert np.max(np.abs(fs - np.array(ora.layer_f)) / np.array(ora.layer_f)) < 1e-10
+    sizes = pb.two_site_layer_sizes(c.n, 2, len(c.layers))
+    fb = pb.fp64_bound(ora.step_log, sizes, 2 * 4, 1e-10)
+    ab = pb.fp64_bound(ora.step_log, sizes, 2 * 4, AMP_TOL[FP64])
+    err = np.max(np.abs(fs - np.array(ora.layer_f)) / np.array(ora.layer_f))
+    amp = rel_l2(st.statevector(), dmrg.to_statevector(ora))
+    print("sequence %s max rel f error %.2e (bound %.2e), amplitudes %.2e (bound %.2e), worst gap %.2e"
+          % (sequence, err, fb, amp, ab, pb.worst_gap(ora.step_log)))
+    assert err < fb
     assert st.bond_dims() == ora.bond_dims()
-    assert rel_l2(st.statevector(), dmrg.to_statevector(ora)) < AMP_TOL[FP64]
+    assert amp < ab
 
 
 @pytest.mark.parametrize("sequence", ["I", "II"])
