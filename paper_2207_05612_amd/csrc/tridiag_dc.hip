@@ -561,6 +561,257 @@ __global__ __launch_bounds__(256) void dc_gemm_kernel(DcArgs g, int t) {
             }
 }
 
+// Merges of at most SMALL_M rows: every step of a merge in one workgroup, on LDS copies (the
+// steps are those of the kernels above; one launch per depth instead of seven).
+constexpr int SMALL_M = 64;
+
+// Root j of 1 + sum_i w_i / (d_i - lambda) (w_i = rho z_i^2 > 0, d ascending, K terms in LDS) by
+// one thread: the nearer pole o and tau with lambda = d_o + tau, as in dc_secular_kernel.
+__device__ void secular_root_serial(const double* d, const double* w, int K, int j, int& o_out, double& tau_out) {
+    auto eval = [&](int o, double tau, double& psi, double& dpsi, double& phi, double& dphi) {
+        const double d_o = d[o];
+        psi = dpsi = phi = dphi = 0.0;
+        for (int i = 0; i < K; ++i) {
+            const double del = (d[i] - d_o) - tau;
+            const double tm = w[i] / del;
+            const double dt = tm / del;
+            if (i <= j) { psi += tm; dpsi += dt; }
+            else        { phi += tm; dphi += dt; }
+        }
+    };
+    int o;
+    double lo, hi, psi, dpsi, phi, dphi;
+    const bool last = j == K - 1;
+    if (!last) {
+        const double gap = d[j + 1] - d[j];
+        eval(j, 0.5 * gap, psi, dpsi, phi, dphi);
+        if (1.0 + psi + phi >= 0.0) { o = j;     lo = 0.0;        hi = 0.5 * gap; }
+        else                        { o = j + 1; lo = -0.5 * gap; hi = 0.0; }
+    } else {
+        double ws = 0.0;
+        for (int i = 0; i < K; ++i) ws += w[i];
+        o = j;
+        lo = 0.0;
+        hi = ws;
+    }
+    const double dl = d[j] - d[o];
+    const double dr = last ? 0.0 : d[j + 1] - d[o];
+    double tau = o == j ? hi : lo;
+    for (int it = 0; it < SEC_MAX_IT; ++it) {
+        eval(o, tau, psi, dpsi, phi, dphi);
+        const double f = 1.0 + psi + phi;
+        if (f < 0.0) lo = fmax(lo, tau);
+        else         hi = fmin(hi, tau);
+        if (fabs(f) <= 32.0 * DC_EPS * (1.0 + phi - psi) || hi - lo <= 4.0 * DC_EPS * fmax(fabs(lo), fabs(hi))) break;
+        const double A = dl - tau;
+        const double qq = dpsi * A * A;
+        const double pp = psi - dpsi * A;
+        double eta;
+        if (!last) {
+            const double B = dr - tau;
+            const double ss = dphi * B * B;
+            const double rr = phi - dphi * B;
+            const double c0 = 1.0 + pp + rr;
+            const double bb = c0 * (A + B) + qq + ss;
+            const double cc = A * B * f;
+            const double disc = fmax(bb * bb - 4.0 * c0 * cc, 0.0);
+            const double den = bb + copysign(sqrt(disc), bb);
+            eta = den != 0.0 ? 2.0 * cc / den : 0.0;
+        } else {
+            const double c0 = 1.0 + pp;
+            eta = c0 != 0.0 ? A + qq / c0 : 0.0;
+        }
+        if (fabs(eta) <= 2.0 * DC_EPS * fabs(tau)) break;
+        double nt = tau + eta;
+        if (!(nt > lo && nt < hi)) nt = 0.5 * (lo + hi);
+        tau = nt;
+    }
+    o_out = o;
+    tau_out = tau;
+}
+
+__global__ __launch_bounds__(256) void dc_small_merge_kernel(DcArgs g, int t) {
+    const int n = g.n, tid = threadIdx.x;
+    int a, b;
+    node_range(t, blockIdx.x, n, a, b);
+    if (b == a) return;
+    const int c = (int)(((int64_t)(2 * blockIdx.x + 1) * n) >> (t + 1));
+    if (c == a || c == b) return;                          // one child: already in place
+    const int m = b - a;                                   // <= SMALL_M
+    const double beta = g.e[c - 1];
+    const double rho = 2.0 * fabs(beta);
+    const double sgn = beta >= 0.0 ? 1.0 : -1.0;
+
+    __shared__ double sd[SMALL_M], sz[SMALL_M], sw[SMALL_M], zh[SMALL_M], rt[SMALL_M];
+    __shared__ int sc[SMALL_M], ro[SMALL_M], pos_of[SMALL_M], nd[SMALL_M];
+    __shared__ unsigned char typ[SMALL_M];
+    __shared__ double qg[SMALL_M][SMALL_M + 1];          // gathered columns, then rotated
+    __shared__ double uu[SMALL_M][SMALL_M + 1];          // uu[i][j] = u_j[i]
+    __shared__ double rot_c[SMALL_M], rot_s[SMALL_M];
+    __shared__ int rot_p[SMALL_M], rot_q[SMALL_M];
+    __shared__ int sh_K, sh_R;
+    __shared__ double sh_tol;
+
+    int P2 = 1;
+    while (P2 < m) P2 <<= 1;
+    // 1. sort (d, z, source column) ascending by d
+    if (tid < P2) {
+        if (tid < m) {
+            const int col = a + tid;
+            sd[tid] = g.lam[col];
+            const double zr = col < c ? g.zw[(c - 1) + (int64_t)col * n] : sgn * g.zw[c + (int64_t)col * n];
+            sz[tid] = zr * 0.70710678118654752440;
+            sc[tid] = col;
+        } else {
+            sd[tid] = __builtin_inf();
+            sz[tid] = 0.0;
+            sc[tid] = INT_MAX;
+        }
+    }
+    __syncthreads();
+    for (int k = 2; k <= P2; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (tid < P2) {
+                const int q = tid ^ j;
+                if (q > tid) {
+                    const bool up = (tid & k) == 0;
+                    const bool gt = sd[tid] > sd[q] || (sd[tid] == sd[q] && sc[tid] > sc[q]);
+                    if (gt == up) {
+                        const double td = sd[tid], tz = sz[tid];
+                        const int tc = sc[tid];
+                        sd[tid] = sd[q]; sz[tid] = sz[q]; sc[tid] = sc[q];
+                        sd[q] = td; sz[q] = tz; sc[q] = tc;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    // 2. deflation (one thread: at most SMALL_M entries), positions: survivors first
+    if (tid == 0) {
+        double dm = 0.0;
+        for (int p = 0; p < m; ++p) dm = fmax(dm, fabs(sd[p]));
+        const double tol = 8.0 * DC_EPS * fmax(dm, rho);
+        int R = 0, pj = -1;
+        for (int p = 0; p < m; ++p) {
+            typ[p] = rho * fabs(sz[p]) > tol ? 1 : 0;
+            if (!typ[p]) continue;
+            if (pj >= 0) {
+                double s0 = sz[pj], c0 = sz[p];
+                const double tau = hypot(c0, s0);
+                const double tt = sd[p] - sd[pj];
+                c0 /= tau;
+                s0 = -s0 / tau;
+                if (fabs(tt * c0 * s0) <= tol) {
+                    sz[p] = tau;
+                    sz[pj] = 0.0;
+                    const double dpj = sd[pj] * c0 * c0 + sd[p] * s0 * s0;
+                    sd[p] = sd[pj] * s0 * s0 + sd[p] * c0 * c0;
+                    sd[pj] = dpj;
+                    typ[pj] = 0;
+                    rot_p[R] = pj;
+                    rot_q[R] = p;
+                    rot_c[R] = c0;
+                    rot_s[R] = s0;
+                    ++R;
+                }
+            }
+            pj = p;
+        }
+        int K = 0;
+        for (int p = 0; p < m; ++p)
+            if (typ[p]) nd[K++] = p;
+        int q = K;
+        for (int p = 0; p < m; ++p)
+            if (!typ[p]) nd[q++] = p;                  // deflated after the survivors
+        for (int i = 0; i < m; ++i) pos_of[nd[i]] = i;
+        sh_K = K;
+        sh_R = R;
+        sh_tol = tol;
+    }
+    __syncthreads();
+    const int K = sh_K, R = sh_R;
+    // 3. gathered columns in sorted order (explicit zeros off the children's blocks), then the
+    //    rotations in order; qg[r][p] is row a + r of sorted entry p's column
+    for (int idx = tid; idx < m * m; idx += 256) {
+        const int r = idx % m, p = idx / m;
+        const int col = sc[p];
+        const int lo = col < c ? a : c, hi = col < c ? c : b;
+        const int row = a + r;
+        qg[r][p] = (row >= lo && row < hi) ? g.zw[row + (int64_t)col * n] : 0.0;
+    }
+    __syncthreads();
+    if (tid < m)
+        for (int k = 0; k < R; ++k) {
+            const double xv = qg[tid][rot_p[k]], yv = qg[tid][rot_q[k]];
+            qg[tid][rot_p[k]] = rot_c[k] * xv + rot_s[k] * yv;
+            qg[tid][rot_q[k]] = rot_c[k] * yv - rot_s[k] * xv;
+        }
+    // survivors' d and w = rho z^2 in nd order
+    if (tid < K) {
+        const int p = nd[tid];
+        rt[tid] = sd[p];
+        sw[tid] = rho * sz[p] * sz[p];
+        zh[tid] = sz[p];                               // sign of z for the Lowner vector
+    }
+    __syncthreads();
+    // 4. roots (one thread each); rt holds d of the survivors, keep it: roots in zh/ro below
+    __shared__ double dsv[SMALL_M], tauv[SMALL_M];
+    if (tid < K) dsv[tid] = rt[tid];
+    __syncthreads();
+    if (tid < K) {
+        int o;
+        double tau;
+        secular_root_serial(dsv, sw, K, tid, o, tau);
+        ro[tid] = o;
+        tauv[tid] = tau;
+        g.lam[a + tid] = dsv[o] + tau;
+    }
+    if (tid >= K && tid < m) g.lam[a + tid] = sd[nd[tid]];
+    __syncthreads();
+    // 5. Lowner's update vector
+    if (tid < K) {
+        const int i = tid;
+        const double di = dsv[i];
+        double v = 1.0;
+        for (int j = 0; j < K; ++j) {
+            const double lm = (dsv[ro[j]] - di) + tauv[j];
+            double den;
+            if (j == K - 1)  den = rho;
+            else if (j < i)  den = dsv[j] - di;
+            else             den = dsv[j + 1] - di;
+            v *= lm / den;
+        }
+        rt[i] = copysign(sqrt(fmax(v, 0.0)), zh[i]);   // zhat
+    }
+    __syncthreads();
+    // 6. eigenvectors of D + rho zhat zhat^T
+    if (tid < K) {
+        const int j = tid;
+        const double d_o = dsv[ro[j]], tau = tauv[j];
+        double s2 = 0.0;
+        for (int i = 0; i < K; ++i) {
+            const double u = rt[i] / ((dsv[i] - d_o) - tau);
+            uu[i][j] = u;
+            s2 += u * u;
+        }
+        const double inv = 1.0 / sqrt(s2);
+        for (int i = 0; i < K; ++i) uu[i][j] *= inv;
+    }
+    __syncthreads();
+    // 7. merged vectors: column j < K = sum_i qg[:, nd[i]] u_j[i]; deflated columns copied
+    for (int idx = tid; idx < m * m; idx += 256) {
+        const int r = idx % m, j = idx / m;
+        double v;
+        if (j < K) {
+            v = 0.0;
+            for (int i = 0; i < K; ++i) v += qg[r][nd[i]] * uu[i][j];
+        } else {
+            v = qg[r][nd[j]];
+        }
+        g.zw[(a + r) + (int64_t)(a + j) * n] = v;
+    }
+}
+
 // Final order: eigenvalues ascending (ties by column), one workgroup.
 __global__ __launch_bounds__(1024) void dc_sort_kernel(DcArgs g, double* __restrict__ w) {
     const int n = g.n, tid = threadIdx.x;
@@ -655,6 +906,10 @@ hipError_t stedc_dc(int n, double* d, const double* e, double* z, int ldz, void*
         const int merges = 1 << t;
         const int mmax = (n + merges - 1) / merges;
         const int tiles = (mmax + GT - 1) / GT;
+        if (mmax <= SMALL_M) {
+            hipLaunchKernelGGL(dc_small_merge_kernel, dim3(merges), dim3(256), 0, stream, g, t);
+            continue;
+        }
         hipLaunchKernelGGL(dc_scan_kernel, dim3(merges), dim3(256), 0, stream, g, t);
         hipLaunchKernelGGL(dc_gather_kernel, dim3(n), dim3(256), 0, stream, g, t);
         hipLaunchKernelGGL(dc_rotate_kernel, dim3(merges, (mmax + 63) / 64), dim3(64), 0, stream, g, t);
