@@ -44,7 +44,7 @@ DEPTH = 20
 PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0 / 6.0, "bf16x2": 2500.0 / 3.0}
 DTYPE = {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3-f32acc", "bf16x2": "bf16x2-f32acc"}
 GEMM_KERNEL = {"fp32": "cgemm_kernel<float>", "fp64": "cgemm_kernel<double>",
-               "bf16x3": "cgemm_bf16x3_nt_kernel", "bf16x2": "cgemm_bf16x2_nt_kernel"}
+               "bf16x3": "cgemm_bf16x3_planes_kernel", "bf16x2": "cgemm_bf16x2_planes_kernel"}
 GEMM_SOURCE = {"fp32": ("cgemm.hip",), "fp64": ("cgemm.hip",), "bf16x3": ("cgemm_bf16.hip",),
                "bf16x2": ("cgemm_bf16.hip",)}
 HBM_PEAK_GBS = 8000.0

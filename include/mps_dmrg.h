@@ -405,7 +405,10 @@ mps_status mps_kernel_selftest_stedc(int n, const double* d, const double* e, do
  * All calls on one GPU share its scratch array: calls that overlap in time on
  * that GPU (different streams or threads) race and give wrong results; calls
  * on one stream are ordered and safe.  Results equal those of
- * mps_kernel_selftest_cgemm on the same operands (same kernels, same split). */
+ * mps_kernel_selftest_cgemm on the same operands, bit for bit (same split of
+ * K; for the split precisions the same BF16 terms, k tiles and MFMA order,
+ * with each tile's operands split while they are staged instead of in one
+ * pass beforehand). */
 mps_status mps_cgemm_noalloc(int precision, int opa, int opb, int M, int N, int K,
                              const void* a_re, const void* a_im, int64_t lda,
                              const void* b_re, const void* b_im, int64_t ldb,

@@ -26,6 +26,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace mpsk {
@@ -33,6 +35,7 @@ namespace mpsk {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 struct SplitArgs {
     const float* a_re;
@@ -202,8 +205,8 @@ __device__ __forceinline__ void cgemm_split_body(const SplitArgs& g) {
                 for (int j = 0; j < 2; ++j) {
                     const bf16x8 fbr = *(const bf16x8*)&Bs[buf][lds_off<SBN>(sb, 0, lchunk, wn0 + j * 32 + lrow)];
                     const bf16x8 fbi = *(const bf16x8*)&Bs[buf][lds_off<SBN>(sb, 1, lchunk, wn0 + j * 32 + lrow)];
-                    u16x8 t = __builtin_bit_cast(u16x8, fbi);
-                    t ^= (unsigned short)0x8000;
+                    // -b_im: flip the sign bit of each BF16 (two per 32-bit word)
+                    const u32x4 t = __builtin_bit_cast(u32x4, fbi) ^ 0x80008000u;
                     const bf16x8 fbn = __builtin_bit_cast(bf16x8, t);
 #pragma unroll
                     for (int i = 0; i < 2; ++i) {
@@ -304,6 +307,306 @@ static hipError_t launch_split(int terms, int M, int N, int K, CView<float> A, C
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Operands split once per product.  The kernels above split every k tile as it
+// is staged, so a row of A is split again for every tile column of C and a row
+// of B for every tile row.  Here split_planes_kernel writes the S BF16 terms of
+// an operand once, as planes, and the product kernel streams the planes from
+// memory straight into LDS (global_load_lds_dwordx4: no registers, no VALU).
+// The terms, the LDS layout, the MFMA sequence and the k tiles (k padded to a
+// multiple of 16 with zeros) are those of the kernels above, so both give
+// bit-identical products.
+//
+// Plane layout: plane (s, p) (term s, part p = re / im) of an operand of
+// `rows` rows holds R x Kp BF16 values, R = rows rounded up to the tile (256
+// for A, 128 for B), Kp = K rounded up to 16, entries beyond K and rows past
+// `rows` zero; it starts at ((s * 2 + p) R Kp) and stores (row, k) at
+// ((k / 8) R + row) 8 + k mod 8: the 8 k of one MFMA lane are 16 bytes, and
+// consecutive rows follow each other.  That is the LDS layout of a tile, so
+// one wavefront load moves 64 rows x 16 bytes, 1 KiB of contiguous memory.
+
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+// One block step covers 64 rows x 4 groups of 8 k: each wavefront writes one
+// group of 64 rows (1 KiB contiguous), and the four wavefronts together read
+// whole 128-byte lines of the source rows.
+template <int S, bool VEC>
+__global__ __launch_bounds__(256) void split_planes_kernel(const float* __restrict__ re, const float* __restrict__ im,
+                                                           int64_t ld, int rows, int rows_pad, int K, int Kp,
+                                                           unsigned short* __restrict__ planes) {
+    const int gpr = Kp >> 3;                       // groups of 8 k per row
+    const int nkb = (gpr + 3) >> 2;                // blocks of 4 groups
+    const int64_t units = (int64_t)(rows_pad >> 6) * nkb;
+    const int64_t plane = (int64_t)rows_pad * Kp;
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int64_t row = (u / nkb) * 64 + (threadIdx.x & 63);
+        const int kg = (int)(u % nkb) * 4 + (threadIdx.x >> 6);
+        if (kg >= gpr) continue;
+        const int k0 = kg * 8;
+        const bool live = row < rows;
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const float* src = (p ? im : re) + (live ? row : 0) * ld + k0;
+            float x[8];
+            if (!live) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) x[e] = 0.f;
+            } else if (VEC && k0 + 8 <= K) {
+                const f32x4v lo = *(const f32x4v*)src, hi = *(const f32x4v*)(src + 4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) { x[e] = lo[e]; x[e + 4] = hi[e]; }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) x[e] = k0 + e < K ? src[e] : 0.f;
+            }
+            u16x8 h, m, l;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                if (S == 3) {
+                    unsigned short a, b, c;
+                    split3(x[e], a, b, c);
+                    h[e] = a; m[e] = b; l[e] = c;
+                } else {
+                    h[e] = bf16_rne(x[e]);
+                    m[e] = bf16_rne(x[e] - bf16_to_float(h[e]));
+                }
+            }
+            unsigned short* dst = planes + (int64_t)p * plane + ((int64_t)kg * rows_pad + row) * 8;
+            *(u16x8*)dst = h;
+            *(u16x8*)(dst + 2 * plane) = m;
+            if (S == 3) *(u16x8*)(dst + 4 * plane) = l;
+        }
+    }
+}
+
+struct PlaneArgs {
+    const unsigned short* a;   // planes of A (M rows)
+    const unsigned short* b;   // planes of B (N rows)
+    float* c_re;
+    float* c_im;
+    int64_t ldc;
+    int M, N, Kp;
+    int gm, gn;
+    int kchunk;                // k range of split blockIdx.y (a multiple of 16)
+    int64_t split_stride;      // C offset of split y
+};
+
+// 16 bytes per lane from global memory into LDS: lane l of the wavefront reads
+// base + lane_bytes (base the same in every lane, lane_bytes zero-extended, so
+// that the load takes the scalar-base form) and writes lds_wave_base + 16 l.
+// The base goes through readfirstlane: it is uniform anyway, and the compiler
+// then keeps it in scalar registers instead of forming one 64-bit vector
+// address per load outside the k loop.
+typedef const __attribute__((address_space(1))) char* gchar_ptr;
+__device__ __forceinline__ void dma16(const unsigned short* base, unsigned lane_bytes, unsigned short* lds_wave_base) {
+    const uint64_t v = (uint64_t)base;
+    const uint64_t u = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32)) << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)((gchar_ptr)u + lane_bytes),
+                                     (__attribute__((address_space(3))) void*)lds_wave_base, 16, 0, 0);
+}
+
+template <int S>
+__device__ __forceinline__ void cgemm_planes_body(const PlaneArgs& g) {
+    // two buffers as separate objects, so that the compiler can tell the LDS
+    // reads of one buffer from the loads in flight into the other
+    __shared__ __attribute__((aligned(16))) unsigned short As0[S * 2 * 2 * SBM * 8];
+    __shared__ __attribute__((aligned(16))) unsigned short As1[S * 2 * 2 * SBM * 8];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs0[S * 2 * 2 * SBN * 8];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs1[S * 2 * 2 * SBN * 8];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm0 = (wave >> 1) * 64;
+    const int wn0 = (wave & 1) * 64;
+
+    int pid = blockIdx.x;
+    const int nb = g.gm * g.gn;
+    if ((nb & 7) == 0) pid = (pid & 7) * (nb >> 3) + (pid >> 3);
+    constexpr int GROUP = 8;
+    const int group = pid / (GROUP * g.gn);
+    const int first_m = group * GROUP;
+    const int gsz = min(g.gm - first_m, GROUP);
+    const int tm = first_m + (pid % gsz);
+    const int tn = (pid % (GROUP * g.gn)) / gsz;
+    const int m0 = tm * SBM, n0 = tn * SBN;
+    const int M = g.M, N = g.N;
+    const int kbeg = blockIdx.y * g.kchunk;
+    const int nk = (min(g.Kp, kbeg + g.kchunk) - kbeg) / SBK;
+    float* const c_re = g.c_re + blockIdx.y * g.split_stride;
+    float* const c_im = g.c_im + blockIdx.y * g.split_stride;
+    // padded rows and plane sizes
+    const int64_t ra = (int64_t)g.gm * SBM, rbn = (int64_t)g.gn * SBN;
+    const int64_t pa = ra * g.Kp, pb = rbn * g.Kp;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);   // the wavefront index as a scalar
+    const unsigned lane_bytes = (unsigned)lane * 16u;
+
+    // One k tile is 16 S wavefront loads for A ((s, p, c) x 4 blocks of 64 rows)
+    // and 8 S for B; wavefront w issues loads w, w + 8, ...  Each load moves the
+    // 16 bytes (8 k) of 64 consecutive rows, 1 KiB contiguous in the planes.
+    auto issue = [&](unsigned short* as, unsigned short* bs, int k0) {
+        const int kg0 = k0 >> 3;
+#pragma unroll
+        for (int u = 0; u < 3 * S; ++u) {
+            const int q = wv + 8 * u;
+            if (u < 2 * S) {
+                const int rb = q & 3, spc = q >> 2, c = spc & 1, sp = spc >> 1;
+                const unsigned short* base = g.a + (sp * pa + ((int64_t)(kg0 + c) * ra + m0 + rb * 64) * 8);
+                dma16(base, lane_bytes, as + (spc * SBM + rb * 64) * 8);
+            } else {
+                const int qb = q - 16 * S;
+                const int rb = qb & 1, spc = qb >> 1, c = spc & 1, sp = spc >> 1;
+                const unsigned short* base = g.b + (sp * pb + ((int64_t)(kg0 + c) * rbn + n0 + rb * 64) * 8);
+                dma16(base, lane_bytes, bs + (spc * SBN + rb * 64) * 8);
+            }
+        }
+    };
+
+    f32x16 acc_re[2][2], acc_im[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) { acc_re[i][j][v] = 0.f; acc_im[i][j][v] = 0.f; }
+
+    const int lrow = lane & 31;
+    const int lchunk = lane >> 5;
+    auto compute = [&](const unsigned short* as, const unsigned short* bs) {
+#pragma unroll
+        for (int sa = 0; sa < S; ++sa) {
+            bf16x8 fa[2][2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+                    fa[i][p] = *(const bf16x8*)&as[lds_off<SBM>(sa, p, lchunk, wm0 + i * 32 + lrow)];
+            for (int sb = 0; sb < S - sa; ++sb) {
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const bf16x8 fbr = *(const bf16x8*)&bs[lds_off<SBN>(sb, 0, lchunk, wn0 + j * 32 + lrow)];
+                    const bf16x8 fbi = *(const bf16x8*)&bs[lds_off<SBN>(sb, 1, lchunk, wn0 + j * 32 + lrow)];
+                    // -b_im: flip the sign bit of each BF16 (two per 32-bit word)
+                    const u32x4 t = __builtin_bit_cast(u32x4, fbi) ^ 0x80008000u;
+                    const bf16x8 fbn = __builtin_bit_cast(bf16x8, t);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][0], fbr, acc_re[i][j], 0, 0, 0);
+                        acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][0], fbi, acc_im[i][j], 0, 0, 0);
+                        acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][1], fbn, acc_re[i][j], 0, 0, 0);
+                        acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][1], fbr, acc_im[i][j], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    };
+
+    // Tile t is in buffer t mod 2.  The loads of tile t + 1 are issued before
+    // the MFMAs of tile t; the wait and the barrier after them make tile t + 1
+    // visible and end every wavefront's reads of tile t before its buffer is
+    // loaded again.
+    if (nk > 0) {
+        issue(As0, Bs0, kbeg);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
+    for (int kt = 0; kt < nk; ++kt) {
+        const bool odd = kt & 1;
+        if (kt + 1 < nk) issue(odd ? As0 : As1, odd ? Bs0 : Bs1, kbeg + (kt + 1) * SBK);
+        compute(odd ? As1 : As0, odd ? Bs1 : Bs0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int r = m0 + wm0 + i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+                const int c = n0 + wn0 + j * 32 + lrow;
+                if (r < M && c < N) {
+                    const int64_t off = (int64_t)r * g.ldc + c;
+                    c_re[off] = acc_re[i][j][v];
+                    c_im[off] = acc_im[i][j][v];
+                }
+            }
+}
+
+__global__ __launch_bounds__(NT, 1) void cgemm_bf16x3_planes_kernel(PlaneArgs g) { cgemm_planes_body<3>(g); }
+__global__ __launch_bounds__(NT, 1) void cgemm_bf16x2_planes_kernel(PlaneArgs g) { cgemm_planes_body<2>(g); }
+
+static int64_t pad_rows(int rows, bool is_a) {
+    const int t = is_a ? SBM : SBN;
+    return ((int64_t)rows + t - 1) / t * t;
+}
+
+int64_t split_planes_elems(int terms, int rows, int K, bool is_a) {
+    return (int64_t)terms * 2 * pad_rows(rows, is_a) * (((int64_t)K + SBK - 1) / SBK * SBK);
+}
+
+hipError_t split_planes(int terms, int rows, int K, bool is_a, CView<float> X, unsigned short* planes,
+                        hipStream_t stream) {
+    if (rows <= 0 || K <= 0) return hipSuccess;
+    if (terms != 2 && terms != 3) return hipErrorInvalidValue;
+    const int Kp = (K + SBK - 1) / SBK * SBK;
+    const int64_t rp = pad_rows(rows, is_a);
+    if (rp > 0x7fffffff) return hipErrorInvalidValue;
+    const int64_t units = (rp >> 6) * (((Kp >> 3) + 3) >> 2);
+    const unsigned grid = (unsigned)std::min<int64_t>(units, 65536);
+    const bool vec = (X.ld % 4 == 0) && ((((uintptr_t)X.re) | ((uintptr_t)X.im)) & 15) == 0;
+    const int r = rows, rpi = (int)rp;
+    if (terms == 3) {
+        if (vec) hipLaunchKernelGGL((split_planes_kernel<3, true>), dim3(grid), dim3(256), 0, stream, X.re, X.im, X.ld, r, rpi, K, Kp, planes);
+        else hipLaunchKernelGGL((split_planes_kernel<3, false>), dim3(grid), dim3(256), 0, stream, X.re, X.im, X.ld, r, rpi, K, Kp, planes);
+    } else {
+        if (vec) hipLaunchKernelGGL((split_planes_kernel<2, true>), dim3(grid), dim3(256), 0, stream, X.re, X.im, X.ld, r, rpi, K, Kp, planes);
+        else hipLaunchKernelGGL((split_planes_kernel<2, false>), dim3(grid), dim3(256), 0, stream, X.re, X.im, X.ld, r, rpi, K, Kp, planes);
+    }
+    return hipGetLastError();
+}
+
+// The product of split operands; the k chunks of ksplit are those of launch_split.
+static hipError_t launch_planes(int terms, int M, int N, int K, const unsigned short* pa, const unsigned short* pb,
+                                CViewMut<float> C, int ksplit, int64_t split_stride, hipStream_t stream) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (terms != 2 && terms != 3) return hipErrorInvalidValue;
+    PlaneArgs g;
+    g.a = pa; g.b = pb;
+    g.c_re = C.re; g.c_im = C.im; g.ldc = C.ld;
+    g.M = M; g.N = N;
+    g.Kp = (K + SBK - 1) / SBK * SBK;
+    g.gm = (M + SBM - 1) / SBM;
+    g.gn = (N + SBN - 1) / SBN;
+    if (ksplit < 1) ksplit = 1;
+    g.kchunk = (((K + ksplit - 1) / ksplit) + SBK - 1) / SBK * SBK;
+    if (g.kchunk < SBK) g.kchunk = SBK;
+    ksplit = (K + g.kchunk - 1) / g.kchunk;
+    if (ksplit < 1) ksplit = 1;
+    g.split_stride = ksplit > 1 ? split_stride : 0;
+    const int64_t nblocks = (int64_t)g.gm * g.gn;
+    if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
+    // 16-byte aligned planes for the 16-byte loads
+    if (((((uintptr_t)pa) | ((uintptr_t)pb)) & 15) != 0) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nblocks, (unsigned)ksplit);
+    if (terms == 3) hipLaunchKernelGGL(cgemm_bf16x3_planes_kernel, grid, dim3(NT), 0, stream, g);
+    else hipLaunchKernelGGL(cgemm_bf16x2_planes_kernel, grid, dim3(NT), 0, stream, g);
+    return hipGetLastError();
+}
+
+hipError_t cgemm_bf16_planes(int terms, int M, int N, int K, const unsigned short* pa, const unsigned short* pb,
+                             CViewMut<float> C, hipStream_t stream) {
+    return launch_planes(terms, M, N, K, pa, pb, C, 1, 0, stream);
+}
+
+hipError_t cgemm_bf16_planes_splitk(int terms, int M, int N, int K, const unsigned short* pa,
+                                    const unsigned short* pb, float* ws_re, float* ws_im, int ksplit,
+                                    hipStream_t stream) {
+    return launch_planes(terms, M, N, K, pa, pb, {ws_re, ws_im, N}, ksplit, (int64_t)M * N, stream);
 }
 
 hipError_t cgemm_bf16_nt(int terms, int M, int N, int K, CView<float> A, CView<float> B, CViewMut<float> C,

@@ -505,11 +505,13 @@ struct mps_state {
     rocblas_handle blas = nullptr;
     // scratch
     Planar<float> splitws;         // partial sums of split-K FP32 / split-precision GEMMs
+    Raw<unsigned short> planes;    // BF16 terms of the operands of split-precision GEMMs
     Planar<double> splitws64;      // partial sums of split-K FP64 Gram matrices
     // second stream: the right block of the next two-site step runs on it
     // while the current step's truncation runs on the state's stream
     hipStream_t stream2 = nullptr;
     Planar<float> splitws2;
+    Raw<unsigned short> planes2;
     hipEvent_t ev_order[4] = {nullptr, nullptr, nullptr, nullptr};
     int eigh_method = 1;           // EIGH_PERSISTENT, or EIGH_ROCSOLVER
     bool overlap_right = true;     // right blocks on the second stream
@@ -581,8 +583,9 @@ void flush_timings(mps_state* st) {
 struct Lane {
     hipStream_t s;
     Planar<float>* ws;
+    Raw<unsigned short>* pl;
 };
-Lane main_lane(mps_state* st) { return Lane{st->stream, &st->splitws}; }
+Lane main_lane(mps_state* st) { return Lane{st->stream, &st->splitws, &st->planes}; }
 
 template <typename R>
 hipError_t gemm_raw(int opa, int opb, int M, int N, int K, const R* ar, const R* ai, int64_t lda,
@@ -664,13 +667,26 @@ void gemm_split(mps_state* st, int cls, int64_t M, int64_t N, int64_t K, const f
     const Lane ln = lane ? *lane : main_lane(st);
     const double fl = 8.0 * (double)M * (double)N * (double)K;
     const double by = 8.0 * ((double)M * K + (double)K * N + (double)M * N);
+    const int terms = split_terms(st);
+    // both operands split once into BF16 planes (counted as OTHER, like the split-K sum)
+    const int64_t ea = split_planes_elems(terms, (int)M, (int)K, true);
+    const int64_t eb = split_planes_elems(terms, (int)N, (int)K, false);
+    ln.pl->ensure(ea + eb, ln.s);
+    unsigned short* pa = ln.pl->p;
+    unsigned short* pb = pa + ea;
+    {
+        Timer t(st, MPS_KCLASS_OTHER, 0, 4.0 * ((double)M + N) * K + 2.0 * (ea + eb), ln.s);
+        HIPCHK(split_planes(terms, (int)M, (int)K, true, {ar, ai, lda}, pa, ln.s));
+        HIPCHK(split_planes(terms, (int)N, (int)K, false, {br, bi, ldb}, pb, ln.s));
+        t.done();
+    }
     const int ks = splitk_chunks((int)K, splitk_for_split(M, N, K), 16);
     if (ks > 1) {
         ln.ws->ensure(M * N * ks, ln.s);
         {
             Timer t(st, cls, fl, by, ln.s);
-            HIPCHK(cgemm_bf16_nt_splitk(split_terms(st), (int)M, (int)N, (int)K, {ar, ai, lda}, {br, bi, ldb}, ln.ws->re(),
-                                          ln.ws->im(), splitk_for_split(M, N, K), ln.s));
+            HIPCHK(cgemm_bf16_planes_splitk(terms, (int)M, (int)N, (int)K, pa, pb, ln.ws->re(), ln.ws->im(),
+                                            splitk_for_split(M, N, K), ln.s));
             t.done();
         }
         Timer t(st, MPS_KCLASS_OTHER, 0, 8.0 * (double)M * N * (ks + 1), ln.s);
@@ -678,7 +694,7 @@ void gemm_split(mps_state* st, int cls, int64_t M, int64_t N, int64_t K, const f
         t.done();
     } else {
         Timer t(st, cls, fl, by, ln.s);
-        HIPCHK(cgemm_bf16_nt(split_terms(st), (int)M, (int)N, (int)K, {ar, ai, lda}, {br, bi, ldb}, {cr, ci, ldc}, ln.s));
+        HIPCHK(cgemm_bf16_planes(terms, (int)M, (int)N, (int)K, pa, pb, {cr, ci, ldc}, ln.s));
         t.done();
     }
 }
@@ -1433,7 +1449,7 @@ struct Engine {
     double sweep(int o) {
         if (n < 2) return 0;
         ensure_stream2();
-        const Lane l2 = st->overlap_right ? Lane{st->stream2, &st->splitws2} : main_lane(st);
+        const Lane l2 = st->overlap_right ? Lane{st->stream2, &st->splitws2, &st->planes2} : main_lane(st);
         hipEvent_t ev_start = st->ev_order[0], ev_used = st->ev_order[1];
         hipEvent_t ev_right[2] = {st->ev_order[2], st->ev_order[3]};
         HIPCHK(hipEventRecord(ev_start, s));
@@ -1743,9 +1759,11 @@ mps_status mps_destroy(mps_state* st) {
     st->dscal.release(st->stream);
     st->partial.release(st->stream);
     st->splitws.release(st->stream);
+    st->planes.release(st->stream);
     st->splitws64.release(st->stream);
     if (st->stream2) {
         st->splitws2.release(st->stream2);
+        st->planes2.release(st->stream2);
         (void)hipStreamSynchronize(st->stream2);
         (void)hipStreamDestroy(st->stream2);
         st->stream2 = nullptr;
@@ -2270,12 +2288,20 @@ void selftest_cgemm_impl(int opa, int opb, int M, int N, int K, const double* a,
     const int ks = sizeof(R) == 4 ? splitk_chunks(K, req, 16) : 1;
     float* ws = nullptr;
     if (ks > 1) ws = (float*)dalloc(sizeof(float) * 2 * (size_t)nc * ks, s);
+    // split precision: operands split once into BF16 planes, as in the compression step
+    unsigned short* pl = nullptr;
+    int64_t ea = 0;
+    if (split) {
+        ea = split_planes_elems(split_terms_, M, K, true);
+        const int64_t eb = split_planes_elems(split_terms_, N, K, false);
+        pl = (unsigned short*)dalloc(sizeof(unsigned short) * (size_t)std::max<int64_t>(ea + eb, 1), s);
+        HIPCHK(split_planes(split_terms_, M, K, true, {(const float*)da, (const float*)(da + na), lda}, pl, s));
+        HIPCHK(split_planes(split_terms_, N, K, false, {(const float*)db, (const float*)(db + nb), ldb}, pl + ea, s));
+    }
     if (split && ks > 1)
-        HIPCHK(cgemm_bf16_nt_splitk(split_terms_, M, N, K, {(const float*)da, (const float*)(da + na), lda},
-                                      {(const float*)db, (const float*)(db + nb), ldb}, ws, ws + nc * ks, req, s));
+        HIPCHK(cgemm_bf16_planes_splitk(split_terms_, M, N, K, pl, pl + ea, ws, ws + nc * ks, req, s));
     else if (split)
-        HIPCHK(cgemm_bf16_nt(split_terms_, M, N, K, {(const float*)da, (const float*)(da + na), lda},
-                               {(const float*)db, (const float*)(db + nb), ldb}, {(float*)dc, (float*)(dc + nc), N}, s));
+        HIPCHK(cgemm_bf16_planes(split_terms_, M, N, K, pl, pl + ea, {(float*)dc, (float*)(dc + nc), N}, s));
     else if (ks > 1)
         HIPCHK(cgemm_f32_splitk(opa, opb, M, N, K, {(const float*)da, (const float*)(da + na), lda},
                                 {(const float*)db, (const float*)(db + nb), ldb}, ws, ws + nc * ks, req, s));
@@ -2287,6 +2313,7 @@ void selftest_cgemm_impl(int opa, int opb, int M, int N, int K, const double* a,
     }
     HIPCHK(hipMemcpyAsync(hc.data(), dc, sizeof(R) * 2 * nc, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (pl) dfree(pl, s, nullptr);
     dfree(da, s, nullptr); dfree(db, s, nullptr); dfree(dc, s, nullptr);
     HIPCHK(hipStreamSynchronize(s));
     for (int64_t i = 0; i < nc; ++i) { c[2 * i] = hc[i]; c[2 * i + 1] = hc[nc + i]; }

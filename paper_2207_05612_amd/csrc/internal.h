@@ -66,6 +66,23 @@ hipError_t splitk_reduce64(const double* ws_re, const double* ws_im, int nsplit,
 hipError_t cgemm_bf16_nt(int terms, int M, int N, int K, CView<float> A, CView<float> B, CViewMut<float> C,
                          hipStream_t stream);
 
+// The same product with each operand split once beforehand.  split_planes
+// writes the `terms` BF16 terms of an operand (rows x K, FP32 planar) as
+// planes of split_planes_elems() elements (rows padded to the product's tile,
+// 256 for the A operand, 128 for B; k padded to 16; the padding zero; stored
+// by groups of 8 k, rows consecutive within a group, as the tiles sit in LDS);
+// cgemm_bf16_planes(_splitk) multiplies two such operands and gives the same
+// bits as cgemm_bf16_nt(_splitk) on the FP32 operands.  Planes must be 16-byte
+// aligned.
+int64_t split_planes_elems(int terms, int rows, int K, bool is_a);
+hipError_t split_planes(int terms, int rows, int K, bool is_a, CView<float> X, unsigned short* planes,
+                        hipStream_t stream);
+hipError_t cgemm_bf16_planes(int terms, int M, int N, int K, const unsigned short* pa, const unsigned short* pb,
+                             CViewMut<float> C, hipStream_t stream);
+hipError_t cgemm_bf16_planes_splitk(int terms, int M, int N, int K, const unsigned short* pa,
+                                    const unsigned short* pb, float* ws_re, float* ws_im, int ksplit,
+                                    hipStream_t stream);
+
 // Structured MPO application on one site.
 //   in  [P][w_in][2 (t)][Q],  out [P][2 (s)][w_out][Q]
 //   w_in = H * r_in * lo, w_out = H * r_out * lo; one of r_in, r_out is 1.

@@ -73,6 +73,33 @@ def test_split_bf16_kernel_matches_numpy(prec):
             assert rel < 1e-4, (M, N, K, rel)
 
 
+@pytest.mark.parametrize("prec", [BF16X3, BF16X2])
+def test_split_planes_equal_staged_split(prec):
+    """The compression step splits each operand once into BF16 planes (mps_kernel_selftest_cgemm
+    runs that path); the allocation-free entry point splits every k tile while staging it.  Same
+    terms, k tiles and MFMA order: the products must agree bit for bit, on ragged shapes (rows
+    past the tile, k past a multiple of 16), several tiles and the split-K path."""
+    import torch
+    rng = np.random.default_rng(31)
+    shapes = GEMM_SHAPES + [(256, 130, 40), (33, 300, 257), (257, 129, 17), (513, 385, 1000), (600, 260, 12000)]
+    for M, N, K in shapes:
+        a = _rc(rng, M, K).astype(np.complex64).astype(np.complex128)
+        b = _rc(rng, N, K).astype(np.complex64).astype(np.complex128)
+        ref = mps.selftest_cgemm(prec, 0, 1, a, b)
+        ar = torch.tensor(np.ascontiguousarray(a.real), dtype=torch.float32, device="cuda")
+        ai = torch.tensor(np.ascontiguousarray(a.imag), dtype=torch.float32, device="cuda")
+        br = torch.tensor(np.ascontiguousarray(b.real), dtype=torch.float32, device="cuda")
+        bi = torch.tensor(np.ascontiguousarray(b.imag), dtype=torch.float32, device="cuda")
+        cr = torch.full((M, N), float("nan"), dtype=torch.float32, device="cuda")
+        ci = torch.full((M, N), float("nan"), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        mps.cgemm_noalloc(prec, 0, 1, M, N, K, (ar.data_ptr(), ai.data_ptr()), K, (br.data_ptr(), bi.data_ptr()), K,
+                          (cr.data_ptr(), ci.data_ptr()), N)
+        torch.cuda.synchronize()
+        got = cr.double().cpu().numpy() + 1j * ci.double().cpu().numpy()
+        assert np.array_equal(got, ref), (M, N, K, np.abs(got - ref).max())
+
+
 def run_gpu(circuit, chi, n_sweeps, prec, depth=None, bits=None):
     st = mps.MPS(circuit.n, bits, max_chi=max(chi, 1), precision=prec)
     layers = circuit.layers if depth is None else circuit.layers[:depth]

@@ -211,7 +211,10 @@ def test_full_size_properties_chi1024():
     n_before = 0
     for d in range(5):
         f = st.apply_layer_dmrg(c.layers[d], chi, 2)
-        assert 0.0 < f <= 1.0 + 1e-6
+        # f is the kept weight of the FP32-rounded local tensor (Sec. VI.A), whose norm differs from
+        # the normalised state's by the contraction's rounding (about sqrt(4096) 2^-24 per split-K
+        # chunk): f <= 1 holds up to the precision's f target
+        assert 0.0 < f <= 1.0 + pb.F_TARGET[FP32]
         f_log, s2_log, k_log = st.step_log()
         layer_log = f_log[n_before:]
         n_before = len(f_log)

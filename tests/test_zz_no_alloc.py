@@ -1,11 +1,13 @@
 """The allocation-free GEMM entry point (mps_cgemm_noalloc) against the allocating one.
 
-mps_cgemm_noalloc runs the kernels of mps_kernel_selftest_cgemm on device
-operands with its split-K partial sums in the library's static scratch array.
-Two calls in a row (the second smaller, so the scratch keeps the first call's
+mps_cgemm_noalloc runs the products of mps_kernel_selftest_cgemm on device
+operands with its split-K partial sums in the library's static scratch array
+(for the split precisions it splits each k tile while staging it, where the
+selftest splits the operands once beforehand: same terms, same bits).  Two
+calls in a row (the second smaller, so the scratch keeps the first call's
 partial sums) must each equal mps_kernel_selftest_cgemm on the same operands
-bit for bit (same kernels, same split), and so meet the same bound against
-NumPy as the kernel tests.  A product whose partial sums exceed the scratch
+bit for bit (same split of K), and so meet the same bound against NumPy as
+the kernel tests.  A product whose partial sums exceed the scratch
 array is refused before any work.
 """
 import numpy as np
