@@ -300,9 +300,12 @@ static hipError_t launch(int opa, int opb, int M, int N, int K, CView<TIn> A, CV
         return hipGetLastError();                                                                 \
     }
     if (sub) {
-        // the subtracting form exists for the FP64 back-transformation only (opa = C, opb = N)
-        if (sizeof(TAcc) != 8 || opa != OP_C || opb != OP_N) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((cgemm_kernel<TIn, TAcc, OP_C, OP_N, BM, BN, BK, true>), grid, block, 0, stream, g);
+        // the subtracting forms exist for the FP64 back-transformation only (C^H N and N N)
+        if (sizeof(TAcc) != 8 || opb != OP_N || (opa != OP_C && opa != OP_N)) return hipErrorInvalidValue;
+        if (opa == OP_C)
+            hipLaunchKernelGGL((cgemm_kernel<TIn, TAcc, OP_C, OP_N, BM, BN, BK, true>), grid, block, 0, stream, g);
+        else
+            hipLaunchKernelGGL((cgemm_kernel<TIn, TAcc, OP_N, OP_N, BM, BN, BK, true>), grid, block, 0, stream, g);
         return hipGetLastError();
     }
     MPS_GEMM_CASE(OP_N, OP_N)
@@ -372,6 +375,11 @@ hipError_t cgemm_f64(int opa, int opb, int M, int N, int K, CView<double> A, CVi
 hipError_t cgemm_f64_sub(int opa, int opb, int M, int N, int K, CView<double> A, CView<double> B, CViewMut<double> C,
                          hipStream_t stream) {
     return launch<double, double, 128, 64, 8>(opa, opb, M, N, K, A, B, C, stream, 0, 1, 0, 1);
+}
+
+hipError_t cgemm_f64_batched_sub(int M, int N, int K, CView<double> A, int64_t sa, CView<double> B, int64_t sb,
+                                 CViewMut<double> C, int64_t sc, int batch, hipStream_t stream) {
+    return launch<double, double, 128, 64, 8>(OP_N, OP_N, M, N, K, A, B, C, stream, 0, 1, 0, 1, batch, sa, sb, sc);
 }
 
 hipError_t cgemm_f64_batched(int opa, int opb, int M, int N, int K, CView<double> A, int64_t sa, CView<double> B,

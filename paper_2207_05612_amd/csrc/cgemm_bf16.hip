@@ -381,6 +381,50 @@ __global__ __launch_bounds__(256) void split_planes_kernel(const float* __restri
     }
 }
 
+// The same planes for the transposed operand X = src^T, src K x rows row-major
+// (leading dimension ld): plane entry (r, k) is src[k][r].  Lane r of a
+// wavefront reads 8 rows of src at column r (coalesced across lanes) and
+// writes the 16 bytes of (r, 8 k), consecutive lanes consecutive.
+template <int S>
+__global__ __launch_bounds__(256) void split_planes_t_kernel(const float* __restrict__ re, const float* __restrict__ im,
+                                                             int64_t ld, int rows, int rows_pad, int K, int Kp,
+                                                             unsigned short* __restrict__ planes) {
+    const int gpr = Kp >> 3;
+    const int nkb = (gpr + 3) >> 2;
+    const int64_t units = (int64_t)(rows_pad >> 6) * nkb;
+    const int64_t plane = (int64_t)rows_pad * Kp;
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int64_t row = (u / nkb) * 64 + (threadIdx.x & 63);
+        const int kg = (int)(u % nkb) * 4 + (threadIdx.x >> 6);
+        if (kg >= gpr) continue;
+        const int k0 = kg * 8;
+        const bool live = row < rows;
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const float* src = (p ? im : re) + (live ? row : 0);
+            float x[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x[e] = (live && k0 + e < K) ? src[(int64_t)(k0 + e) * ld] : 0.f;
+            u16x8 h, m, l;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                if (S == 3) {
+                    unsigned short a, b, c;
+                    split3(x[e], a, b, c);
+                    h[e] = a; m[e] = b; l[e] = c;
+                } else {
+                    h[e] = bf16_rne(x[e]);
+                    m[e] = bf16_rne(x[e] - bf16_to_float(h[e]));
+                }
+            }
+            unsigned short* dst = planes + (int64_t)p * plane + ((int64_t)kg * rows_pad + row) * 8;
+            *(u16x8*)dst = h;
+            *(u16x8*)(dst + 2 * plane) = m;
+            if (S == 3) *(u16x8*)(dst + 4 * plane) = l;
+        }
+    }
+}
+
 struct PlaneArgs {
     const unsigned short* a;   // planes of A (M rows)
     const unsigned short* b;   // planes of B (N rows)
@@ -567,6 +611,23 @@ hipError_t split_planes(int terms, int rows, int K, bool is_a, CView<float> X, u
         if (vec) hipLaunchKernelGGL((split_planes_kernel<2, true>), dim3(grid), dim3(256), 0, stream, X.re, X.im, X.ld, r, rpi, K, Kp, planes);
         else hipLaunchKernelGGL((split_planes_kernel<2, false>), dim3(grid), dim3(256), 0, stream, X.re, X.im, X.ld, r, rpi, K, Kp, planes);
     }
+    return hipGetLastError();
+}
+
+hipError_t split_planes_t(int terms, int rows, int K, bool is_a, CView<float> Xt, unsigned short* planes,
+                          hipStream_t stream) {
+    if (rows <= 0 || K <= 0) return hipSuccess;
+    if (terms != 2 && terms != 3) return hipErrorInvalidValue;
+    const int Kp = (K + SBK - 1) / SBK * SBK;
+    const int64_t rp = pad_rows(rows, is_a);
+    if (rp > 0x7fffffff) return hipErrorInvalidValue;
+    const int64_t units = (rp >> 6) * (((Kp >> 3) + 3) >> 2);
+    const unsigned grid = (unsigned)std::min<int64_t>(units, 65536);
+    const int r = rows, rpi = (int)rp;
+    if (terms == 3)
+        hipLaunchKernelGGL((split_planes_t_kernel<3>), dim3(grid), dim3(256), 0, stream, Xt.re, Xt.im, Xt.ld, r, rpi, K, Kp, planes);
+    else
+        hipLaunchKernelGGL((split_planes_t_kernel<2>), dim3(grid), dim3(256), 0, stream, Xt.re, Xt.im, Xt.ld, r, rpi, K, Kp, planes);
     return hipGetLastError();
 }
 

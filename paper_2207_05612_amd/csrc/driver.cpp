@@ -659,27 +659,13 @@ void gemm(mps_state* st, int cls, int opa, int opb, int64_t M, int64_t N, int64_
 int split_terms(const mps_state* st) { return st->prec == MPS_BF16X2 ? 2 : 3; }
 bool is_split(int prec) { return prec == MPS_BF16X2 || prec == MPS_BF16X3; }
 
-// Split-precision (BF16 x 2 or x 3) complex GEMM, C = A B^T with both operands k-contiguous.
-void gemm_split(mps_state* st, int cls, int64_t M, int64_t N, int64_t K, const float* ar, const float* ai,
-                int64_t lda, const float* br, const float* bi, int64_t ldb, float* cr, float* ci, int64_t ldc,
-                const Lane* lane = nullptr) {
-    if (M > 0x7fffffff || N > 0x7fffffff || K > 0x7fffffff) fail(MPS_ERR_ARG, "GEMM dimension too large");
-    const Lane ln = lane ? *lane : main_lane(st);
+// Split-precision (BF16 x 2 or x 3) complex GEMM, C = A B^T, on operands
+// already split into BF16 planes (split_planes / split_planes_t).
+void gemm_split_planes(mps_state* st, int cls, int64_t M, int64_t N, int64_t K, const unsigned short* pa,
+                       const unsigned short* pb, float* cr, float* ci, int64_t ldc, const Lane& ln) {
     const double fl = 8.0 * (double)M * (double)N * (double)K;
     const double by = 8.0 * ((double)M * K + (double)K * N + (double)M * N);
     const int terms = split_terms(st);
-    // both operands split once into BF16 planes (counted as OTHER, like the split-K sum)
-    const int64_t ea = split_planes_elems(terms, (int)M, (int)K, true);
-    const int64_t eb = split_planes_elems(terms, (int)N, (int)K, false);
-    ln.pl->ensure(ea + eb, ln.s);
-    unsigned short* pa = ln.pl->p;
-    unsigned short* pb = pa + ea;
-    {
-        Timer t(st, MPS_KCLASS_OTHER, 0, 4.0 * ((double)M + N) * K + 2.0 * (ea + eb), ln.s);
-        HIPCHK(split_planes(terms, (int)M, (int)K, true, {ar, ai, lda}, pa, ln.s));
-        HIPCHK(split_planes(terms, (int)N, (int)K, false, {br, bi, ldb}, pb, ln.s));
-        t.done();
-    }
     const int ks = splitk_chunks((int)K, splitk_for_split(M, N, K), 16);
     if (ks > 1) {
         ln.ws->ensure(M * N * ks, ln.s);
@@ -697,6 +683,38 @@ void gemm_split(mps_state* st, int cls, int64_t M, int64_t N, int64_t K, const f
         HIPCHK(cgemm_bf16_planes(terms, (int)M, (int)N, (int)K, pa, pb, {cr, ci, ldc}, ln.s));
         t.done();
     }
+}
+
+// The lane's plane buffer for an A operand of M rows and a B operand of N rows over K.
+void lane_planes(mps_state* st, const Lane& ln, int64_t M, int64_t N, int64_t K, unsigned short*& pa,
+                 unsigned short*& pb) {
+    const int terms = split_terms(st);
+    const int64_t ea = split_planes_elems(terms, (int)M, (int)K, true);
+    const int64_t eb = split_planes_elems(terms, (int)N, (int)K, false);
+    ln.pl->ensure(ea + eb, ln.s);
+    pa = ln.pl->p;
+    pb = pa + ea;
+}
+
+// Split-precision complex GEMM, C = A B^T with both operands FP32 and
+// k-contiguous: both are split once into BF16 planes (counted as OTHER, like
+// the split-K sum), then multiplied.
+void gemm_split(mps_state* st, int cls, int64_t M, int64_t N, int64_t K, const float* ar, const float* ai,
+                int64_t lda, const float* br, const float* bi, int64_t ldb, float* cr, float* ci, int64_t ldc,
+                const Lane* lane = nullptr) {
+    if (M > 0x7fffffff || N > 0x7fffffff || K > 0x7fffffff) fail(MPS_ERR_ARG, "GEMM dimension too large");
+    const Lane ln = lane ? *lane : main_lane(st);
+    const int terms = split_terms(st);
+    unsigned short *pa, *pb;
+    lane_planes(st, ln, M, N, K, pa, pb);
+    {
+        // 8 bytes read and 4 terms bytes written per complex element
+        Timer t(st, MPS_KCLASS_OTHER, 0, (8.0 + 4.0 * terms) * ((double)M + N) * K, ln.s);
+        HIPCHK(split_planes(terms, (int)M, (int)K, true, {ar, ai, lda}, pa, ln.s));
+        HIPCHK(split_planes(terms, (int)N, (int)K, false, {br, bi, ldb}, pb, ln.s));
+        t.done();
+    }
+    gemm_split_planes(st, cls, M, N, K, pa, pb, cr, ci, ldc, ln);
 }
 
 // Split count for a GEMM with `active` output tiles over k range K: fill whole
@@ -909,7 +927,7 @@ void eigh_gram(mps_state* st, EighWork& wk, const double* re, const double* im, 
     if (method == EIGH_PERSISTENT && dim >= 2 && dim <= hetrd_max_n()) {
         wk.Z.ensure(2 * (int64_t)dim * dim, s);      // full matrix first, real eigenvectors after
         // reflectors padded to whole blocks of the back-transformation with zero rows (tau = 0)
-        const int nb = wy_block(), nblk = (dim - 1 + nb - 1) / nb, npad = nblk * nb - (dim - 1);
+        const int nb = wy_block(dim), nblk = (dim - 1 + nb - 1) / nb, npad = nblk * nb - (dim - 1);
         wk.tau.ensure(2 * (int64_t)nblk * nb, s);
         wk.vh.ensure((int64_t)nblk * nb * dim, s);
         if (npad > 0) {
@@ -1012,7 +1030,7 @@ void top_eigvecs(mps_state* st, EighWork& wk, int dim, int k, double* out_re, do
     }
     HIPCHK(take_top_real_eigvecs(wk.Z.p, dim, k, out_re, out_im, s));
     Timer t(st, MPS_KCLASS_EIGH, 0, 0);
-    const int nb = wy_block(), nblk = (dim - 1 + nb - 1) / nb;
+    const int nb = wy_block(dim), nblk = (dim - 1 + nb - 1) / nb;
     const int64_t nbb = (int64_t)nb * nb, nbd = (int64_t)nb * dim;
     wk.S.ensure(nblk * nbb, s);
     wk.T.ensure(nblk * nbb, s);
@@ -1024,7 +1042,25 @@ void top_eigvecs(mps_state* st, EighWork& wk, int dim, int k, double* out_re, do
     HIPCHK(cgemm_f64_batched_splitk(OP_N, OP_C, nb, nb, dim, {wk.vh.re(), wk.vh.im(), dim}, nbd,
                                     {wk.vh.re(), wk.vh.im(), dim}, nbd, wk.ws.re(), wk.ws.im(), ks, nblk, s));
     HIPCHK(splitk_reduce64(wk.ws.re(), wk.ws.im(), chunks, (int64_t)nblk * nb, nb, wk.S.re(), wk.S.im(), nb, s));
-    HIPCHK(wy_t_factors(wk.S.re(), wk.S.im(), nblk, wk.tau.p, wk.T.re(), wk.T.im(), s));
+    // T factors: the 64 x 64 diagonal sub-blocks from the recurrence, then pairs of
+    // h-blocks merged into 2h-blocks, I - [V1 V2] [[T1, -T1 (V1^H V2) T2], [0, T2]] [V1 V2]^H
+    // being the product of the two compact WY forms (the blocks below the diagonal stay zero)
+    if (nb > 64) {
+        HIPCHK(hipMemsetAsync(wk.T.re(), 0, sizeof(double) * nblk * nbb, s));
+        HIPCHK(hipMemsetAsync(wk.T.im(), 0, sizeof(double) * nblk * nbb, s));
+    }
+    HIPCHK(wy_t_diag_factors(wk.S.re(), wk.S.im(), nblk, nb, wk.tau.p, wk.T.re(), wk.T.im(), s));
+    for (int h = 64; h < nb; h *= 2)
+        for (int o = 0; o < nb; o += 2 * h) {
+            const int64_t d1 = (int64_t)o * nb + o, d2 = (int64_t)(o + h) * nb + (o + h), up = (int64_t)o * nb + o + h;
+            // X = S12 T2 (h x h per block, in the split-K workspace), then T12 -= T1 X
+            HIPCHK(cgemm_f64_batched(OP_N, OP_N, h, h, h, {wk.S.re() + up, wk.S.im() + up, nb}, nbb,
+                                     {wk.T.re() + d2, wk.T.im() + d2, nb}, nbb, {wk.ws.re(), wk.ws.im(), h},
+                                     (int64_t)h * h, nblk, s));
+            HIPCHK(cgemm_f64_batched_sub(h, h, h, {wk.T.re() + d1, wk.T.im() + d1, nb}, nbb,
+                                         {wk.ws.re(), wk.ws.im(), h}, (int64_t)h * h,
+                                         {wk.T.re() + up, wk.T.im() + up, nb}, nbb, nblk, s));
+        }
     HIPCHK(cgemm_f64_batched(OP_N, OP_N, nb, dim, nb, {wk.T.re(), wk.T.im(), nb}, nbb, {wk.vh.re(), wk.vh.im(), dim},
                              nbd, {wk.Y.re(), wk.Y.im(), dim}, nbd, nblk, s));
     for (int b = nblk - 1; b >= 0; --b) {
@@ -1051,7 +1087,7 @@ struct Engine {
     std::vector<Planar<R>> env;       // per bond
     std::vector<Planar<R>> psi[2];    // per view-site, view layout
     std::vector<Planar<double>> phi;  // per site, layout of the pass that wrote it
-    Planar<R> X, T2, TH, UR, T2T;
+    Planar<R> X, T2, TH, UR;
     Planar<R> XR, T2R[2];             // right blocks, written on the second stream
     Planar<R> MT[2][2];               // per lane: intermediates of multi-layer MPO factors
     bool split = false;   // split-precision BF16 contractions (R = float only): operands kept k-contiguous
@@ -1075,7 +1111,7 @@ struct Engine {
         for (auto& e : env) e.release(s);
         for (int o = 0; o < 2; ++o)
             for (auto& e : psi[o]) e.release(s);
-        X.release(s); T2.release(s); TH.release(s); UR.release(s); T2T.release(s);
+        X.release(s); T2.release(s); TH.release(s); UR.release(s);
         TH64.release(s); GR.release(s); U64.release(s); V64.release(s); M64.release(s);
         LX.release(s); LY.release(s); LQ.release(s); LR.release(s); LP.release(s); LT.release(s); LU.release(s);
         ew.release(s); svec.release(s); QZ.release(s); QG.release(s); QT.release(s); QI.release(s);
@@ -1387,18 +1423,25 @@ struct Engine {
         env[bM].ensure(tr.k * wM * DM, s);
         UR.ensure(rows * tr.k, s);
         if (split) {
-            // env = U^H T2 as (U^H) (T2^T)^T: both operands k-contiguous
-            T2T.ensure(rows * wM * DM, s);
+            // env = U^H T2 = (U^H) (T2^T)^T: U^H is k-contiguous as it stands, and T2^T is
+            // split into planes straight from T2 (never formed in FP32)
+            HIPCHK(adjoint_to_f32(U64.re(), U64.im(), rows, tr.k, (float*)UR.re(), (float*)UR.im(), s));
+            const Lane ln = main_lane(st);
+            const int terms = split_terms(st);
+            const int64_t N = wM * DM;
+            if (N > 0x7fffffff) fail(MPS_ERR_ARG, "GEMM dimension too large");
+            unsigned short *pa, *pb;
+            lane_planes(st, ln, tr.k, N, rows, pa, pb);
             {
-                Timer t(st, MPS_KCLASS_OTHER, 0, 16.0 * rows * wM * DM);
-                HIPCHK(transpose_planar((const float*)T2.re(), (const float*)T2.im(), rows, wM * DM, (float*)T2T.re(),
-                                        (float*)T2T.im(), s));
+                Timer t(st, MPS_KCLASS_OTHER, 0, (8.0 + 4.0 * terms) * ((double)tr.k + N) * rows, s);
+                HIPCHK(split_planes(terms, tr.k, (int)rows, true, {(const float*)UR.re(), (const float*)UR.im(), rows},
+                                    pa, s));
+                HIPCHK(split_planes_t(terms, (int)N, (int)rows, false, {(const float*)T2.re(), (const float*)T2.im(), N},
+                                      pb, s));
                 t.done();
             }
-            HIPCHK(adjoint_to_f32(U64.re(), U64.im(), rows, tr.k, (float*)UR.re(), (float*)UR.im(), s));
-            gemm_split(st, MPS_KCLASS_CONTRACT, tr.k, wM * DM, rows, (const float*)UR.re(), (const float*)UR.im(),
-                       rows, (const float*)T2T.re(), (const float*)T2T.im(), rows, (float*)env[bM].re(),
-                       (float*)env[bM].im(), wM * DM);
+            gemm_split_planes(st, MPS_KCLASS_CONTRACT, tr.k, N, rows, pa, pb, (float*)env[bM].re(),
+                              (float*)env[bM].im(), N, ln);
             return;
         }
         HIPCHK((convert_planar<double, R>(U64.re(), U64.im(), rows * tr.k, UR.re(), UR.im(), s)));

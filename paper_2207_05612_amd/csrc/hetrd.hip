@@ -728,18 +728,24 @@ __global__ __launch_bounds__(256) void herm_full_kernel(const double* __restrict
 // lane l holding T[i][l]; one workgroup per block of reflectors.
 constexpr int WY_MAX = 64;
 constexpr int WY_THREADS = 1024;
+// Workgroup z forms the 64 x 64 diagonal sub-block q = z mod (nb / 64) of the
+// T factor of block b = z / (nb / 64) (S and T planar row-major nb x nb per
+// block, leading dimension nb; tau of the sub-block's reflectors at 64 z).
 __global__ __launch_bounds__(WY_THREADS) void wy_t_kernel(const double* __restrict__ s_re, const double* __restrict__ s_im,
                                                         const double2* __restrict__ tau, double* __restrict__ t_re,
-                                                        double* __restrict__ t_im) {
+                                                        double* __restrict__ t_im, int nb) {
     __shared__ double2 S[WY_MAX][WY_MAX + 1];
-    const int64_t b = blockIdx.x;
+    const int sub = nb / WY_MAX;
+    const int64_t b = blockIdx.x / sub, q = blockIdx.x % sub;
+    const int64_t off = b * nb * nb + q * WY_MAX * (nb + 1);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const double* sr = s_re + b * WY_MAX * WY_MAX;
-    const double* si = s_im + b * WY_MAX * WY_MAX;
+    const double* sr = s_re + off;
+    const double* si = s_im + off;
     for (int idx = threadIdx.x; idx < WY_MAX * WY_MAX; idx += WY_THREADS)
-        S[idx / WY_MAX][idx % WY_MAX] = make_double2(sr[idx], si[idx]);
+        S[idx / WY_MAX][idx % WY_MAX] = make_double2(sr[(idx / WY_MAX) * nb + idx % WY_MAX],
+                                                     si[(idx / WY_MAX) * nb + idx % WY_MAX]);
     __syncthreads();
-    const double2* tb = tau + b * WY_MAX;
+    const double2* tb = tau + (int64_t)blockIdx.x * WY_MAX;
     for (int i = wave; i < WY_MAX; i += WY_THREADS / 64) {
         double2 t = make_double2(0.0, 0.0);        // T[i][lane]
         if (lane == i) t = tb[i];
@@ -752,8 +758,8 @@ __global__ __launch_bounds__(WY_THREADS) void wy_t_kernel(const double* __restri
                 t = make_double2(-tt.x, -tt.y);
             }
         }
-        t_re[b * WY_MAX * WY_MAX + (int64_t)i * WY_MAX + lane] = t.x;
-        t_im[b * WY_MAX * WY_MAX + (int64_t)i * WY_MAX + lane] = t.y;
+        t_re[off + (int64_t)i * nb + lane] = t.x;
+        t_im[off + (int64_t)i * nb + lane] = t.y;
     }
 }
 
@@ -772,13 +778,13 @@ __global__ __launch_bounds__(256) void top_real_kernel(const double* __restrict_
 
 }  // namespace
 
-int wy_block() { return WY_MAX; }
+int wy_block(int n) { return n > 512 ? 4 * WY_MAX : WY_MAX; }
 
-hipError_t wy_t_factors(const double* s_re, const double* s_im, int nblk, const double* tau_z, double* t_re,
-                        double* t_im, hipStream_t stream) {
-    if (nblk < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(WY_THREADS), 0, stream, s_re, s_im, (const double2*)tau_z, t_re,
-                       t_im);
+hipError_t wy_t_diag_factors(const double* s_re, const double* s_im, int nblk, int nb, const double* tau_z,
+                             double* t_re, double* t_im, hipStream_t stream) {
+    if (nblk < 1 || nb < WY_MAX || nb % WY_MAX != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(wy_t_kernel, dim3(nblk * (nb / WY_MAX)), dim3(WY_THREADS), 0, stream, s_re, s_im,
+                       (const double2*)tau_z, t_re, t_im, nb);
     return hipGetLastError();
 }
 

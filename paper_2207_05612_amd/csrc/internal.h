@@ -77,6 +77,10 @@ hipError_t cgemm_bf16_nt(int terms, int M, int N, int K, CView<float> A, CView<f
 int64_t split_planes_elems(int terms, int rows, int K, bool is_a);
 hipError_t split_planes(int terms, int rows, int K, bool is_a, CView<float> X, unsigned short* planes,
                         hipStream_t stream);
+// The planes of X = Xt^T for Xt (K x rows, FP32 planar, row-major): the split of
+// a transposed operand without forming it.
+hipError_t split_planes_t(int terms, int rows, int K, bool is_a, CView<float> Xt, unsigned short* planes,
+                          hipStream_t stream);
 hipError_t cgemm_bf16_planes(int terms, int M, int N, int K, const unsigned short* pa, const unsigned short* pb,
                              CViewMut<float> C, hipStream_t stream);
 hipError_t cgemm_bf16_planes_splitk(int terms, int M, int N, int K, const unsigned short* pa,
@@ -113,9 +117,6 @@ hipError_t site_to_view(const double* re, const double* im, int Dl, int Dr, int 
 hipError_t site_to_kmajor(const double* re, const double* im, int Dlv, int Drv, int swap_legs, float* ore,
                           float* oim, hipStream_t stream);
 
-// out (C x R) = in^T of a row-major R x C planar FP32 matrix (LDS-tiled).
-hipError_t transpose_planar(const float* ire, const float* iim, int64_t R, int64_t C, float* ore, float* oim,
-                            hipStream_t stream);
 
 // out (k x m, FP32) = in^H of a row-major m x k FP64 planar matrix.
 hipError_t adjoint_to_f32(const double* re, const double* im, int64_t m, int64_t k, float* ore, float* oim,
@@ -214,10 +215,6 @@ struct TrRequest {
 int hetrd_batch_max();
 int hetrd_workgroups(int n);
 hipError_t hetrd_persistent_multi(const TrRequest* reqs, int count, hipStream_t stream);
-// T factors (wy_block() x wy_block(), planar row-major, block b at
-// b wy_block()^2) of the compact WY forms of nblk blocks of wy_block()
-// reflectors, from S_b = V_b^H V_b (same layout) and tau (interleaved,
-// nblk wy_block() entries; tau = 0 marks an identity reflector).
 // Divide-and-conquer eigen-decomposition of the real symmetric tridiagonal
 // matrix (d, e) of order n <= stedc_dc_max_n(), all on the device: d is
 // replaced by the eigenvalues in ascending order and z (column-major, leading
@@ -228,9 +225,16 @@ size_t stedc_dc_workspace_bytes(int n);
 hipError_t stedc_dc(int n, double* d, const double* e, double* z, int ldz, void* ws, size_t ws_bytes,
                     hipStream_t stream);
 
-int wy_block();
-hipError_t wy_t_factors(const double* s_re, const double* s_im, int nblk, const double* tau_z, double* t_re,
-                        double* t_im, hipStream_t stream);
+// Reflectors per block of the blocked back-transformation of an order-n
+// reduction (64, or 256 above order 512).
+int wy_block(int n);
+// The 64 x 64 diagonal sub-blocks of the T factors of the compact WY forms
+// I - V_b T_b V_b^H of nblk blocks of nb reflectors (nb a multiple of 64):
+// S_b = V_b^H V_b and T_b planar row-major nb x nb, block b at b nb^2; tau
+// interleaved complex, nblk nb entries (tau = 0 marks an identity
+// reflector).  Sub-blocks off the diagonal are not written.
+hipError_t wy_t_diag_factors(const double* s_re, const double* s_im, int nblk, int nb, const double* tau_z,
+                             double* t_re, double* t_im, hipStream_t stream);
 // Top-k eigenvectors of a real column-major eigenvector matrix (ascending
 // eigenvalues) as planar complex row-major n x k, largest first.
 hipError_t take_top_real_eigvecs(const double* evec, int n, int k, double* out_re, double* out_im, hipStream_t stream);
@@ -245,6 +249,9 @@ hipError_t cgemm_f64_batched_splitk(int opa, int opb, int M, int N, int K, CView
 // C -= op(A) op(B) (FP64 complex, same operand conventions as cgemm_f64).
 hipError_t cgemm_f64_sub(int opa, int opb, int M, int N, int K, CView<double> A, CView<double> B, CViewMut<double> C,
                          hipStream_t stream);
+// C_z -= A_z B_z over a batch (FP64, opa = opb = N): the off-diagonal blocks of merged WY T factors.
+hipError_t cgemm_f64_batched_sub(int M, int N, int K, CView<double> A, int64_t sa, CView<double> B, int64_t sb,
+                                 CViewMut<double> C, int64_t sc, int batch, hipStream_t stream);
 
 // ---- exact statevector (FP64 planar, chain site q = index bit n-1-q) ----
 struct SvGate2 { double re[16], im[16]; };   // [row * 4 + col], row = 2 s_a + s_b

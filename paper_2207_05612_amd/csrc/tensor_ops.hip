@@ -490,44 +490,6 @@ hipError_t site_to_kmajor(const double* re, const double* im, int Dlv, int Drv, 
     return hipGetLastError();
 }
 
-// ------------------------------------------------ tiled planar transpose --
-// out (C x R) = in^T for a row-major R x C planar matrix; 64 x 64 tiles via LDS.
-__global__ __launch_bounds__(256) void transpose_planar_kernel(const float* __restrict__ ire,
-                                                               const float* __restrict__ iim, int64_t R,
-                                                               int64_t C, float* __restrict__ ore,
-                                                               float* __restrict__ oim) {
-    __shared__ float tr[64][65];
-    __shared__ float ti[64][65];
-    const int64_t tiles_c = (C + 63) / 64;
-    const int64_t r0 = (blockIdx.x / tiles_c) * 64, c0 = (blockIdx.x % tiles_c) * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 64 x 4
-    for (int k = ty; k < 64; k += 4) {
-        const int64_t r = r0 + k, c = c0 + tx;
-        if (r < R && c < C) {
-            tr[k][tx] = ire[r * C + c];
-            ti[k][tx] = iim[r * C + c];
-        }
-    }
-    __syncthreads();
-    for (int k = ty; k < 64; k += 4) {
-        const int64_t c = c0 + k, r = r0 + tx;
-        if (r < R && c < C) {
-            ore[c * R + r] = tr[tx][k];
-            oim[c * R + r] = ti[tx][k];
-        }
-    }
-}
-
-hipError_t transpose_planar(const float* ire, const float* iim, int64_t R, int64_t C, float* ore, float* oim,
-                            hipStream_t stream) {
-    if (R <= 0 || C <= 0) return hipSuccess;
-    const int64_t tiles = ((R + 63) / 64) * ((C + 63) / 64);
-    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(transpose_planar_kernel, dim3((unsigned)tiles), dim3(256), 0, stream, ire, iim, R, C, ore,
-                       oim);
-    return hipGetLastError();
-}
-
 // out (k x m, FP32) = in^H for a row-major m x k FP64 planar matrix
 __global__ __launch_bounds__(256) void adjoint_to_f32_kernel(const double* __restrict__ re,
                                                              const double* __restrict__ im, int64_t m,
