@@ -348,9 +348,10 @@ mps_status mps_kernel_stats(const mps_state* state, int kernel_class, int64_t* l
  *   opb 0 (N): b is K x N;   opb 1 (T): b is N x K, op(B) = b^T;
  *   opb 2 (C): b is N x K, op(B) = b^H.
  *   c receives M x N.
- * precision MPS_BF16X3 runs the split-precision kernel, which takes only
- * opa = 0, opb = 1.  For kernel-level parity tests; not used by the
- * compression step. */
+ * precision MPS_BF16X3 / MPS_BF16X2 runs the split-precision product, which
+ * takes opa = 0 with opb = 1 (b split as it stands) or opb = 0 (b^T split
+ * straight from b, as the environment update does).  For kernel-level parity
+ * tests; not used by the compression step. */
 mps_status mps_kernel_selftest_cgemm(int precision, int opa, int opb, int M, int N, int K,
                                      const double* a, const double* b, double* c);
 

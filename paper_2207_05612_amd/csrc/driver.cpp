@@ -514,7 +514,9 @@ struct mps_state {
     Raw<unsigned short> planes2;
     hipEvent_t ev_order[4] = {nullptr, nullptr, nullptr, nullptr};
     int eigh_method = 1;           // EIGH_PERSISTENT, or EIGH_ROCSOLVER
-    bool overlap_right = true;     // right blocks on the second stream
+    // right blocks on the second stream (MPS_OVERLAP=1); off by default: on the benchmark the
+    // overlap saved no time, and concurrent products stretch each other's launches
+    bool overlap_right = false;
     Raw<double> dscal;             // small device scalars
     Raw<double> partial;           // reduction partials
     bool prof = false;
@@ -1487,8 +1489,8 @@ struct Engine {
     // contracted over the MPO bond and the psi bond between the pair
     // (rows (cL, s1), columns (cR, s2)).  The right block depends only on psi
     // and on right environments that this pass has not yet overwritten, so
-    // the block of the next pair is built on the second stream while the
-    // current pair is truncated.
+    // the block of the next pair can be built on the second stream while the
+    // current pair is truncated (overlap_right).
     double sweep(int o) {
         if (n < 2) return 0;
         ensure_stream2();
@@ -2339,7 +2341,11 @@ void selftest_cgemm_impl(int opa, int opb, int M, int N, int K, const double* a,
         const int64_t eb = split_planes_elems(split_terms_, N, K, false);
         pl = (unsigned short*)dalloc(sizeof(unsigned short) * (size_t)std::max<int64_t>(ea + eb, 1), s);
         HIPCHK(split_planes(split_terms_, M, K, true, {(const float*)da, (const float*)(da + na), lda}, pl, s));
-        HIPCHK(split_planes(split_terms_, N, K, false, {(const float*)db, (const float*)(db + nb), ldb}, pl + ea, s));
+        if (opb == OP_T)
+            HIPCHK(split_planes(split_terms_, N, K, false, {(const float*)db, (const float*)(db + nb), ldb}, pl + ea, s));
+        else   // b is K x N: the planes of b^T straight from b, as in the environment update
+            HIPCHK(split_planes_t(split_terms_, N, K, false, {(const float*)db, (const float*)(db + nb), ldb}, pl + ea,
+                                  s));
     }
     if (split && ks > 1)
         HIPCHK(cgemm_bf16_planes_splitk(split_terms_, M, N, K, pl, pl + ea, ws, ws + nc * ks, req, s));
@@ -2455,7 +2461,8 @@ extern "C" mps_status mps_kernel_selftest_cgemm(int precision, int opa, int opb,
         if ((int64_t)M * K > (1 << 28) || (int64_t)K * N > (1 << 28) || (int64_t)M * N > (1 << 28))
             fail(MPS_ERR_ARG, "self-test operands too large");
         if (is_split(precision)) {
-            if (opa != OP_N || opb != OP_T) fail(MPS_ERR_ARG, "the split-precision kernel takes opa = 0, opb = 1");
+            if (opa != OP_N || (opb != OP_T && opb != OP_N))
+                fail(MPS_ERR_ARG, "the split-precision kernel takes opa = 0, opb = 1 (or 0: B split transposed)");
             selftest_cgemm_impl<float>(opa, opb, M, N, K, a, b, c, precision == MPS_BF16X2 ? 2 : 3);
         } else if (precision == MPS_FP32) selftest_cgemm_impl<float>(opa, opb, M, N, K, a, b, c);
         else if (precision == MPS_FP64) selftest_cgemm_impl<double>(opa, opb, M, N, K, a, b, c);

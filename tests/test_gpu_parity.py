@@ -100,6 +100,19 @@ def test_split_planes_equal_staged_split(prec):
         assert np.array_equal(got, ref), (M, N, K, np.abs(got - ref).max())
 
 
+@pytest.mark.parametrize("prec", [BF16X3, BF16X2])
+def test_split_planes_of_transposed_operand(prec):
+    """opb = 0 splits b^T into planes straight from b (K x N), the environment update's path: the
+    same planes as splitting the explicit transpose, so the same bits as opb = 1 on b^T."""
+    rng = np.random.default_rng(47)
+    for M, N, K in [(5, 7, 3), (130, 257, 70), (300, 64, 513), (70, 90, 9001), (257, 129, 17)]:
+        a = _rc(rng, M, K).astype(np.complex64).astype(np.complex128)
+        b = _rc(rng, K, N).astype(np.complex64).astype(np.complex128)
+        got = mps.selftest_cgemm(prec, 0, 0, a, b)
+        ref = mps.selftest_cgemm(prec, 0, 1, a, np.ascontiguousarray(b.T))
+        assert np.array_equal(got, ref), (M, N, K, np.abs(got - ref).max())
+
+
 def run_gpu(circuit, chi, n_sweeps, prec, depth=None, bits=None):
     st = mps.MPS(circuit.n, bits, max_chi=max(chi, 1), precision=prec)
     layers = circuit.layers if depth is None else circuit.layers[:depth]
@@ -304,6 +317,21 @@ def test_torch_caching_allocator_parity(prec):
     ref.close()
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated() == base
+
+
+@pytest.mark.parametrize("prec", [FP64, BF16X3])
+def test_right_block_on_second_stream_same_result(prec, monkeypatch):
+    """MPS_OVERLAP=1 builds the next pair's right block on the state's second stream while the
+    current pair is truncated: the same kernels on the same data, so the same bits as the default
+    schedule (one stream), on a truncated 20-qubit case with saturated bonds."""
+    c = circuits.random_circuit(circuits.grid_from_shape(5, 4), 8, seed=5)
+    ref, fr = run_gpu(c, 16, 2, prec)
+    monkeypatch.setenv("MPS_OVERLAP", "1")
+    st, fs = run_gpu(c, 16, 2, prec)
+    assert np.array_equal(fs, fr)
+    assert np.array_equal(st.statevector(), ref.statevector())
+    st.close()
+    ref.close()
 
 
 def test_eigensolver_counts():
