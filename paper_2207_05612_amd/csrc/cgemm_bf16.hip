@@ -15,14 +15,22 @@
 // Tiling: 512 threads = 8 wavefronts (4 x 2), wave tile 64 x 64 complex
 // (2 x 2 MFMA tiles of 32 x 32), block tile 256 x 128, BK = 16 (one MFMA k
 // step), two wavefronts per SIMD so that one wave's MFMAs cover the other's
-// waits.  The split happens when a k-tile is staged from registers into LDS;
-// LDS holds [split][re|im][k/8][row][8] so that the 8 consecutive k of one
-// MFMA lane are one 16-byte read and the 32 lanes of a row group read
+// waits.  LDS holds [split][re|im][k/8][row][8] so that the 8 consecutive k
+// of one MFMA lane are one 16-byte read and the 32 lanes of a row group read
 // consecutive 16-byte words.  Two LDS buffers (144 KiB for S = 3) overlap the
-// next tile's float4 global loads with the current tile's 96 (S = 3) or 48
-// (S = 2) MFMAs per wave;
-// fragments are read per split pair to keep each wave under 256 registers.
-// Block ids map to tiles XCD-first, then in groups of 8 tile rows.
+// next tile's loads with the current tile's 96 (S = 3) or 48 (S = 2) MFMAs
+// per wave.  Block ids map to tiles XCD-first, then in groups of 8 tile rows.
+//
+// Two ways to fill LDS, with the same terms, tiles and MFMA order (and so the
+// same bits):
+//   * staging (cgemm_bf16x{3,2}_nt_kernel): each k tile is loaded as float4
+//     and split in registers on the way into LDS; fragments are read per split
+//     pair to keep each wave under 256 registers.  The allocation-free entry
+//     point uses it (it needs no memory beyond the operands).
+//   * planes (split_planes*_kernel, then cgemm_bf16x{3,2}_planes_kernel): each
+//     operand is split once into BF16 planes laid out like the LDS tiles, and
+//     the product kernel moves them into LDS with direct global-to-LDS loads.
+//     The compression step uses it.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

@@ -507,8 +507,8 @@ struct mps_state {
     Planar<float> splitws;         // partial sums of split-K FP32 / split-precision GEMMs
     Raw<unsigned short> planes;    // BF16 terms of the operands of split-precision GEMMs
     Planar<double> splitws64;      // partial sums of split-K FP64 Gram matrices
-    // second stream: the right block of the next two-site step runs on it
-    // while the current step's truncation runs on the state's stream
+    // second stream: with overlap_right, the right block of the next two-site
+    // step runs on it while the current step's truncation runs on the state's stream
     hipStream_t stream2 = nullptr;
     Planar<float> splitws2;
     Raw<unsigned short> planes2;
@@ -1090,7 +1090,7 @@ struct Engine {
     std::vector<Planar<R>> psi[2];    // per view-site, view layout
     std::vector<Planar<double>> phi;  // per site, layout of the pass that wrote it
     Planar<R> X, T2, TH, UR;
-    Planar<R> XR, T2R[2];             // right blocks, written on the second stream
+    Planar<R> XR, T2R[2];             // right blocks (written on the second stream with overlap_right)
     Planar<R> MT[2][2];               // per lane: intermediates of multi-layer MPO factors
     bool split = false;   // split-precision BF16 contractions (R = float only): operands kept k-contiguous
     Planar<double> TH64, GR, U64, V64, M64;
@@ -1525,9 +1525,9 @@ struct Engine {
                     gemm<R>(st, MPS_KCLASS_CONTRACT, OP_N, OP_T, rows, cols, K, T2.re(), T2.im(), K, rb.re(), rb.im(),
                             K, TH.re(), TH.im(), cols);
             }
-            // The right block of the next pair is queued on the second stream once
-            // this pair's tridiagonal reduction (a whole-device cooperative launch)
-            // has finished, so it overlaps the rest of the truncation.
+            // The right block of the next pair is queued once this pair's tridiagonal
+            // reduction (a whole-device cooperative launch) has finished: on the second
+            // stream (overlap_right) it overlaps the rest of the truncation.
             bool queued = last;
             const std::function<void()> queue_right = [&, j]() {
                 if (queued) return;
