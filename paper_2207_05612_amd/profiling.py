@@ -17,6 +17,12 @@ Usage (on the GPU machine, after the profiled runs):
       algorithmic bytes per launch that the benchmark line of the same run
       reports under <roofline-key>.
 
+  python -m paper_2207_05612_amd.profiling mfma <kernel-regex> <dir> [<out.txt>]
+      Executed BF16 matrix-core work of the kernels matching <kernel-regex> in
+      the timed region, from one rocprofv3 --pmc SQ_INSTS_VALU_MFMA_MOPS_BF16
+      run (512 flops per MOP): flops, summed launch time and their ratio,
+      against the dense BF16 peak.
+
 The files are found by name below the given directories (rocprofv3 places
 them in per-host / per-process subdirectories).
 """
@@ -200,6 +206,36 @@ def traffic(kernel_regex: str, fetch_dir: str, write_dir: str, bench_json: str, 
             "bytes_per_algorithmic_byte": measured / alg}
 
 
+BF16_DENSE_PEAK = 2.5e15     # flop/s, MI355X dense BF16 matrix cores
+
+
+def mfma(kernel_regex: str, directory: str) -> str:
+    """Executed BF16 MFMA flops of the matching launches in the timed region over their summed time."""
+    pat = re.compile(kernel_regex)
+    disp = OrderedDict()
+    for path in _find(directory, "counter_collection.csv"):
+        with open(path, newline="") as fh:
+            for r in csv.DictReader(fh):
+                k = (_col(r.keys(), "dispatch_id", "dispatch"), _col(r.keys(), "kernel_name"),
+                     _col(r.keys(), "counter_name"), _col(r.keys(), "counter_value", "value"),
+                     _col(r.keys(), "start_timestamp"), _col(r.keys(), "end_timestamp"))
+                d = disp.setdefault(int(r[k[0]]), {"name": r[k[1]], "t": (int(r[k[4]]), int(r[k[5]])), "mops": 0.0})
+                if r[k[2]] == "SQ_INSTS_VALU_MFMA_MOPS_BF16":
+                    d["mops"] += float(r[k[3]])    # rows of one dispatch (hardware instances) are summed
+    rows = [(i, d["name"], d) for i, d in sorted(disp.items())]
+    timed = timed_region(rows, lambda r: r[1])
+    sel = [d for _, name, d in timed if pat.search(name)]
+    if not sel:
+        raise ValueError("no dispatch matching %r in the timed region" % kernel_regex)
+    secs = sum((d["t"][1] - d["t"][0]) * 1e-9 for d in sel)
+    flops = sum(d["mops"] * 512.0 for d in sel)
+    rate = flops / secs
+    return ("# executed BF16 MFMA work of %r in the timed region\n"
+            "launches %d\nkernel time %.4f s\nBF16 MFMA flops executed %.4e\n"
+            "rate %.1f TFLOP/s = %.3f of the %.1f PFLOP/s dense peak\n"
+            % (kernel_regex, len(sel), secs, flops, rate / 1e12, rate / BF16_DENSE_PEAK, BF16_DENSE_PEAK / 1e15))
+
+
 def main(argv):
     if len(argv) >= 2 and argv[0] == "trace":
         text = trace_summary(argv[1])
@@ -213,6 +249,13 @@ def main(argv):
         with open(argv[6], "w") as fh:
             json.dump(rec, fh, indent=1)
         print(json.dumps(rec, indent=1))
+        return 0
+    if len(argv) >= 3 and argv[0] == "mfma":
+        text = mfma(argv[1], argv[2])
+        if len(argv) > 3:
+            with open(argv[3], "w") as fh:
+                fh.write(text)
+        print(text)
         return 0
     print(__doc__)
     return 2
