@@ -440,8 +440,8 @@ def statevector_leg(mps, circuits, torch, n_qubits):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU: the compression step has no multi-GPU path in this build "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        print("bench.py runs on one GPU: the compression step has no multi-GPU path "
+              "(--gpus %d requested; the sharding design is written up, not built)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
