@@ -3,7 +3,7 @@
 Plain NumPy complex128 implementation of one compression step of the paper
 (Sec. IV.B, the compression step), in its two-site variant (mentioned in the
 same section), with K >= 1 layers per step and one qubit per MPS tensor
-(Sec. IV.A with r_tau = 1).
+(Sec. IV.A with r_tau = 1) or r_tau consecutive qubits per tensor.
 
 Steps, in the paper's order:
   * the layer's gates become an MPO: one-qubit gates are absorbed into the
@@ -30,6 +30,10 @@ Readings where the paper is silent (each one is listed in the design notes):
     are dropped;
   * composite MPO bonds order the open gates by their left chain site, the
     leftmost gate being the most significant digit.
+
+Groupings (Sec. IV.A with r_tau > 1): r_tau consecutive qubits per tensor, physical
+dimension 2^r_tau (group_state, group_mpo); the zip-up, the sweeps and the truncation run
+unchanged on the grouped sites (apply_layers with sizes).
 
 K > 1 layers per step (Sec. IV.B, the contraction of Sec. IV.B.2 with K layers
 between the two MPS): the MPO of the step is the site-by-site product of the K
@@ -199,7 +203,7 @@ class StepRecord:
 
 @dataclasses.dataclass
 class OracleMPS:
-    tensors: List[np.ndarray]      # A_k[a, s, b], shape (D_k, 2, D_{k+1})
+    tensors: List[np.ndarray]      # A_k[a, s, b], shape (D_k, d_k, D_{k+1}); d_k = 2 per qubit of the site
     center: int                    # 0 or n-1: site holding the norm
     log_f: float = 0.0
     n_layers: int = 0
@@ -319,9 +323,9 @@ def zipup_left_to_right(a, w, chi, envs, log):
     envs[0] = c
     for k in range(n - 1):
         t = _ein("pba,atx,bstc->pscx", c, a[k], w[k])
-        cl, _, wk, dk = t.shape
-        u, s, vh, total, cond = truncated_svd_gap(t.reshape(cl * 2, wk * dk), chi_at(chi, k + 1))
-        b[k] = u.reshape(cl, 2, len(s))
+        cl, ds, wk, dk = t.shape
+        u, s, vh, total, cond = truncated_svd_gap(t.reshape(cl * ds, wk * dk), chi_at(chi, k + 1))
+        b[k] = u.reshape(cl, ds, len(s))
         c = (s[:, None] * vh).reshape(len(s), wk, dk)
         envs[k + 1] = c
         conds.append(cond)
@@ -329,7 +333,7 @@ def zipup_left_to_right(a, w, chi, envs, log):
     f0 = float(np.sum(np.abs(t) ** 2))
     if not f0 > 0.0:
         raise FloatingPointError("zip-up produced a zero state")
-    b[n - 1] = t.reshape(t.shape[0], 2, 1) / math.sqrt(f0)
+    b[n - 1] = t.reshape(t.shape[0], t.shape[1], 1) / math.sqrt(f0)
     log.append(StepRecord("zip", -1, f0, f0, b[n - 1].shape[0], min((c[0] for c in conds), default=math.inf),
                          max((c[1] for c in conds), default=0.0)))
     return b, f0
@@ -343,9 +347,9 @@ def zipup_right_to_left(a, w, chi, envs, log):
     envs[n] = c
     for k in range(n - 1, 0, -1):
         t = _ein("qez,ytz,bste->ybsq", c, a[k], w[k])
-        dk, wk, _, cr = t.shape
-        u, s, vh, total, cond = truncated_svd_gap(t.reshape(dk * wk, 2 * cr), chi_at(chi, k))
-        b[k] = vh.reshape(len(s), 2, cr)
+        dk, wk, ds, cr = t.shape
+        u, s, vh, total, cond = truncated_svd_gap(t.reshape(dk * wk, ds * cr), chi_at(chi, k))
+        b[k] = vh.reshape(len(s), ds, cr)
         c = (u * s[None, :]).reshape(dk, wk, len(s)).transpose(2, 1, 0)
         envs[k] = c
         conds.append(cond)
@@ -353,7 +357,7 @@ def zipup_right_to_left(a, w, chi, envs, log):
     f0 = float(np.sum(np.abs(t) ** 2))
     if not f0 > 0.0:
         raise FloatingPointError("zip-up produced a zero state")
-    b[0] = t.reshape(1, 2, t.shape[3]) / math.sqrt(f0)
+    b[0] = t.reshape(1, t.shape[2], t.shape[3]) / math.sqrt(f0)
     log.append(StepRecord("zip", -1, f0, f0, b[0].shape[2], min((c[0] for c in conds), default=math.inf),
                          max((c[1] for c in conds), default=0.0)))
     return b, f0
@@ -366,11 +370,11 @@ def sweep_left_to_right(a, w, b, chi, envs, log):
     f = None
     for k in range(n - 1):
         th = two_site_tensor(envs[k], a[k], w[k], a[k + 1], w[k + 1], envs[k + 2])
-        cl, _, _, cr = th.shape
-        u, s, vh, total, cond = truncated_svd_gap(th.reshape(cl * 2, 2 * cr), chi_at(chi, k + 1))
+        cl, d1, d2, cr = th.shape
+        u, s, vh, total, cond = truncated_svd_gap(th.reshape(cl * d1, d2 * cr), chi_at(chi, k + 1))
         f = float(np.sum(s ** 2))
-        b[k] = u.reshape(cl, 2, len(s))
-        b[k + 1] = (s[:, None] * vh / math.sqrt(f)).reshape(len(s), 2, cr)
+        b[k] = u.reshape(cl, d1, len(s))
+        b[k + 1] = (s[:, None] * vh / math.sqrt(f)).reshape(len(s), d2, cr)
         envs[k + 1] = env_left_step(envs[k], a[k], w[k], b[k])
         log.append(StepRecord("l2r", k + 1, f, total, len(s), *cond))
     return f
@@ -382,11 +386,11 @@ def sweep_right_to_left(a, w, b, chi, envs, log):
     f = None
     for k in range(n - 2, -1, -1):
         th = two_site_tensor(envs[k], a[k], w[k], a[k + 1], w[k + 1], envs[k + 2])
-        cl, _, _, cr = th.shape
-        u, s, vh, total, cond = truncated_svd_gap(th.reshape(cl * 2, 2 * cr), chi_at(chi, k + 1))
+        cl, d1, d2, cr = th.shape
+        u, s, vh, total, cond = truncated_svd_gap(th.reshape(cl * d1, d2 * cr), chi_at(chi, k + 1))
         f = float(np.sum(s ** 2))
-        b[k + 1] = vh.reshape(len(s), 2, cr)
-        b[k] = (u * (s / math.sqrt(f))[None, :]).reshape(cl, 2, len(s))
+        b[k + 1] = vh.reshape(len(s), d2, cr)
+        b[k] = (u * (s / math.sqrt(f))[None, :]).reshape(cl, d1, len(s))
         envs[k + 1] = env_right_step(envs[k + 2], a[k + 1], w[k + 1], b[k + 1])
         log.append(StepRecord("r2l", k + 1, f, total, len(s), *cond))
     return f
@@ -410,13 +414,13 @@ def sweep_single_left_to_right(a, w, b, envs, log):
         f = float(np.sum(np.abs(m) ** 2))
         if not f > 0.0:
             raise FloatingPointError("local tensor has zero norm")
-        cl, _, cr = m.shape
+        cl, ds, cr = m.shape
         if k == n - 1:
             b[k] = m / math.sqrt(f)
             log.append(StepRecord("l2r1", k + 1, f, f, cr))
             break
-        q, _ = np.linalg.qr(m.reshape(cl * 2, cr))          # M = Q R, Q left-isometric
-        b[k] = q.reshape(cl, 2, q.shape[1])
+        q, _ = np.linalg.qr(m.reshape(cl * ds, cr))         # M = Q R, Q left-isometric
+        b[k] = q.reshape(cl, ds, q.shape[1])
         envs[k + 1] = env_left_step(envs[k], a[k], w[k], b[k])
         log.append(StepRecord("l2r1", k + 1, f, f, q.shape[1]))
     return f
@@ -431,17 +435,57 @@ def sweep_single_right_to_left(a, w, b, envs, log):
         f = float(np.sum(np.abs(m) ** 2))
         if not f > 0.0:
             raise FloatingPointError("local tensor has zero norm")
-        cl, _, cr = m.shape
+        cl, ds, cr = m.shape
         if k == 0:
             b[k] = m / math.sqrt(f)
             log.append(StepRecord("r2l1", k, f, f, cl))
             break
         # M = L Q with Q right-isometric: QR of M^H
-        q, _ = np.linalg.qr(m.reshape(cl, 2 * cr).conj().T)
-        b[k] = q.conj().T.reshape(q.shape[1], 2, cr)
+        q, _ = np.linalg.qr(m.reshape(cl, ds * cr).conj().T)
+        b[k] = q.conj().T.reshape(q.shape[1], ds, cr)
         envs[k] = env_right_step(envs[k + 1], a[k], w[k], b[k])
         log.append(StepRecord("r2l1", k, f, f, q.shape[1]))
     return f
+
+
+# ------------------------------------------------------------ groupings ---
+def _group(ts, sizes, join):
+    sizes = [int(r) for r in sizes]
+    if min(sizes, default=1) < 1 or sum(sizes) != len(ts):
+        raise ValueError("group sizes must be >= 1 and add up to the number of qubits")
+    out, k = [], 0
+    for r in sizes:
+        g = ts[k]
+        for t in ts[k + 1:k + r]:
+            g = join(g, t)
+        out.append(g)
+        k += r
+    return out
+
+
+def group_tensors(tensors: Sequence[np.ndarray], sizes: Sequence[int]) -> List[np.ndarray]:
+    """Sites of r consecutive qubits (Sec. IV.A, r_tau qubits per tensor, physical dimension
+    2^r_tau): A_g[a, (s_1 .. s_r), b] = sum over the inner bonds of A_1[a, s_1, .] ... A_r[., s_r, b],
+    the group's first qubit the most significant digit of its index (so the state's amplitudes keep
+    their order)."""
+    return _group(list(tensors), sizes, lambda g, a: np.einsum("asb,btc->astc", g, a).reshape(
+        g.shape[0], g.shape[1] * a.shape[1], a.shape[2]))
+
+
+def group_mpo(mpo: Sequence[np.ndarray], sizes: Sequence[int]) -> List[np.ndarray]:
+    """The MPO on the same sites: W_g[b, (s_1 .. s_r), (t_1 .. t_r), c] = sum over the inner MPO
+    bonds of W_1 ... W_r, with the digit order of group_tensors on the output (s) and input (t)
+    legs."""
+    return _group(list(mpo), sizes, lambda g, w: np.einsum("bstc,cuvd->bsutvd", g, w).reshape(
+        g.shape[0], g.shape[1] * w.shape[1], g.shape[2] * w.shape[2], w.shape[3]))
+
+
+def group_state(state: OracleMPS, sizes: Sequence[int]) -> OracleMPS:
+    """The same state with r_tau consecutive qubits per tensor; the norm stays at the chain end
+    that held it."""
+    ts = group_tensors(state.tensors, sizes)
+    return OracleMPS(tensors=ts, center=0 if state.center == 0 else len(ts) - 1, log_f=state.log_f,
+                     n_layers=state.n_layers, n_2q=state.n_2q)
 
 
 # ------------------------------------------------------ compression step ---
@@ -453,13 +497,19 @@ def apply_layer(state: OracleMPS, layer, chi: int, n_sweeps: int, update: str = 
     return apply_layers(state, [layer], chi, n_sweeps, update)
 
 
-def apply_layers(state: OracleMPS, layers, chi: int, n_sweeps: int, update: str = "two-site") -> float:
+def apply_layers(state: OracleMPS, layers, chi: int, n_sweeps: int, update: str = "two-site",
+                 sizes: Optional[Sequence[int]] = None) -> float:
     """One compression step over K consecutive layers: fit a bond-chi MPS to
     U_K ... U_1 |psi> with the MPO of step_mpo; return f_delta (one f for the K layers).
 
     chi is one cap for every bond or a sequence of n + 1 caps, entry c for the bond
     between sites c - 1 and c (a grouping of the qubits into tensors leaves the bonds
-    inside a group uncapped)."""
+    inside a group uncapped).
+
+    sizes (Sec. IV.A, r_tau qubits per tensor): the number of consecutive qubits in each
+    site of the state (made by group_state), default one each; the step's MPO is grouped
+    the same way (group_mpo) and everything else is unchanged, with n the number of
+    sites."""
     if np.isscalar(chi):
         if chi < 1:
             raise ValueError("chi >= 1 required")
@@ -472,7 +522,15 @@ def apply_layers(state: OracleMPS, layers, chi: int, n_sweeps: int, update: str 
     layers = list(layers)
     single = update == "single-site"
     n = state.n
-    w = step_mpo(n, layers)
+    if sizes is None:
+        w = step_mpo(n, layers)
+    else:
+        sizes = [int(r) for r in sizes]
+        if len(sizes) != n or min(sizes) < 1:
+            raise ValueError("sizes needs one entry >= 1 per site of the state")
+        if any(a.shape[1] != 2 ** r for a, r in zip(state.tensors, sizes)):
+            raise ValueError("the state's physical dimensions are not 2^sizes")
+        w = group_mpo(step_mpo(sum(sizes), layers), sizes)
     a = state.tensors
     envs: Dict[int, np.ndarray] = {}
     log: List[StepRecord] = []

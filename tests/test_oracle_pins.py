@@ -803,3 +803,65 @@ def test_truncation_sensitivity_bounds_the_state_change(gap):
     print("gap %.0e kappa %.3g worst ratio %.3f" % (gap, kappa, worst_ratio))
     assert worst_ratio <= 2.0          # first-order bound (2 eps = relative size of the Gram change)
     assert worst_ratio >= 0.1          # and not vacuous: the worst perturbation comes close to it
+
+
+# --------------------------------------------- groupings (r_tau qubits per tensor) ---
+# Sec. IV.A: a tensor may hold r_tau consecutive qubits (physical dimension 2^r_tau); the
+# compression step is unchanged on such sites.
+
+def _grouped_run(c, sizes, chi, n_sweeps, update="two-site"):
+    st = dmrg.group_state(dmrg.product_state(c.n), sizes)
+    fs = [dmrg.apply_layers(st, [layer], chi, n_sweeps, update, sizes=sizes) for layer in c.layers]
+    return st, np.array(fs)
+
+
+@pytest.mark.parametrize("update", ["two-site", "single-site"])
+def test_grouped_sites_of_one_qubit_are_the_plain_oracle(update):
+    """r_tau = 1 everywhere: the same arithmetic as the plain oracle, bit for bit."""
+    c = circuits.random_circuit(circuits.grid_from_shape(3, 4), 6, seed=4)
+    st, fs = _grouped_run(c, [1] * c.n, 6, 2, update)
+    ref = dmrg.product_state(c.n)
+    fr = np.array([dmrg.apply_layer(ref, layer, 6, 2, update=update) for layer in c.layers])
+    assert np.array_equal(fs, fr)
+    assert np.array_equal(dmrg.to_statevector(st), dmrg.to_statevector(ref))
+
+
+@pytest.mark.parametrize("sizes", [[3, 3, 3, 3], [2] * 6, [4, 4, 4], [1, 3, 4, 2, 2]])
+def test_grouped_sites_exact_regime_match_the_statevector(sizes):
+    """chi at least the largest Schmidt rank of a cut between groups: the grouped simulation is
+    exact (every f_delta = 1, amplitudes equal to the brute-force state) whatever the grouping."""
+    c = circuits.random_circuit(circuits.grid_from_shape(3, 4), 6, seed=5)
+    st, fs = _grouped_run(c, sizes, 64, 2)
+    assert np.all(np.abs(fs - 1.0) < 1e-12)
+    want = sv.run(c)
+    got = dmrg.to_statevector(st)
+    assert np.linalg.norm(got - want) < 1e-10
+    assert [a.shape[1] for a in st.tensors] == [2 ** r for r in sizes]
+
+
+def test_one_group_holds_the_whole_state():
+    """One tensor of all n qubits: the MPS is the state vector itself, the zip-up applies the layer
+    exactly and no truncation happens, even at chi = 1 (a chain of one site has no inner bond)."""
+    c = circuits.random_circuit(circuits.grid_from_shape(2, 4), 5, seed=6)
+    st, fs = _grouped_run(c, [c.n], 1, 2)
+    assert np.all(np.abs(fs - 1.0) < 1e-12)
+    assert np.linalg.norm(dmrg.to_statevector(st) - sv.run(c)) < 1e-10
+
+
+@pytest.mark.parametrize("update", ["two-site", "single-site"])
+def test_grouped_sites_truncated_invariants(update):
+    """Truncated (chi = 4 between groups of 2): every step keeps f <= the local tensor's weight,
+    0 < f_delta <= 1, the state stays normalised, F~ is the product of the f_delta, the bonds
+    between groups respect chi, and the fidelity with the brute-force state is at most 1."""
+    c = circuits.random_circuit(circuits.grid_from_shape(3, 4), 8, seed=7)
+    sizes = [2] * 6
+    st, fs = _grouped_run(c, sizes, 4, 2, update)
+    assert np.all(fs <= 1.0 + 1e-12) and np.all(fs > 0.0)
+    for rec in st.step_log:
+        assert rec.f <= rec.sum_s2 * (1.0 + 1e-12)
+    v = dmrg.to_statevector(st)
+    assert abs(np.vdot(v, v).real - 1.0) < 1e-10
+    _, log_f, _ = dmrg.fidelity(st)
+    assert abs(log_f - np.sum(np.log(fs))) < 1e-12
+    assert all(a.shape[0] <= 4 and a.shape[2] <= 4 for a in st.tensors)
+    assert abs(np.vdot(sv.run(c), v)) ** 2 <= 1.0 + 1e-12
