@@ -12,14 +12,16 @@ past the circuit's depth 20 (``steps`` in the output line is the number
 actually timed).  All inputs are resident on the GPU when timing starts (the
 gate list of a layer is a few KiB and is copied inside the call).
 
-Prints one JSON line.  ``roofline`` describes the contraction GEMM kernel:
-algorithmic flops (8 per complex multiply-add) over the summed launch
+Prints one JSON line.  ``roofline_contraction`` describes the contraction GEMM
+kernel: algorithmic flops (8 per complex multiply-add) over the summed launch
 durations measured with HIP events on the stream each launch runs on.
 ``roofline_truncation`` does the same for the persistent FP64 tridiagonal
-reduction of the truncation ((16/3) n^3 flops per order-n matrix).  Both
-carry ``traffic``: the HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE
-record of the same kernel source under profiles/, scaled to this run's
-algorithmic bytes per launch (null when the kernel changed since).
+reduction of the truncation ((16/3) n^3 flops per order-n matrix).
+``roofline`` repeats whichever of the two took more time in the timed layers
+(the dominant kernel).  Each carries ``traffic``: the HBM bytes per launch from
+the FETCH_SIZE / WRITE_SIZE record of the same kernel source under profiles/,
+scaled to this run's algorithmic bytes per launch (null when the kernel
+changed since).
 ``fp64_path`` times the all-FP64 path on the first ``--fp64-steps`` of the
 same layers; ``speedup_vs_fp64`` compares the two on exactly those layers.
 ``cpu_baseline`` times the FP64 oracle on a bounded sample (see
@@ -479,6 +481,12 @@ def main():
     layers_timed = list(range(warmup, warmup + steps))
     classes = [layer_class(c.layers[d]) for d in layers_timed]
 
+    gemm_roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                 "frac": achieved / peak,
+                 "traffic": ratio * alg_bytes if ratio is not None else None,
+                 "algorithmic_bytes_per_launch": alg_bytes,
+                 "kernel": "%s (complex planar GEMM, %d launches, %.1f ms)"
+                           % (GEMM_KERNEL[prec_name], con["launches"], con["ms"])}
     out = {
         "metric": "gate-layers/s & TFLOP/s at chi=1024, split-FP32 vs FP64 on 1 GPU, equal fidelity",
         "value": value,
@@ -505,13 +513,9 @@ def main():
         "class_algorithmic_tflops": {k: round(tflops(v), 2) for k, v in stats.items() if v["flops"] > 0},
         "f_delta": run["f"],
         "F_tilde_after_timed_layers": run["fid"]["F_tilde"],
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak,
-                     "traffic": ratio * alg_bytes if ratio is not None else None,
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "kernel": "%s (complex planar GEMM, %d launches, %.1f ms)"
-                               % (GEMM_KERNEL[prec_name], con["launches"], con["ms"])},
+        "roofline": gemm_roof,
         "contraction_frac_of_fp32_mfma_peak": achieved / PEAK["fp32"],
+        "roofline_contraction": dict(gemm_roof),
         "truncation_counters": run["counters"],
     }
     tri = stats["tridiag"]
@@ -525,6 +529,8 @@ def main():
             "algorithmic_bytes_per_launch": tri_bytes,
             "kernel": "hetrd_kernel (persistent FP64 tridiagonal reduction, %d launches, %.1f ms)"
                       % (tri["launches"], tri["ms"])}
+        if tri["ms"] > con["ms"]:
+            out["roofline"] = dict(out["roofline_truncation"])
         trunc_ms = sum(stats[k]["ms"] for k in ("gram", "tridiag", "eigh"))
         out["truncation_seconds"] = trunc_ms / 1e3
         out["truncation_effective_tflops"] = (
