@@ -293,6 +293,25 @@ def sycamore_row_groups(layout: "SycamoreLayout", offset: int = 0):
     return order, sizes
 
 
+def sycamore_diagonal_groups(layout: "SycamoreLayout", direction: str = "up"):
+    """A diagonal grouping of the Sycamore layout (the D groupings of Sec. V.C): one group per
+    diagonal line of qubits, y - c constant for direction "up" (the lines that couplers A and B
+    follow, so the A and B layers stay inside the groups) and y + c constant for "down" (C and
+    D).  Returns (order, sizes) as sycamore_row_groups: the column-major chain sites in the new
+    chain order (group by group, each group by column) and the group sizes in that order."""
+    if direction not in ("up", "down"):
+        raise ValueError("direction must be 'up' or 'down'")
+    groups = {}
+    for c, y in layout.coords():
+        groups.setdefault(y - c if direction == "up" else y + c, []).append((c, y))
+    order, sizes = [], []
+    for key in sorted(groups):
+        members = sorted(groups[key])
+        order += [layout.site(c, y) for c, y in members]
+        sizes.append(len(members))
+    return order, sizes
+
+
 def relabel_circuit(circuit: Circuit, order: Sequence[int]) -> Circuit:
     """The same circuit on a new chain: site order[k] of the old chain becomes site k."""
     pos = {old: new for new, old in enumerate(order)}

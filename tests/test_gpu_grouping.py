@@ -109,3 +109,38 @@ def test_row_grouping_trivial_layers_21_qubits():
             assert abs(abs(np.vdot(st.statevector(), target)) - 1.0) < 1e-10
         assert all(st.bond_dims()[k] <= 4 for k in cuts)
     assert st.fidelity()["F_tilde"] < 0.999
+
+
+@pytest.mark.parametrize("direction,trivial", [("up", "AB"), ("down", "CD")])
+def test_diagonal_grouping_21_qubits(direction, trivial):
+    """D groupings (one group per diagonal line, the chain relabelled so that each line is
+    contiguous) on 21 qubits with the paper's fixed fSim: the layers along the lines are exact
+    at chi = 4 between groups, the bonds between groups stay <= 4; and with Haar couplers on the
+    same grouping, per-layer f and bond dimensions as the oracle's (FP64)."""
+    lay = circuits.SycamoreLayout(4, 6)
+    order, sizes = circuits.sycamore_diagonal_groups(lay, direction)
+    prof = circuits.group_bond_profile(sizes, 4)
+    cuts = np.cumsum(sizes)[:-1]
+    c = circuits.relabel_circuit(circuits.sycamore_circuit(lay, 8, seed=2, sequence="I"), order)
+    st = mps.MPS(c.n, None, max_chi=max(prof), precision=FP64)
+    for d, layer in enumerate(c.layers):
+        before = st.statevector()
+        f = st.apply_layers_dmrg([layer], prof, 1)
+        if circuits.SEQUENCE_I[d % 8] in trivial:
+            assert abs(f - 1.0) < 1e-12, (d, f)
+            target = sv.apply_layer(before, c.n, layer)
+            assert abs(abs(np.vdot(st.statevector(), target)) - 1.0) < 1e-10
+        assert all(st.bond_dims()[k] <= 4 for k in cuts)
+    assert st.fidelity()["F_tilde"] < 0.999
+    st.close()
+    h = circuits.relabel_circuit(circuits.sycamore_circuit(lay, 6, seed=6, sequence="I", two_qubit="haar"), order)
+    g = mps.MPS(h.n, None, max_chi=max(prof), precision=FP64)
+    fs = np.array([g.apply_layers_dmrg([layer], prof, 2) for layer in h.layers])
+    ora = dmrg.product_state(h.n)
+    for layer in h.layers:
+        dmrg.apply_layers(ora, [layer], prof, 2)
+    of = np.array(ora.layer_f)
+    print("diagonal %s f %s" % (direction, np.round(fs, 6)))
+    assert np.max(np.abs(fs - of) / of) < 1e-10
+    assert g.bond_dims() == ora.bond_dims()
+    g.close()

@@ -757,6 +757,35 @@ def test_row_grouping_layers_are_trivial_after_relabelling():
     assert min(st.layer_f) < 0.99
 
 
+@pytest.mark.parametrize("direction,trivial", [("up", "AB"), ("down", "CD")])
+def test_diagonal_groupings_trivial_layers(direction, trivial):
+    """D groupings (one group per diagonal line of the layout): exactly the two coupler classes
+    that run along the lines stay inside the groups (checked on the 54-qubit processor), and on
+    the 10-qubit layout, relabelled so that each line is contiguous, those layers are exact at
+    chi = 2 between groups while the others truncate."""
+    big = circuits.SycamoreLayout(5, 12)
+    order, sizes = circuits.sycamore_diagonal_groups(big, direction)
+    assert sorted(order) == list(range(big.n)) and sum(sizes) == big.n
+    gid = np.empty(big.n, dtype=int)
+    gid[np.array(order)] = np.repeat(np.arange(len(sizes)), sizes)
+    assert _internal_letters(big, gid) == trivial
+    lay = circuits.SycamoreLayout(3, 4)
+    order, sizes = circuits.sycamore_diagonal_groups(lay, direction)
+    c = circuits.relabel_circuit(circuits.sycamore_circuit(lay, 8, seed=3, sequence="I"), order)
+    prof = circuits.group_bond_profile(sizes, 2)
+    cuts = np.cumsum(sizes)[:-1]
+    st = dmrg.product_state(c.n)
+    for d, layer in enumerate(c.layers):
+        before = dmrg.to_statevector(st)
+        f = dmrg.apply_layers(st, [layer], prof, 2)
+        if circuits.SEQUENCE_I[d % 8] in trivial:
+            assert abs(f - 1.0) < 1e-12, (d, f)
+            target = sv.apply_layer(before, c.n, layer)
+            assert abs(abs(np.vdot(dmrg.to_statevector(st), target)) - 1.0) < 1e-12
+        assert all(st.bond_dims()[k] <= 2 for k in cuts)
+    assert min(st.layer_f) < 0.99
+
+
 # ------------------------------------------- conditioning of a truncation --
 @pytest.mark.parametrize("gap", [1e-1, 1e-3, 1e-5])
 def test_truncation_sensitivity_bounds_the_state_change(gap):
